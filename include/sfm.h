@@ -1,0 +1,181 @@
+/*
+ * sfm.h - C ABI of libsfm.so: S-fraction multiscale finite-volume wave propagation
+ * (Druskin, Mamonov, Zaslavsky, arXiv 1406.6923) on one AMD MI355X (gfx950).
+ *
+ * The library implements the paper's Algorithm 1 for the 3-D constant-density
+ * acoustic equation u_tt = c^2 Lap(u) on a box of ncell[0] x ncell[1] x ncell[2]
+ * cells split into equal box subdomains:
+ *
+ *   Stage 1 (sfm_build_roms): per subdomain, the fine-grid operator A^alpha, the
+ *     6m boundary functions F^alpha (m per face), block Lanczos on (A_+, F)
+ *     (polynomial Krylov space, shift sigma = infinity), the S-fraction
+ *     coefficients Gamma_j, Gamma-hat_j (eq. "GammaTrans") and the projections
+ *     of sources and receivers (eq. "Uj").  Reductions are FP64 on the device.
+ *   Stage 2 (sfm_step): explicit leapfrog of the coupled ROMs, eqs. "intrtstep"
+ *     (interior layers) and "bdrytstep" (boundary layer, exchange of m numbers
+ *     per shared face).  Coefficients stream from HBM in FP32, or BF16 with FP32
+ *     accumulation.
+ *
+ * Conventions shared by every entry point
+ *   - Grid nodes are x = h (i, j, l), 0 <= i <= ncell[0] etc.; nodal arrays are
+ *     C-ordered [l][j][i] (x fastest); l = 0 is the surface.
+ *   - Subdomain alpha = (bz * nsub_y + by) * nsub_x + bx.  Its boundary layer
+ *     U_1 has p = 6m entries: face-major (x-, x+, y-, y+, z-, z+), then patch.
+ *     ROM state arrays are [S][k][p] (layer j = 1..k, then entry).
+ *   - Symmetric coefficient blocks are exchanged as full [p][p] row-major FP64.
+ *   - Device pointers are borrowed: the caller keeps them alive and unaliased
+ *     until the stream has passed the call.  Host arrays are read during the
+ *     call and may be freed afterwards.
+ *   - Every call returns an sfm_status.  No exception crosses the ABI.  On an
+ *     error the context keeps its previous state and sfm_last_error(ctx)
+ *     describes the failure.  Calls that take a stream are asynchronous on it
+ *     unless marked "synchronizes".
+ *   - A context is bound to the device current at sfm_create and is not
+ *     thread-safe; distinct contexts are independent.
+ */
+#ifndef SFM_H
+#define SFM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfm_ctx_s* sfm_ctx;
+
+typedef enum {
+  SFM_OK = 0,
+  SFM_EINVAL = -1,      /* invalid argument or configuration */
+  SFM_EHIP = -2,        /* HIP runtime or library failure (no device, launch error) */
+  SFM_ENOMEM = -3,      /* device allocation failed */
+  SFM_EBREAKDOWN = -4,  /* block Lanczos breakdown or non-SPD S-fraction level */
+  SFM_ESTATE = -5,      /* call out of order (e.g. step before ROMs exist) */
+  SFM_EUNSTABLE = -6    /* time step above the stability limit */
+} sfm_status;
+
+typedef enum {
+  SFM_PREC_FP32 = 0,        /* coefficient blocks stored FP32 */
+  SFM_PREC_BF16_FP32ACC = 1 /* coefficient blocks stored BF16, FP32 accumulation */
+} sfm_precision;
+
+typedef struct {
+  int32_t ncell[3];      /* cells along x, y, z (nodes = ncell + 1) */
+  int32_t sub_cells[3];  /* cells per subdomain edge; ncell[d] % sub_cells[d] == 0, sub_cells >= 2 */
+  double h;              /* grid step (metres), > 0 */
+  int32_t m;             /* boundary functions per face: m1 x m2 patches, m1 >= m2, m1 - m2 minimal */
+  int32_t k;             /* S-fraction levels (blocks of the ROM), 2 <= k, 6mk <= subdomain nodes */
+  int32_t precision;     /* sfm_precision */
+  int32_t build_batch;   /* subdomains per ROM-build batch (device memory), 0 = automatic */
+} sfm_config;
+
+typedef struct {
+  int32_t n_subdomains;      /* S */
+  int32_t p;                 /* 6m */
+  int32_t k;
+  int32_t nsrc, nrec;        /* after sfm_build_roms / sfm_load_roms */
+  int32_t has_roms;
+  int64_t steps_done;        /* n of the current state U^n */
+  int64_t coef_bytes;        /* device bytes of the streamed coefficient tiles */
+  int64_t coef_bytes_algorithmic;  /* (2k-1) p (p+1)/2 words per subdomain in the stored precision */
+  int64_t state_bytes;       /* one [S][k][p] FP32 state array */
+  double build_seconds;      /* wall time of the last sfm_build_roms (device work included) */
+} sfm_info;
+
+/* Validate cfg and allocate a context on the current device.
+ * Errors: SFM_EINVAL (bad configuration, checked before any HIP call),
+ *         SFM_EHIP (no usable device).  *out is NULL on failure. */
+sfm_status sfm_create(const sfm_config* cfg, sfm_ctx* out);
+
+/* Release every device buffer owned by ctx (NULL is ignored). */
+void sfm_destroy(sfm_ctx ctx);
+
+/* Per-context message of the last failing call ("" if none); valid until the next call on ctx.
+ * With ctx == NULL, the message of the last failed sfm_create on this thread. */
+const char* sfm_last_error(sfm_ctx ctx);
+
+/* Sizes and counters of ctx.  Never fails for a valid ctx. */
+sfm_status sfm_query(sfm_ctx ctx, sfm_info* out);
+
+/* Algorithm 1, Stage 1 (steps 1.1-1.4), entirely on the device: per subdomain the
+ * fine-grid operator from the nodal sound speed, the patch basis F, block Lanczos
+ * with full two-pass FP64 re-orthogonalisation, the FP64 S-fraction transform,
+ * the projections of point sources (s = G Z^T M^{-1/2} e_s) and receivers
+ * (r = e_r^T M^{-1/2} Z G^{-1}), and (step 1.4) of optional initial conditions
+ * (U(0) = G Z^T M^{1/2} u0, U_t(0) = G Z^T M^{1/2} v0, eq. "Uj").  Sets the state
+ * to U^0 = U(0), U^0 - U^{-1} = 0 (see sfm_reset_state for a nonzero v0).
+ *   vel_dev   device, float [nz+1][ny+1][nx+1] sound speed at the nodes (> 0)
+ *   src_ijk   host, int32 [nsrc][3] source nodes, each strictly inside one subdomain
+ *   rec_ijk   host, int32 [nrec][3] receiver nodes; a node on a subdomain boundary
+ *             is reconstructed from the lowest-index subdomain that holds it
+ *   u0_dev, v0_dev  device, float nodal fields like vel_dev, or NULL for zero
+ *   stream    hipStream_t (NULL = default stream)
+ * Synchronizes (the build reports breakdowns).  Errors: SFM_EINVAL,
+ * SFM_EBREAKDOWN (rank-deficient Lanczos block or non-SPD Gamma_j, j < k),
+ * SFM_ENOMEM, SFM_EHIP. */
+sfm_status sfm_build_roms(sfm_ctx ctx, const float* vel_dev, int32_t nsrc, const int32_t* src_ijk,
+                          int32_t nrec, const int32_t* rec_ijk, const float* u0_dev,
+                          const float* v0_dev, void* stream);
+
+/* Restart from the projected initial conditions with step dt: U^0 = U(0) and
+ * U^{-1} = U(0) - dt U_t(0) (first-order start, as the fine-grid leapfrog), n = 0.
+ * Zero if the ROMs were built without initial conditions or loaded.  Errors: SFM_ESTATE. */
+sfm_status sfm_reset_state(sfm_ctx ctx, double dt, void* stream);
+
+/* Parity hook: install ROMs computed elsewhere instead of building them.
+ *   gamma, gamma_hat  host, double [S][k][p][p]; gamma_hat[.][0] must be diagonal
+ *   src_vec           host, double [nsrc][k][p] (source projections; may be NULL if nsrc == 0)
+ *   rec_rows          host, double [nrec][k][p] (receiver rows; may be NULL if nrec == 0)
+ * Face masses C_f = (sum over sides of Gamma-hat_1^{-1})^{-1} (eq. "bdrytstep") are
+ * derived from the diagonal of gamma_hat[.][0].  Synchronizes; resets the state. */
+sfm_status sfm_load_roms(sfm_ctx ctx, const double* gamma, const double* gamma_hat,
+                         int32_t nsrc, const int32_t* src_ijk, const double* src_vec,
+                         int32_t nrec, const int32_t* rec_ijk, const double* rec_rows);
+
+/* Copy the FP64 S-fraction coefficients to host arrays double [S][k][p][p] (either may
+ * be NULL).  Synchronizes. */
+sfm_status sfm_export_roms(sfm_ctx ctx, double* gamma, double* gamma_hat);
+
+/* Copy the FP64 source projections double [nsrc][k][p] and receiver rows
+ * double [nrec][k][p] to the host (either may be NULL).  Synchronizes. */
+sfm_status sfm_export_projections(sfm_ctx ctx, double* src_vec, double* rec_rows);
+
+/* Stability limit of leapfrog for the coupled ROM: dt_max = 2 / sqrt(rho), rho the
+ * largest eigenvalue of the coupled operator estimated by `iters` (>= 10) power
+ * iterations of the FP32 step operator from a fixed seeded start.  Leaves the state
+ * unchanged.  Synchronizes.  Errors: SFM_ESTATE (no ROMs), SFM_EINVAL. */
+sfm_status sfm_cfl_dt(sfm_ctx ctx, int32_t iters, double* dt_max, void* stream);
+
+/* Advance the coupled ROMs nsteps leapfrog steps of size dt (Algorithm 1, Stage 2):
+ *   U^{n+1} = 2 U^n - U^{n-1} + dt^2 a(U^n, t_n),
+ * a from eqs. "intrtstep" and "bdrytstep" with point forcing f_s(t_n).
+ *   wavelet_dev  device, float [nsteps][nsrc] source samples f_s(t_n) (NULL iff nsrc == 0)
+ *   traces_dev   device, float [nrec][ld]; if not NULL, receiver sample of U^{n+1} for the
+ *                i-th step of this call goes to traces_dev[r * ld + i]  (ld >= nsteps)
+ * If dt exceeds the last sfm_cfl_dt result (when one was computed) the call fails with
+ * SFM_EUNSTABLE before launching anything.  Errors: SFM_ESTATE, SFM_EINVAL. */
+sfm_status sfm_step(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet_dev,
+                    float* traces_dev, int64_t ld, void* stream);
+
+/* Receiver samples of the current state: out_dev[r] = r_r . U^{alpha(r), n} (device,
+ * float [nrec]).  Errors: SFM_ESTATE. */
+sfm_status sfm_record_receivers(sfm_ctx ctx, float* out_dev, void* stream);
+
+/* Apply the coupled step operator without forcing: a_dev = a(u_dev) as in sfm_step
+ * (device, float [S][k][p] each; shared boundary entries of u must agree on both sides).
+ * Errors: SFM_ESTATE. */
+sfm_status sfm_apply_operator(sfm_ctx ctx, const float* u_dev, float* a_dev, void* stream);
+
+/* Checkpoint: copy U^n and the increment U^n - U^{n-1} (host, float [S][k][p] each; either
+ * may be NULL) and n.  The increment is the stored leapfrog variable, so set_state of
+ * what get_state returned resumes bit-identically.  Synchronizes. */
+sfm_status sfm_get_state(sfm_ctx ctx, float* u_now, float* u_incr, int64_t* n);
+
+/* Restore a checkpoint written by sfm_get_state (NULL arrays mean zero).  Synchronizes. */
+sfm_status sfm_set_state(sfm_ctx ctx, const float* u_now, const float* u_incr, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFM_H */

@@ -1,0 +1,657 @@
+// C ABI of libsfm: context management, ROM installation, stepping, state and checks.
+//
+// Algorithm 1 of the paper: Stage 1 (ROM construction) lives in build.hip; Stage 2
+// (the leapfrog of the coupled ROMs) is driven from here with the kernels of
+// step_kernels.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sfm_internal.h"
+
+using sfm::kTile;
+
+namespace {
+thread_local std::string g_create_error;
+
+#define SFM_TRY_HIP(ctx, call)                                                              \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return (ctx)->fail(SFM_EHIP, std::string(#call) + " failed: " + hipGetErrorString(e_)); \
+  } while (0)
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+__global__ void reset_state_kernel(float* U, float* D, const float* U0, const float* V0, float dt, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    U[i] = U0 ? U0[i] : 0.f;
+    D[i] = V0 ? dt * V0[i] : 0.f;
+  }
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- context helpers
+void* sfm_ctx_s::dalloc(size_t bytes, hipError_t* e) {
+  void* p = nullptr;
+  *e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+  if (*e != hipSuccess) return nullptr;
+  owned.push_back(p);
+  return p;
+}
+
+void sfm_ctx_s::dfree(void* p) {
+  if (!p) return;
+  auto it = std::find(owned.begin(), owned.end(), p);
+  if (it != owned.end()) {
+    (void)hipFree(p);
+    owned.erase(it);
+  }
+}
+
+void sfm_ctx_s::dfree_all() {
+  for (void* p : owned) (void)hipFree(p);
+  owned.clear();
+}
+
+namespace sfm {
+
+// Drop every ROM-dependent buffer (before a new build or load).
+static void release_roms(sfm_ctx c) {
+  void* bufs[] = {c->tiles_d, c->coef64_d, c->src_vec_d, c->src_vec64_d, c->src_off_d, c->src_ids_d,
+                  c->sw_off_d, c->sw_q_d, c->sw_src_d, c->sw_w_d, c->rec_sub_d, c->rec_rows_d,
+                  c->rec_rows64_d, c->U0_d, c->V0_d};
+  for (void* b : bufs) c->dfree(b);
+  c->tiles_d = nullptr; c->coef64_d = nullptr; c->src_vec_d = nullptr; c->src_vec64_d = nullptr;
+  c->src_off_d = nullptr; c->src_ids_d = nullptr; c->sw_off_d = nullptr; c->sw_q_d = nullptr;
+  c->sw_src_d = nullptr; c->sw_w_d = nullptr; c->rec_sub_d = nullptr; c->rec_rows_d = nullptr;
+  c->rec_rows64_d = nullptr; c->U0_d = nullptr; c->V0_d = nullptr;
+  c->has_roms = false;
+  c->nsrc = c->nrec = 0;
+  c->src_sub.clear();
+  c->dt_max = -1.0;
+}
+
+template <typename T>
+static T* alloc_copy(sfm_ctx c, const std::vector<T>& v, hipError_t* e) {
+  T* d = static_cast<T*>(c->dalloc(v.size() * sizeof(T), e));
+  if (!d) return nullptr;
+  if (!v.empty()) *e = hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return d;
+}
+
+// Resolve source / receiver nodes to subdomains; host arrays of ijk triples.
+sfm_status locate_points(sfm_ctx c, int32_t nsrc, const int32_t* src_ijk, int32_t nrec, const int32_t* rec_ijk,
+                         std::vector<int32_t>& src_sub, std::vector<int32_t>& src_local,
+                         std::vector<int32_t>& rec_sub, std::vector<int32_t>& rec_local) {
+  const Topology& t = c->topo;
+  if (nsrc < 0 || nrec < 0) return c->fail(SFM_EINVAL, "negative source or receiver count");
+  if ((nsrc > 0 && !src_ijk) || (nrec > 0 && !rec_ijk)) return c->fail(SFM_EINVAL, "missing node array");
+  auto local = [&](int s, const int32_t* g) {
+    int o[3];
+    t.origin(s, o);
+    return ((g[2] - o[2]) * t.nodes_local[1] + (g[1] - o[1])) * t.nodes_local[0] + (g[0] - o[0]);
+  };
+  src_sub.resize(nsrc);
+  src_local.resize(nsrc);
+  for (int i = 0; i < nsrc; ++i) {
+    const int32_t* g = src_ijk + 3 * i;
+    const int s = t.owner(g[0], g[1], g[2], true);
+    if (s < 0)
+      return c->fail(SFM_EINVAL, "source " + std::to_string(i) + " at (" + std::to_string(g[0]) + "," +
+                                     std::to_string(g[1]) + "," + std::to_string(g[2]) +
+                                     ") is not strictly inside a subdomain");
+    src_sub[i] = s;
+    src_local[i] = local(s, g);
+  }
+  rec_sub.resize(nrec);
+  rec_local.resize(nrec);
+  for (int i = 0; i < nrec; ++i) {
+    const int32_t* g = rec_ijk + 3 * i;
+    const int s = t.owner(g[0], g[1], g[2], false);
+    if (s < 0) return c->fail(SFM_EINVAL, "receiver " + std::to_string(i) + " is outside the grid");
+    rec_sub[i] = s;
+    rec_local[i] = local(s, g);
+  }
+  return SFM_OK;
+}
+
+// Install ROMs whose FP64 coefficients already sit in c->coef64_d ([S][2][k][p][p]),
+// given the boundary face masses H = diag(Gamma-hat_1) (host, [S][p]) and FP64 source
+// vectors / receiver rows on the device.  Builds the streamed tiles, the combined face
+// masses C_f = (sum over sides of 1/H)^{-1} (eq. "bdrytstep"), the boundary-layer source
+// weights w_f = C_f sum over sides of H^{-1} s_1, and resets the state.
+sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vector<int32_t>& src_sub,
+                         const std::vector<double>& src_vec_host, const std::vector<int32_t>& rec_sub,
+                         hipStream_t st) {
+  const Topology& t = c->topo;
+  const TileGeometry& g = c->geo;
+  const int S = t.S, k = t.k, p = t.p, P16 = g.P16, m = t.m;
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < H.size(); ++i)
+    if (!(H[i] > 0.0)) return c->fail(SFM_EBREAKDOWN, "non-positive face mass diag(Gamma-hat_1)");
+
+  // streamed tiles
+  std::vector<int32_t> wrow, wcol;
+  const bool bf16 = c->cfg.precision == SFM_PREC_BF16_FP32ACC;
+  g.word_map(wrow, wcol, bf16);
+  int32_t* wrow_d = alloc_copy(c, wrow, &e);
+  if (e != hipSuccess) return c->fail(SFM_ENOMEM, "word map allocation failed");
+  int32_t* wcol_d = alloc_copy(c, wcol, &e);
+  if (e != hipSuccess) return c->fail(SFM_ENOMEM, "word map allocation failed");
+  c->tile_elem = bf16 ? 2 : 4;
+  const size_t tile_bytes = (size_t)S * (2 * k - 1) * g.words_per_block * c->tile_elem;
+  c->tiles_d = c->dalloc(tile_bytes, &e);
+  if (!c->tiles_d) return c->fail(SFM_ENOMEM, "coefficient tiles: out of device memory");
+  SFM_TRY_HIP(c, launch_pack(c->coef64_d, 0, 0, k, p, g, wrow_d, wcol_d, c->tiles_d, c->cfg.precision, S, st));
+
+  // combined face masses
+  std::vector<float> C((size_t)S * P16, 0.f);
+  for (int s = 0; s < S; ++s)
+    for (int q = 0; q < p; ++q) {
+      const int f = q / m, pat = q % m;
+      const int nb = t.nbr[(size_t)s * 6 + f];
+      double inv = 1.0 / H[(size_t)s * p + q];
+      if (nb >= 0) inv += 1.0 / H[(size_t)nb * p + (f ^ 1) * m + pat];
+      C[(size_t)s * P16 + q] = (float)(1.0 / inv);
+    }
+  SFM_TRY_HIP(c, hipMemcpyAsync(c->C_d, C.data(), C.size() * sizeof(float), hipMemcpyHostToDevice, st));
+
+  // sources: interior CSR and boundary-layer weights
+  const int nsrc = (int)src_sub.size();
+  c->nsrc = nsrc;
+  c->src_sub = src_sub;
+  if (nsrc > 0) {
+    std::vector<int32_t> off(S + 1, 0), ids(nsrc);
+    for (int i = 0; i < nsrc; ++i) off[src_sub[i] + 1]++;
+    for (int s = 0; s < S; ++s) off[s + 1] += off[s];
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int i = 0; i < nsrc; ++i) ids[fill[src_sub[i]]++] = i;
+    c->src_off_d = alloc_copy(c, off, &e);
+    c->src_ids_d = alloc_copy(c, ids, &e);
+    struct W { int s, q, src; float w; };
+    std::vector<W> ws;
+    for (int i = 0; i < nsrc; ++i) {
+      const int a = src_sub[i];
+      for (int q = 0; q < p; ++q) {
+        const double s1 = src_vec_host[(size_t)i * k * p + q];
+        if (s1 == 0.0) continue;
+        const float w = (float)((double)C[(size_t)a * P16 + q] * s1 / H[(size_t)a * p + q]);
+        ws.push_back({a, q, i, w});
+        const int f = q / m, pat = q % m;
+        const int nb = t.nbr[(size_t)a * 6 + f];
+        if (nb >= 0) ws.push_back({nb, (f ^ 1) * m + pat, i, w});
+      }
+    }
+    std::stable_sort(ws.begin(), ws.end(), [](const W& x, const W& y) { return x.s < y.s; });
+    std::vector<int32_t> swoff(S + 1, 0), swq(ws.size()), swsrc(ws.size());
+    std::vector<float> sww(ws.size());
+    for (size_t i = 0; i < ws.size(); ++i) {
+      swoff[ws[i].s + 1]++;
+      swq[i] = ws[i].q;
+      swsrc[i] = ws[i].src;
+      sww[i] = ws[i].w;
+    }
+    for (int s = 0; s < S; ++s) swoff[s + 1] += swoff[s];
+    c->sw_off_d = alloc_copy(c, swoff, &e);
+    c->sw_q_d = alloc_copy(c, swq, &e);
+    c->sw_src_d = alloc_copy(c, swsrc, &e);
+    c->sw_w_d = alloc_copy(c, sww, &e);
+    c->src_vec_d = static_cast<float*>(c->dalloc((size_t)nsrc * k * P16 * sizeof(float), &e));
+    if (e != hipSuccess) return c->fail(SFM_ENOMEM, "source buffers: out of device memory");
+    SFM_TRY_HIP(c, launch_pad_rows(c->src_vec64_d, (int64_t)nsrc * k, p, P16, c->src_vec_d, st));
+  }
+  // receivers
+  const int nrec = (int)rec_sub.size();
+  c->nrec = nrec;
+  if (nrec > 0) {
+    c->rec_sub_d = alloc_copy(c, rec_sub, &e);
+    c->rec_rows_d = static_cast<float*>(c->dalloc((size_t)nrec * k * P16 * sizeof(float), &e));
+    if (e != hipSuccess) return c->fail(SFM_ENOMEM, "receiver buffers: out of device memory");
+    SFM_TRY_HIP(c, launch_pad_rows(c->rec_rows64_d, (int64_t)nrec * k, p, P16, c->rec_rows_d, st));
+  }
+  const int64_t nstate = (int64_t)S * k * P16;
+  SFM_TRY_HIP(c, hipMemsetAsync(c->exch_d, 0, (size_t)S * P16 * sizeof(float), st));
+  hipLaunchKernelGGL(reset_state_kernel, dim3(1024), dim3(256), 0, st, c->U_d, c->D_d, c->U0_d, nullptr, 0.f, nstate);
+  SFM_TRY_HIP(c, hipGetLastError());
+  SFM_TRY_HIP(c, hipStreamSynchronize(st));
+  c->dfree(wrow_d);
+  c->dfree(wcol_d);
+  c->n = 0;
+  c->has_roms = true;
+  return SFM_OK;
+}
+
+}  // namespace sfm
+
+using namespace sfm;
+
+// ----------------------------------------------------------------------------- ABI
+extern "C" {
+
+sfm_status sfm_create(const sfm_config* cfg, sfm_ctx* out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return SFM_EINVAL;
+  }
+  *out = nullptr;
+  if (!cfg) {
+    g_create_error = "cfg is NULL";
+    return SFM_EINVAL;
+  }
+  Topology topo;
+  const std::string msg = topo.init(*cfg);
+  if (!msg.empty()) {
+    g_create_error = msg;
+    return SFM_EINVAL;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+    g_create_error = "no HIP device available";
+    return SFM_EHIP;
+  }
+  sfm_ctx c = new (std::nothrow) sfm_ctx_s();
+  if (!c) {
+    g_create_error = "host allocation failed";
+    return SFM_ENOMEM;
+  }
+  c->cfg = *cfg;
+  c->topo = topo;
+  c->geo.init(topo.p);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    g_create_error = "hipGetDevice failed";
+    return SFM_EHIP;
+  }
+  hipError_t e = hipSuccess;
+  const int64_t nstate = (int64_t)topo.S * topo.k * c->geo.P16;
+  c->nbr_d = alloc_copy(c, topo.nbr, &e);
+  if (e == hipSuccess) c->C_d = static_cast<float*>(c->dalloc((size_t)topo.S * c->geo.P16 * sizeof(float), &e));
+  if (e == hipSuccess) c->U_d = static_cast<float*>(c->dalloc(nstate * sizeof(float), &e));
+  if (e == hipSuccess) c->D_d = static_cast<float*>(c->dalloc(nstate * sizeof(float), &e));
+  if (e == hipSuccess) c->exch_d = static_cast<float*>(c->dalloc((size_t)topo.S * c->geo.P16 * sizeof(float), &e));
+  if (e == hipSuccess) c->red_d = static_cast<double*>(c->dalloc(64 * sizeof(double), &e));
+  if (e == hipSuccess) c->work_a_d = static_cast<float*>(c->dalloc(nstate * sizeof(float), &e));
+  if (e == hipSuccess) c->work_b_d = static_cast<float*>(c->dalloc(nstate * sizeof(float), &e));
+  if (e == hipSuccess) e = hipMemset(c->U_d, 0, nstate * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(c->D_d, 0, nstate * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(c->C_d, 0, (size_t)topo.S * c->geo.P16 * sizeof(float));
+  if (e != hipSuccess) {
+    g_create_error = std::string("device allocation failed: ") + hipGetErrorString(e);
+    c->dfree_all();
+    delete c;
+    return SFM_ENOMEM;
+  }
+  *out = c;
+  return SFM_OK;
+}
+
+void sfm_destroy(sfm_ctx c) {
+  if (!c) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  c->dfree_all();
+  (void)hipSetDevice(cur);
+  delete c;
+}
+
+const char* sfm_last_error(sfm_ctx c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+sfm_status sfm_query(sfm_ctx c, sfm_info* out) {
+  if (!c || !out) return SFM_EINVAL;
+  const Topology& t = c->topo;
+  out->n_subdomains = t.S;
+  out->p = t.p;
+  out->k = t.k;
+  out->nsrc = c->nsrc;
+  out->nrec = c->nrec;
+  out->has_roms = c->has_roms ? 1 : 0;
+  out->steps_done = c->n;
+  const int64_t elem = c->cfg.precision == SFM_PREC_FP32 ? 4 : 2;
+  out->coef_bytes = (int64_t)t.S * (2 * t.k - 1) * c->geo.words_per_block * elem;
+  out->coef_bytes_algorithmic = (int64_t)t.S * (2 * t.k - 1) * ((int64_t)t.p * (t.p + 1) / 2) * elem;
+  out->state_bytes = (int64_t)t.S * t.k * t.p * 4;
+  out->build_seconds = c->build_seconds;
+  return SFM_OK;
+}
+
+sfm_status sfm_load_roms(sfm_ctx c, const double* gamma, const double* gamma_hat, int32_t nsrc,
+                         const int32_t* src_ijk, const double* src_vec, int32_t nrec, const int32_t* rec_ijk,
+                         const double* rec_rows) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!gamma || !gamma_hat) return c->fail(SFM_EINVAL, "gamma and gamma_hat are required");
+  if ((nsrc > 0 && !src_vec) || (nrec > 0 && !rec_rows)) return c->fail(SFM_EINVAL, "missing projections");
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  const Topology& t = c->topo;
+  const int S = t.S, k = t.k, p = t.p;
+  std::vector<int32_t> src_sub, src_local, rec_sub, rec_local;
+  sfm_status rc = locate_points(c, nsrc, src_ijk, nrec, rec_ijk, src_sub, src_local, rec_sub, rec_local);
+  if (rc != SFM_OK) return rc;
+  // Gamma-hat_1 must be diagonal (non-overlapping boundary functions).
+  std::vector<double> H((size_t)S * p);
+  const size_t blk = (size_t)p * p;
+  for (int s = 0; s < S; ++s) {
+    const double* g1 = gamma_hat + (size_t)s * k * blk;
+    double dmax = 0.0, omax = 0.0;
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) {
+        const double v = std::fabs(g1[(size_t)i * p + j]);
+        if (i == j) dmax = std::max(dmax, v); else omax = std::max(omax, v);
+      }
+    if (omax > 1e-10 * dmax)
+      return c->fail(SFM_EINVAL, "gamma_hat[" + std::to_string(s) + "][0] is not diagonal");
+    for (int i = 0; i < p; ++i) H[(size_t)s * p + i] = g1[(size_t)i * p + i];
+  }
+  release_roms(c);
+  hipError_t e = hipSuccess;
+  c->coef64_d = static_cast<double*>(c->dalloc((size_t)S * 2 * k * blk * sizeof(double), &e));
+  if (!c->coef64_d) return c->fail(SFM_ENOMEM, "FP64 coefficients: out of device memory");
+  for (int s = 0; s < S; ++s) {
+    SFM_TRY_HIP(c, hipMemcpy(c->coef64_d + (size_t)s * 2 * k * blk, gamma + (size_t)s * k * blk,
+                             k * blk * sizeof(double), hipMemcpyHostToDevice));
+    SFM_TRY_HIP(c, hipMemcpy(c->coef64_d + ((size_t)s * 2 + 1) * k * blk, gamma_hat + (size_t)s * k * blk,
+                             k * blk * sizeof(double), hipMemcpyHostToDevice));
+  }
+  std::vector<double> sv;
+  if (nsrc > 0) {
+    sv.assign(src_vec, src_vec + (size_t)nsrc * k * p);
+    c->src_vec64_d = alloc_copy(c, sv, &e);
+  }
+  if (nrec > 0) {
+    std::vector<double> rr(rec_rows, rec_rows + (size_t)nrec * k * p);
+    c->rec_rows64_d = alloc_copy(c, rr, &e);
+  }
+  if (e != hipSuccess) return c->fail(SFM_ENOMEM, "projection buffers: out of device memory");
+  c->build_seconds = 0.0;
+  return finalize_roms(c, H, src_sub, sv, rec_sub, nullptr);
+}
+
+sfm_status sfm_export_roms(sfm_ctx c, double* gamma, double* gamma_hat) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs: call sfm_build_roms or sfm_load_roms first");
+  const Topology& t = c->topo;
+  const size_t chunk = (size_t)t.k * t.p * t.p * sizeof(double);
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  SFM_TRY_HIP(c, hipDeviceSynchronize());
+  if (gamma)
+    SFM_TRY_HIP(c, hipMemcpy2D(gamma, chunk, c->coef64_d, 2 * chunk, chunk, t.S, hipMemcpyDeviceToHost));
+  if (gamma_hat)
+    SFM_TRY_HIP(c, hipMemcpy2D(gamma_hat, chunk, reinterpret_cast<const char*>(c->coef64_d) + chunk, 2 * chunk,
+                               chunk, t.S, hipMemcpyDeviceToHost));
+  return SFM_OK;
+}
+
+sfm_status sfm_export_projections(sfm_ctx c, double* src_vec, double* rec_rows) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs");
+  const Topology& t = c->topo;
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  SFM_TRY_HIP(c, hipDeviceSynchronize());
+  if (src_vec && c->nsrc > 0)
+    SFM_TRY_HIP(c, hipMemcpy(src_vec, c->src_vec64_d, (size_t)c->nsrc * t.k * t.p * sizeof(double),
+                             hipMemcpyDeviceToHost));
+  if (rec_rows && c->nrec > 0)
+    SFM_TRY_HIP(c, hipMemcpy(rec_rows, c->rec_rows64_d, (size_t)c->nrec * t.k * t.p * sizeof(double),
+                             hipMemcpyDeviceToHost));
+  return SFM_OK;
+}
+
+}  // extern "C"
+
+namespace sfm {
+
+static StepParams make_step_params(sfm_ctx c) {
+  StepParams prm{};
+  const TileGeometry& g = c->geo;
+  prm.tiles = c->tiles_d;
+  prm.words_per_block = g.words_per_block;
+  prm.words_per_sub = (int64_t)(2 * c->topo.k - 1) * g.words_per_block;
+  std::memcpy(prm.job_off, g.job_off, sizeof(prm.job_off));
+  prm.S = c->topo.S;
+  prm.k = c->topo.k;
+  prm.P16 = g.P16;
+  prm.nt = g.nt;
+  prm.npairs = g.npairs;
+  prm.nslots = g.nslots;
+  prm.U = c->U_d;
+  prm.D = c->D_d;
+  prm.exch = c->exch_d;
+  return prm;
+}
+
+static FaceParams make_face_params(sfm_ctx c) {
+  FaceParams f{};
+  f.S = c->topo.S;
+  f.k = c->topo.k;
+  f.P16 = c->geo.P16;
+  f.p = c->topo.p;
+  f.m = c->topo.m;
+  f.nbr = c->nbr_d;
+  f.C = c->C_d;
+  f.exch = c->exch_d;
+  f.U = c->U_d;
+  f.D = c->D_d;
+  return f;
+}
+
+// a = a(u) of the coupled scheme without forcing (both kernels in operator mode).
+static hipError_t apply_operator(sfm_ctx c, const float* u, float* a, hipStream_t st) {
+  StepParams prm = make_step_params(c);
+  prm.mode = 1;
+  prm.Uin = u;
+  prm.Aout = a;
+  hipError_t e = launch_step_main(prm, c->cfg.precision, st);
+  if (e != hipSuccess) return e;
+  FaceParams f = make_face_params(c);
+  f.mode = 1;
+  f.Aout = a;
+  return launch_step_face(f, st);
+}
+
+}  // namespace sfm
+
+extern "C" {
+
+sfm_status sfm_step(sfm_ctx c, int32_t nsteps, double dt, const float* wavelet_dev, float* traces_dev, int64_t ld,
+                    void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs: call sfm_build_roms or sfm_load_roms first");
+  if (nsteps < 0) return c->fail(SFM_EINVAL, "nsteps must be >= 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return c->fail(SFM_EINVAL, "dt must be positive and finite");
+  if (c->nsrc > 0 && nsteps > 0 && !wavelet_dev) return c->fail(SFM_EINVAL, "wavelet_dev is required with sources");
+  if (traces_dev && ld < nsteps) return c->fail(SFM_EINVAL, "ld must be >= nsteps");
+  if (c->dt_max > 0.0 && dt > c->dt_max)
+    return c->fail(SFM_EUNSTABLE, "dt = " + std::to_string(dt) + " exceeds the stability limit " +
+                                      std::to_string(c->dt_max));
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = as_stream(stream);
+  StepParams prm = make_step_params(c);
+  FaceParams f = make_face_params(c);
+  prm.mode = 0;
+  f.mode = 0;
+  prm.dt2 = (float)(dt * dt);
+  f.dt2 = prm.dt2;
+  prm.nsrc = f.nsrc = c->nsrc;
+  prm.wavelet = f.wavelet = wavelet_dev;
+  if (c->nsrc > 0) {
+    prm.src_off = c->src_off_d;
+    prm.src_ids = c->src_ids_d;
+    prm.src_vec = c->src_vec_d;
+    f.sw_off = c->sw_off_d;
+    f.sw_q = c->sw_q_d;
+    f.sw_src = c->sw_src_d;
+    f.sw_w = c->sw_w_d;
+  }
+  RecParams r{};
+  r.nrec = c->nrec;
+  r.k = c->topo.k;
+  r.P16 = c->geo.P16;
+  r.rec_sub = c->rec_sub_d;
+  r.rows = c->rec_rows_d;
+  r.U = c->U_d;
+  r.out = traces_dev;
+  r.ld = ld;
+  for (int32_t i = 0; i < nsteps; ++i) {
+    prm.step = f.step = i;
+    SFM_TRY_HIP(c, launch_step_main(prm, c->cfg.precision, st));
+    SFM_TRY_HIP(c, launch_step_face(f, st));
+    if (traces_dev && c->nrec > 0) {
+      r.col = i;
+      SFM_TRY_HIP(c, launch_record(r, st));
+    }
+  }
+  c->n += nsteps;
+  return SFM_OK;
+}
+
+sfm_status sfm_record_receivers(sfm_ctx c, float* out_dev, void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs");
+  if (c->nrec > 0 && !out_dev) return c->fail(SFM_EINVAL, "out_dev is NULL");
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  RecParams r{};
+  r.nrec = c->nrec;
+  r.k = c->topo.k;
+  r.P16 = c->geo.P16;
+  r.rec_sub = c->rec_sub_d;
+  r.rows = c->rec_rows_d;
+  r.U = c->U_d;
+  r.out = out_dev;
+  r.ld = 1;
+  r.col = 0;
+  SFM_TRY_HIP(c, launch_record(r, as_stream(stream)));
+  return SFM_OK;
+}
+
+sfm_status sfm_apply_operator(sfm_ctx c, const float* u_dev, float* a_dev, void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs");
+  if (!u_dev || !a_dev) return c->fail(SFM_EINVAL, "u_dev and a_dev are required");
+  if (u_dev == a_dev) return c->fail(SFM_EINVAL, "u_dev and a_dev must not alias");
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = as_stream(stream);
+  // The caller's arrays are [S][k][p]; the kernels work on [S][k][P16] (zero padding).
+  const Topology& t = c->topo;
+  const int P16 = c->geo.P16;
+  if (P16 == t.p) {
+    SFM_TRY_HIP(c, apply_operator(c, u_dev, a_dev, st));
+    return SFM_OK;
+  }
+  SFM_TRY_HIP(c, hipMemsetAsync(c->work_a_d, 0, (size_t)t.S * t.k * P16 * sizeof(float), st));
+  SFM_TRY_HIP(c, hipMemcpy2DAsync(c->work_a_d, P16 * sizeof(float), u_dev, t.p * sizeof(float),
+                                  t.p * sizeof(float), (size_t)t.S * t.k, hipMemcpyDeviceToDevice, st));
+  SFM_TRY_HIP(c, apply_operator(c, c->work_a_d, c->work_b_d, st));
+  SFM_TRY_HIP(c, hipMemcpy2DAsync(a_dev, t.p * sizeof(float), c->work_b_d, P16 * sizeof(float),
+                                  t.p * sizeof(float), (size_t)t.S * t.k, hipMemcpyDeviceToDevice, st));
+  return SFM_OK;
+}
+
+sfm_status sfm_cfl_dt(sfm_ctx c, int32_t iters, double* dt_max, void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs");
+  if (iters < 10 || !dt_max) return c->fail(SFM_EINVAL, "iters must be >= 10 and dt_max non-NULL");
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  hipStream_t st = as_stream(stream);
+  const Topology& t = c->topo;
+  const int P16 = c->geo.P16;
+  const int64_t n = (int64_t)t.S * t.k * P16;
+  // Seeded start vector; shared boundary entries take the value of the lower-index side.
+  std::vector<float> v((size_t)n, 0.f);
+  uint64_t z = 0x9E3779B97F4A7C15ull;
+  for (int s = 0; s < t.S; ++s)
+    for (int j = 0; j < t.k; ++j)
+      for (int q = 0; q < t.p; ++q) {
+        z ^= z << 13; z ^= z >> 7; z ^= z << 17;
+        v[((size_t)s * t.k + j) * P16 + q] = (float)((double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5);
+      }
+  for (int s = 0; s < t.S; ++s)
+    for (int q = 0; q < t.p; ++q) {
+      const int f = q / t.m, pat = q % t.m;
+      const int nb = t.nbr[(size_t)s * 6 + f];
+      if (nb >= 0 && nb < s) v[(size_t)s * t.k * P16 + q] = v[(size_t)nb * t.k * P16 + (f ^ 1) * t.m + pat];
+    }
+  SFM_TRY_HIP(c, hipMemcpyAsync(c->work_a_d, v.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+  SFM_TRY_HIP(c, launch_norm2(c->work_a_d, n, c->red_d, st));
+  SFM_TRY_HIP(c, launch_scale(c->work_a_d, n, c->red_d, c->work_a_d, st));
+  for (int it = 0; it < iters; ++it) {
+    SFM_TRY_HIP(c, apply_operator(c, c->work_a_d, c->work_b_d, st));
+    SFM_TRY_HIP(c, launch_norm2(c->work_b_d, n, c->red_d, st));
+    if (it + 1 < iters) SFM_TRY_HIP(c, launch_scale(c->work_b_d, n, c->red_d, c->work_a_d, st));
+  }
+  double nrm2 = 0.0;
+  SFM_TRY_HIP(c, hipMemcpyAsync(&nrm2, c->red_d, sizeof(double), hipMemcpyDeviceToHost, st));
+  SFM_TRY_HIP(c, hipStreamSynchronize(st));
+  // a = -M^{-1} K v with |v| = 1, so |a| -> rho.
+  const double rho = std::sqrt(nrm2);
+  if (!(rho > 0.0) || !std::isfinite(rho)) return c->fail(SFM_EBREAKDOWN, "spectral radius estimate failed");
+  c->dt_max = 2.0 / std::sqrt(rho);
+  *dt_max = c->dt_max;
+  return SFM_OK;
+}
+
+sfm_status sfm_get_state(sfm_ctx c, float* u_now, float* u_incr, int64_t* n) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  const Topology& t = c->topo;
+  const int P16 = c->geo.P16;
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  SFM_TRY_HIP(c, hipDeviceSynchronize());
+  if (u_now)
+    SFM_TRY_HIP(c, hipMemcpy2D(u_now, t.p * sizeof(float), c->U_d, P16 * sizeof(float), t.p * sizeof(float),
+                               (size_t)t.S * t.k, hipMemcpyDeviceToHost));
+  if (u_incr)
+    SFM_TRY_HIP(c, hipMemcpy2D(u_incr, t.p * sizeof(float), c->D_d, P16 * sizeof(float), t.p * sizeof(float),
+                               (size_t)t.S * t.k, hipMemcpyDeviceToHost));
+  if (n) *n = c->n;
+  return SFM_OK;
+}
+
+sfm_status sfm_set_state(sfm_ctx c, const float* u_now, const float* u_incr, int64_t n) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (n < 0) return c->fail(SFM_EINVAL, "n must be >= 0");
+  const Topology& t = c->topo;
+  const int P16 = c->geo.P16;
+  const size_t bytes = (size_t)t.S * t.k * P16 * sizeof(float);
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  SFM_TRY_HIP(c, hipDeviceSynchronize());
+  SFM_TRY_HIP(c, hipMemset(c->U_d, 0, bytes));
+  SFM_TRY_HIP(c, hipMemset(c->D_d, 0, bytes));
+  if (u_now)
+    SFM_TRY_HIP(c, hipMemcpy2D(c->U_d, P16 * sizeof(float), u_now, t.p * sizeof(float), t.p * sizeof(float),
+                               (size_t)t.S * t.k, hipMemcpyHostToDevice));
+  if (u_incr)
+    SFM_TRY_HIP(c, hipMemcpy2D(c->D_d, P16 * sizeof(float), u_incr, t.p * sizeof(float), t.p * sizeof(float),
+                               (size_t)t.S * t.k, hipMemcpyHostToDevice));
+  c->n = n;
+  return SFM_OK;
+}
+
+sfm_status sfm_reset_state(sfm_ctx c, double dt, void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs");
+  if (!(dt >= 0.0)) return c->fail(SFM_EINVAL, "dt must be >= 0");
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  const int64_t n = (int64_t)c->topo.S * c->topo.k * c->geo.P16;
+  hipLaunchKernelGGL(reset_state_kernel, dim3(1024), dim3(256), 0, as_stream(stream), c->U_d, c->D_d, c->U0_d,
+                     c->V0_d, (float)dt, n);
+  SFM_TRY_HIP(c, hipGetLastError());
+  c->n = 0;
+  return SFM_OK;
+}
+
+}  // extern "C"

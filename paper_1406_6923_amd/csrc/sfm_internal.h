@@ -1,0 +1,181 @@
+// Internal declarations of libsfm: context, device layouts and kernel launchers.
+//
+// Layout of the streamed coefficient blocks ("tiles")
+// ---------------------------------------------------
+// Every symmetric p x p block (Gamma_j or Gamma-hat_j) is zero-padded to
+// P16 = 16 * nt rows and cut into 16 x 16 tiles.  Only tiles on or above the
+// diagonal are stored, each in "wrapped diagonal" order: for a tile at block
+// rows 16I.. and columns 16J.., lane i (0..15) holds W_t[i] = A(16I + i, 16J + (i + t) mod 16).
+//   * off-diagonal tile (I < J): t = 0..15, 256 words, stored [v][lane][4] with t = 4v + e
+//     (FP32) or [v][lane][8] (BF16), so each load instruction of a 16-lane row is contiguous;
+//   * diagonal tile (I = J): t = 0..8 (t = 8 repeats the half-diagonal once), 144 words,
+//     stored [t 0..3][lane][4], [t 4..7][lane][4], [t = 8][lane] (FP32) or
+//     [t 0..7][lane][8], [t = 8][lane] (BF16).
+// The symmetric product y = A x then needs each stored word once: W_t[i] multiplies
+// x_J[i + t] into y_I[i], and, rotated by t lanes, x_I[c - t] into y_J[c] (DPP row
+// rotations inside a 16-lane row).
+// Tiles are grouped into "jobs" of one or two tile strips: job g covers strip g and
+// strip nt - 1 - g (diagonal tile first, then the tiles to its right), so every job of
+// an even-nt block holds nt + 1 tiles.  A block is the concatenation of its jobs and a
+// subdomain stream is [Gamma_1 .. Gamma_k, Gamma-hat_2 .. Gamma-hat_k].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "sfm.h"
+
+namespace sfm {
+
+constexpr int kTile = 16;
+constexpr int kDiagWords = 144;
+constexpr int kOffWords = 256;
+constexpr int kStepThreads = 256;      // 16 rows of 16 lanes per subdomain work-group
+constexpr int kMaxNt = 16;             // p <= 256
+
+// Geometry of the tile stream of one block.
+struct TileGeometry {
+  int p = 0, P16 = 0, nt = 0, npairs = 0, nslots = 0;
+  int64_t words_per_block = 0;
+  int32_t job_off[kMaxNt / 2 + 1] = {};   // word offset of job g inside a block
+
+  void init(int p_);
+  // (row, col) of every stored word of a block, in stream order (row, col may be >= p: padding).
+  void word_map(std::vector<int32_t>& rows, std::vector<int32_t>& cols, bool bf16) const;
+};
+
+// Decomposition of the global box into equal subdomains and their faces.
+struct Topology {
+  int ncell[3] = {}, sub[3] = {}, nsub[3] = {};
+  int S = 0, m = 0, m1 = 0, m2 = 0, p = 0, k = 0;
+  int nodes_local[3] = {};               // sub + 1
+  int64_t N_local = 0;                   // nodes per subdomain
+  std::vector<int32_t> nbr;              // [S][6], -1 = outer face
+
+  std::string init(const sfm_config& cfg);   // returns "" or an error message
+  int index(int bx, int by, int bz) const { return (bz * nsub[1] + by) * nsub[0] + bx; }
+  // Subdomain holding global node (i, j, l): strictly inside if strict, else lowest index.
+  int owner(int i, int j, int l, bool strict) const;
+  void origin(int s, int o[3]) const;
+};
+
+struct StepParams {
+  const void* tiles;          // [S][2k-1][words_per_block]
+  int64_t words_per_sub;
+  int64_t words_per_block;
+  int32_t job_off[kMaxNt / 2 + 1];
+  int S, k, P16, nt, npairs, nslots;
+  float* U;                   // [S][k][P16] state U^n (updated in place for layers 2..k)
+  float* D;                   // [S][k][P16] increment U^n - U^{n-1} (step mode)
+  const float* Uin;           // operator mode input (may alias nothing else)
+  float* Aout;                // operator mode output
+  float* exch;                // [S][P16] boundary-layer fluxes phi_1 (step 2.1 exchange)
+  const int32_t* src_off;     // [S+1] CSR of sources interior to each subdomain
+  const int32_t* src_ids;
+  const float* src_vec;       // [nsrc][k][P16]
+  const float* wavelet;       // [nsteps][nsrc] (row `step`)
+  int nsrc;
+  int64_t step;
+  float dt2;
+  int mode;                   // 0 = leapfrog step, 1 = apply operator
+};
+
+struct FaceParams {
+  int S, k, P16, p, m;
+  const int32_t* nbr;         // [S][6]
+  const float* C;             // [S][P16] combined face mass
+  const float* exch;
+  const int32_t* sw_off;      // [S+1] CSR of layer-1 source weights
+  const int32_t* sw_q;
+  const int32_t* sw_src;
+  const float* sw_w;
+  const float* wavelet;
+  int nsrc;
+  int64_t step;
+  float dt2;
+  float* U;
+  float* D;
+  float* Aout;
+  int mode;
+};
+
+struct RecParams {
+  int nrec, k, P16;
+  const int32_t* rec_sub;
+  const float* rows;          // [nrec][k][P16]
+  const float* U;             // [S][k][P16]
+  float* out;                 // out[r * ld + col]
+  int64_t ld, col;
+};
+
+hipError_t launch_step_main(const StepParams& prm, int precision, hipStream_t st);
+hipError_t launch_step_face(const FaceParams& prm, hipStream_t st);
+hipError_t launch_record(const RecParams& prm, hipStream_t st);
+hipError_t launch_pack(const double* blocks, int64_t nblocks_total, int blocks_per_sub_in,
+                       int k, int p, const TileGeometry& geo, const int32_t* wrow,
+                       const int32_t* wcol, void* tiles, int precision, int S, hipStream_t st);
+hipError_t launch_pad_rows(const double* src, int64_t nrows, int p, int P16, float* dst,
+                           hipStream_t st);
+size_t step_lds_bytes(const StepParams& prm);
+hipError_t launch_norm2(const float* x, int64_t n, double* out, hipStream_t st);
+hipError_t launch_scale(const float* x, int64_t n, const double* num, float* y, hipStream_t st);
+
+}  // namespace sfm
+
+// ----------------------------------------------------------------------------- context
+struct sfm_ctx_s {
+  sfm_config cfg{};
+  sfm::Topology topo;
+  sfm::TileGeometry geo;
+  int device = 0;
+  std::string err;
+
+  // device buffers (owned)
+  std::vector<void*> owned;
+  int32_t* nbr_d = nullptr;
+  void* tiles_d = nullptr;
+  double* coef64_d = nullptr;       // [S][2][k][p][p]: Gamma_j at [.][0], Gamma-hat_j at [.][1]
+  size_t tile_elem = 4;             // bytes per streamed coefficient word
+  float* C_d = nullptr;             // [S][P16]
+  float* U_d = nullptr;             // [S][k][P16]
+  float* D_d = nullptr;
+  float* exch_d = nullptr;          // [S][P16]
+  float* U0_d = nullptr;            // projected initial conditions (or null)
+  float* V0_d = nullptr;
+  // sources
+  int nsrc = 0;
+  std::vector<int32_t> src_sub;
+  float* src_vec_d = nullptr;       // [nsrc][k][P16]
+  double* src_vec64_d = nullptr;    // [nsrc][k][p]
+  int32_t* src_off_d = nullptr;
+  int32_t* src_ids_d = nullptr;
+  int32_t* sw_off_d = nullptr;
+  int32_t* sw_q_d = nullptr;
+  int32_t* sw_src_d = nullptr;
+  float* sw_w_d = nullptr;
+  // receivers
+  int nrec = 0;
+  int32_t* rec_sub_d = nullptr;
+  float* rec_rows_d = nullptr;      // [nrec][k][P16]
+  double* rec_rows64_d = nullptr;   // [nrec][k][p]
+  // scratch
+  double* red_d = nullptr;          // reduction scratch
+  float* work_a_d = nullptr;        // [S][k][P16] operator scratch
+  float* work_b_d = nullptr;
+
+  bool has_roms = false;
+  int64_t n = 0;
+  double dt_max = -1.0;
+  double build_seconds = 0.0;
+
+  sfm_status fail(sfm_status code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  void* dalloc(size_t bytes, hipError_t* e);
+  void dfree_all();
+  void dfree(void* p);
+};

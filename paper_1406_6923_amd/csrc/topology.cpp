@@ -1,0 +1,163 @@
+// Host-side geometry: subdomain decomposition, faces, and the tile layout of the
+// coefficient stream.
+//
+// Decomposition (Introduction; Stage 1 section): the box of ncell cells is split into
+// nsub = ncell / sub_cells equal box subdomains that share their interface nodes.
+// Faces are ordered x-, x+, y-, y+, z-, z+; face f of subdomain s is an interface
+// when a neighbour box exists (nbr >= 0) and outer otherwise.  Boundary entry
+// q = f * m + patch of the boundary layer U_1 is shared with entry (f ^ 1) * m + patch
+// of the neighbour across face f.
+#include <algorithm>
+#include <cstdio>
+
+#include "sfm_internal.h"
+
+namespace sfm {
+
+void TileGeometry::init(int p_) {
+  p = p_;
+  P16 = (p + kTile - 1) / kTile * kTile;
+  nt = P16 / kTile;
+  npairs = (nt + 1) / 2;
+  nslots = nt + nt * (nt - 1) / 2;
+  auto strip_words = [&](int I) { return (int64_t)kDiagWords + (int64_t)kOffWords * (nt - 1 - I); };
+  int64_t off = 0;
+  for (int g = 0; g < npairs; ++g) {
+    job_off[g] = (int32_t)off;
+    off += strip_words(g);
+    if (g != nt - 1 - g) off += strip_words(nt - 1 - g);
+  }
+  words_per_block = off;
+}
+
+// Lane and diagonal index (t) of word w of a diagonal / off-diagonal tile in the stored order.
+static void diag_word(int w, bool bf16, int& lane, int& t) {
+  if (w >= 128) { lane = w - 128; t = 8; return; }
+  if (bf16) { lane = w / 8; t = w % 8; return; }
+  const int v = w / 64, rem = w % 64;
+  lane = rem / 4;
+  t = 4 * v + rem % 4;
+}
+
+static void off_word(int w, bool bf16, int& lane, int& t) {
+  if (bf16) {
+    const int v = w / 128, rem = w % 128;
+    lane = rem / 8;
+    t = 8 * v + rem % 8;
+    return;
+  }
+  const int v = w / 64, rem = w % 64;
+  lane = rem / 4;
+  t = 4 * v + rem % 4;
+}
+
+void TileGeometry::word_map(std::vector<int32_t>& rows, std::vector<int32_t>& cols, bool bf16) const {
+  rows.clear();
+  cols.clear();
+  rows.reserve(words_per_block);
+  cols.reserve(words_per_block);
+  for (int g = 0; g < npairs; ++g) {
+    const int strips[2] = {g, nt - 1 - g};
+    const int ns = strips[0] == strips[1] ? 1 : 2;
+    for (int si = 0; si < ns; ++si) {
+      const int I = strips[si];
+      for (int w = 0; w < kDiagWords; ++w) {
+        int lane, t;
+        diag_word(w, bf16, lane, t);
+        rows.push_back(kTile * I + lane);
+        cols.push_back(kTile * I + (lane + t) % kTile);
+      }
+      for (int J = I + 1; J < nt; ++J) {
+        for (int w = 0; w < kOffWords; ++w) {
+          int lane, t;
+          off_word(w, bf16, lane, t);
+          rows.push_back(kTile * I + lane);
+          cols.push_back(kTile * J + (lane + t) % kTile);
+        }
+      }
+    }
+  }
+}
+
+static std::string fmt(const char* f, long a = 0, long b = 0, long c = 0) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, f, a, b, c);
+  return buf;
+}
+
+std::string Topology::init(const sfm_config& cfg) {
+  for (int d = 0; d < 3; ++d) {
+    if (cfg.ncell[d] < 1) return fmt("ncell[%ld] = %ld must be positive", d, cfg.ncell[d]);
+    if (cfg.sub_cells[d] < 2) return fmt("sub_cells[%ld] = %ld must be at least 2", d, cfg.sub_cells[d]);
+    if (cfg.ncell[d] % cfg.sub_cells[d] != 0)
+      return fmt("ncell[%ld] = %ld is not a multiple of sub_cells = %ld", d, cfg.ncell[d], cfg.sub_cells[d]);
+    ncell[d] = cfg.ncell[d];
+    sub[d] = cfg.sub_cells[d];
+    nsub[d] = ncell[d] / sub[d];
+    nodes_local[d] = sub[d] + 1;
+  }
+  if (!(cfg.h > 0.0)) return "h must be positive";
+  if (cfg.m < 1) return "m must be at least 1";
+  if (cfg.k < 2) return "k must be at least 2";
+  if (cfg.precision != SFM_PREC_FP32 && cfg.precision != SFM_PREC_BF16_FP32ACC) return "unknown precision";
+  if (cfg.build_batch < 0) return "build_batch must be >= 0";
+  m = cfg.m;
+  k = cfg.k;
+  p = 6 * m;
+  if (p > kTile * kMaxNt) return fmt("6m = %ld exceeds the supported maximum %ld", p, kTile * kMaxNt);
+  // m = m1 * m2, m1 >= m2, m1 - m2 minimal
+  m1 = m;
+  m2 = 1;
+  for (int d = 1; d * d <= m; ++d)
+    if (m % d == 0) { m2 = d; m1 = m / d; }
+  const int smin = std::min(sub[0], std::min(sub[1], sub[2]));
+  if (m1 >= smin)
+    return fmt("patch count %ld along a face edge needs more than %ld cells per subdomain edge", m1, m1);
+  N_local = (int64_t)nodes_local[0] * nodes_local[1] * nodes_local[2];
+  if ((int64_t)p * k > N_local)
+    return fmt("ROM size 6mk = %ld exceeds the %ld nodes of a subdomain", (long)p * k, (long)N_local);
+  const int64_t S64 = (int64_t)nsub[0] * nsub[1] * nsub[2];
+  if (S64 > (1 << 24)) return "too many subdomains";
+  S = (int)S64;
+  nbr.assign((size_t)S * 6, -1);
+  for (int bz = 0; bz < nsub[2]; ++bz)
+    for (int by = 0; by < nsub[1]; ++by)
+      for (int bx = 0; bx < nsub[0]; ++bx) {
+        const int s = index(bx, by, bz);
+        const int b[3] = {bx, by, bz};
+        for (int f = 0; f < 6; ++f) {
+          int nb[3] = {b[0], b[1], b[2]};
+          const int d = f / 2;
+          nb[d] += (f % 2) ? 1 : -1;
+          if (nb[d] >= 0 && nb[d] < nsub[d]) nbr[(size_t)s * 6 + f] = index(nb[0], nb[1], nb[2]);
+        }
+      }
+  return "";
+}
+
+int Topology::owner(int i, int j, int l, bool strict) const {
+  const int g[3] = {i, j, l};
+  int b[3];
+  for (int d = 0; d < 3; ++d) {
+    if (g[d] < 0 || g[d] > ncell[d]) return -1;
+    const int q = g[d] / sub[d], r = g[d] % sub[d];
+    if (strict) {
+      if (r == 0) return -1;   // on a subdomain plane (interface or outer boundary)
+      b[d] = q;
+    } else {
+      b[d] = (r == 0 && q > 0) ? q - 1 : q;   // lowest box holding the node
+    }
+  }
+  return index(b[0], b[1], b[2]);
+}
+
+void Topology::origin(int s, int o[3]) const {
+  const int bx = s % nsub[0];
+  const int by = (s / nsub[0]) % nsub[1];
+  const int bz = s / (nsub[0] * nsub[1]);
+  o[0] = bx * sub[0];
+  o[1] = by * sub[1];
+  o[2] = bz * sub[2];
+}
+
+}  // namespace sfm

@@ -1,0 +1,258 @@
+"""ctypes binding of libsfm.so (include/sfm.h) with the same entry-point names.
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device arrays are passed as torch tensors on the GPU (their data pointers are
+borrowed for the duration of the stream work), host arrays as NumPy arrays,
+streams as torch.cuda.Stream (default: the current stream).  A failing call
+raises ``SfmError`` carrying the status and ``sfm_last_error``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsfm.so")
+
+SFM_OK = 0
+SFM_EINVAL = -1
+SFM_EHIP = -2
+SFM_ENOMEM = -3
+SFM_EBREAKDOWN = -4
+SFM_ESTATE = -5
+SFM_EUNSTABLE = -6
+STATUS_NAMES = {0: "SFM_OK", -1: "SFM_EINVAL", -2: "SFM_EHIP", -3: "SFM_ENOMEM",
+                -4: "SFM_EBREAKDOWN", -5: "SFM_ESTATE", -6: "SFM_EUNSTABLE"}
+SFM_PREC_FP32 = 0
+SFM_PREC_BF16_FP32ACC = 1
+
+
+class sfm_config(ctypes.Structure):
+    _fields_ = [("ncell", ctypes.c_int32 * 3), ("sub_cells", ctypes.c_int32 * 3), ("h", ctypes.c_double),
+                ("m", ctypes.c_int32), ("k", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("build_batch", ctypes.c_int32)]
+
+
+class sfm_info(ctypes.Structure):
+    _fields_ = [("n_subdomains", ctypes.c_int32), ("p", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("nsrc", ctypes.c_int32), ("nrec", ctypes.c_int32), ("has_roms", ctypes.c_int32),
+                ("steps_done", ctypes.c_int64), ("coef_bytes", ctypes.c_int64),
+                ("coef_bytes_algorithmic", ctypes.c_int64), ("state_bytes", ctypes.c_int64),
+                ("build_seconds", ctypes.c_double)]
+
+
+class SfmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+
+# name -> (restype, argtypes); mirrors include/sfm.h
+SIGNATURES = {
+    "sfm_create": (_I32, [ctypes.POINTER(sfm_config), ctypes.POINTER(_VP)]),
+    "sfm_destroy": (None, [_VP]),
+    "sfm_last_error": (ctypes.c_char_p, [_VP]),
+    "sfm_query": (_I32, [_VP, ctypes.POINTER(sfm_info)]),
+    "sfm_build_roms": (_I32, [_VP, _VP, _I32, _VP, _I32, _VP, _VP, _VP, _VP]),
+    "sfm_reset_state": (_I32, [_VP, _D, _VP]),
+    "sfm_load_roms": (_I32, [_VP, _VP, _VP, _I32, _VP, _VP, _I32, _VP, _VP]),
+    "sfm_export_roms": (_I32, [_VP, _VP, _VP]),
+    "sfm_export_projections": (_I32, [_VP, _VP, _VP]),
+    "sfm_cfl_dt": (_I32, [_VP, _I32, ctypes.POINTER(_D), _VP]),
+    "sfm_step": (_I32, [_VP, _I32, _D, _VP, _VP, _I64, _VP]),
+    "sfm_record_receivers": (_I32, [_VP, _VP, _VP]),
+    "sfm_apply_operator": (_I32, [_VP, _VP, _VP, _VP]),
+    "sfm_get_state": (_I32, [_VP, _VP, _VP, ctypes.POINTER(_I64)]),
+    "sfm_set_state": (_I32, [_VP, _VP, _VP, _I64]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libsfm.so (built in-tree by ``build_lib.build``); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1406_6923_amd.build_lib`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+# ------------------------------------------------------------------ marshalling helpers
+def _dev(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous GPU tensors")
+    return t.data_ptr()
+
+
+def _host(a, dtype) -> Optional[np.ndarray]:
+    if a is None:
+        return None
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(_VP)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _check(ctx, status: int):
+    if status != SFM_OK:
+        msg = load_library().sfm_last_error(ctx)
+        raise SfmError(status, msg.decode() if msg else "")
+
+
+# ------------------------------------------------------------------ entry points
+def sfm_create(ncell, sub_cells, h: float, m: int, k: int, precision: int = SFM_PREC_FP32,
+               build_batch: int = 0) -> int:
+    lib = load_library()
+    cfg = sfm_config((ctypes.c_int32 * 3)(*ncell), (ctypes.c_int32 * 3)(*sub_cells), float(h), int(m), int(k),
+                     int(precision), int(build_batch))
+    out = _VP()
+    status = lib.sfm_create(ctypes.byref(cfg), ctypes.byref(out))
+    _check(None, status)
+    return out.value
+
+
+def sfm_destroy(ctx: int) -> None:
+    load_library().sfm_destroy(ctx)
+
+
+def sfm_last_error(ctx: Optional[int]) -> str:
+    msg = load_library().sfm_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def sfm_query(ctx: int) -> dict:
+    info = sfm_info()
+    _check(ctx, load_library().sfm_query(ctx, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in sfm_info._fields_}
+
+
+def sfm_build_roms(ctx: int, vel, src_ijk=None, rec_ijk=None, u0=None, v0=None, stream=None) -> None:
+    src = _host(np.zeros((0, 3)) if src_ijk is None else src_ijk, np.int32).reshape(-1, 3)
+    rec = _host(np.zeros((0, 3)) if rec_ijk is None else rec_ijk, np.int32).reshape(-1, 3)
+    _check(ctx, load_library().sfm_build_roms(ctx, _dev(vel), len(src), _ptr(src), len(rec), _ptr(rec),
+                                              _dev(u0), _dev(v0), _stream(stream)))
+
+
+def sfm_reset_state(ctx: int, dt: float, stream=None) -> None:
+    _check(ctx, load_library().sfm_reset_state(ctx, float(dt), _stream(stream)))
+
+
+def sfm_load_roms(ctx: int, gamma, gamma_hat, src_ijk=None, src_vec=None, rec_ijk=None, rec_rows=None) -> None:
+    g = _host(gamma, np.float64)
+    gh = _host(gamma_hat, np.float64)
+    src = _host(np.zeros((0, 3)) if src_ijk is None else src_ijk, np.int32).reshape(-1, 3)
+    rec = _host(np.zeros((0, 3)) if rec_ijk is None else rec_ijk, np.int32).reshape(-1, 3)
+    sv = _host(src_vec, np.float64)
+    rr = _host(rec_rows, np.float64)
+    _check(ctx, load_library().sfm_load_roms(ctx, _ptr(g), _ptr(gh), len(src), _ptr(src), _ptr(sv), len(rec),
+                                             _ptr(rec), _ptr(rr)))
+
+
+def sfm_export_roms(ctx: int):
+    info = sfm_query(ctx)
+    S, k, p = info["n_subdomains"], info["k"], info["p"]
+    g = np.empty((S, k, p, p))
+    gh = np.empty((S, k, p, p))
+    _check(ctx, load_library().sfm_export_roms(ctx, _ptr(g), _ptr(gh)))
+    return g, gh
+
+
+def sfm_export_projections(ctx: int):
+    info = sfm_query(ctx)
+    k, p = info["k"], info["p"]
+    sv = np.empty((info["nsrc"], k, p))
+    rr = np.empty((info["nrec"], k, p))
+    _check(ctx, load_library().sfm_export_projections(ctx, _ptr(sv), _ptr(rr)))
+    return sv, rr
+
+
+def sfm_cfl_dt(ctx: int, iters: int = 200, stream=None) -> float:
+    out = _D()
+    _check(ctx, load_library().sfm_cfl_dt(ctx, int(iters), ctypes.byref(out), _stream(stream)))
+    return out.value
+
+
+def sfm_step(ctx: int, nsteps: int, dt: float, wavelet=None, traces=None, ld: Optional[int] = None,
+             stream=None) -> None:
+    if ld is None:
+        ld = traces.shape[-1] if traces is not None else 0
+    _check(ctx, load_library().sfm_step(ctx, int(nsteps), float(dt), _dev(wavelet), _dev(traces), int(ld),
+                                        _stream(stream)))
+
+
+def sfm_record_receivers(ctx: int, out, stream=None) -> None:
+    _check(ctx, load_library().sfm_record_receivers(ctx, _dev(out), _stream(stream)))
+
+
+def sfm_apply_operator(ctx: int, u, a, stream=None) -> None:
+    _check(ctx, load_library().sfm_apply_operator(ctx, _dev(u), _dev(a), _stream(stream)))
+
+
+def sfm_get_state(ctx: int):
+    info = sfm_query(ctx)
+    shape = (info["n_subdomains"], info["k"], info["p"])
+    u = np.empty(shape, dtype=np.float32)
+    d = np.empty(shape, dtype=np.float32)
+    n = _I64()
+    _check(ctx, load_library().sfm_get_state(ctx, _ptr(u), _ptr(d), ctypes.byref(n)))
+    return u, d, n.value
+
+
+def sfm_set_state(ctx: int, u_now=None, u_incr=None, n: int = 0) -> None:
+    u = _host(u_now, np.float32)
+    d = _host(u_incr, np.float32)
+    _check(ctx, load_library().sfm_set_state(ctx, _ptr(u), _ptr(d), int(n)))
+
+
+class Sfm:
+    """Owning handle around an sfm context (destroyed on close / garbage collection)."""
+
+    def __init__(self, ncell, sub_cells, h, m, k, precision=SFM_PREC_FP32, build_batch=0):
+        self.ctx = sfm_create(ncell, sub_cells, h, m, k, precision, build_batch)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            sfm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def info(self):
+        return sfm_query(self.ctx)

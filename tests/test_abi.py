@@ -1,0 +1,57 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad configurations before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1406_6923_amd import sfm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sfm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_documented_entry_points():
+    names = declared_functions()
+    for required in ("sfm_create", "sfm_build_roms", "sfm_step", "sfm_record_receivers", "sfm_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sfm.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(sfm.SIGNATURES)
+
+
+def test_struct_layouts_match_header():
+    # sfm_config: 3 + 3 int32, a double (8-aligned), 4 int32 -> 48 bytes
+    assert ctypes.sizeof(sfm.sfm_config) == 48
+    assert sfm.sfm_config.h.offset == 24
+    assert ctypes.sizeof(sfm.sfm_info) == 64
+
+
+@pytest.mark.parametrize("kwargs, fragment", [
+    (dict(ncell=(32, 32, 30), sub_cells=(16, 16, 16)), "multiple"),
+    (dict(ncell=(32, 32, 32), sub_cells=(16, 16, 1)), "at least 2"),
+    (dict(h=0.0), "h must be positive"),
+    (dict(m=0), "m must be"),
+    (dict(k=1), "k must be"),
+    (dict(precision=7), "precision"),
+    (dict(m=25, ncell=(8, 8, 8), sub_cells=(4, 4, 4)), "patch"),
+    (dict(m=4, k=300), "exceeds"),
+])
+def test_create_rejects_bad_config_without_gpu(kwargs, fragment):
+    args = dict(ncell=(32, 32, 32), sub_cells=(16, 16, 16), h=10.0, m=4, k=8, precision=0)
+    args.update(kwargs)
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_create(**args)
+    assert ei.value.status == sfm.SFM_EINVAL
+    assert fragment in ei.value.message

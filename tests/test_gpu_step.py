@@ -1,0 +1,140 @@
+"""GPU parity of Stage 2 (coupled leapfrog of the S-fraction ROMs) against the FP64 oracle.
+
+The ROMs come from the oracle through sfm_load_roms, so these tests isolate the step
+kernels (layer fluxes, exchange, interior and boundary updates, receivers) from the
+device ROM build.  Tolerances: one application of the step operator 1e-5 rel-L2 in
+FP32 (2e-2 with BF16 coefficient storage, relative rounding 2^-9 per word), and
+receiver traces 1e-3 rel-L2 (FP32).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.cases import oracle_case, random_consistent_state, rel_l2, rom_arrays
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _ctx(cfg, precision=0):
+    from paper_1406_6923_amd import sfm
+    return sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k, precision=precision)
+
+
+def _loaded(name, precision=0):
+    from paper_1406_6923_amd import sfm
+    cfg, c, subs, roms, cs = oracle_case(name)
+    gam, hat, src, rec = rom_arrays(cs)
+    h = _ctx(cfg, precision)
+    sfm.sfm_load_roms(h.ctx, gam, hat, cfg.sources(), src, cfg.receivers(), rec)
+    return h, cfg, cs
+
+
+@pytest.mark.parametrize("name, precision, tol", [("small", 0, 1e-5), ("ragged", 0, 1e-5), ("small", 1, 2e-2),
+                                                   ("mid", 0, 1e-5)])
+def test_step_operator_matches_oracle(name, precision, tol):
+    from paper_1406_6923_amd import sfm
+    h, cfg, cs = _loaded(name, precision)
+    U = random_consistent_state(cs, seed=11)
+    ref = np.stack(cs.accel(list(U)))
+    u_d = torch.tensor(U, dtype=torch.float32, device="cuda")
+    a_d = torch.empty_like(u_d)
+    sfm.sfm_apply_operator(h.ctx, u_d, a_d)
+    torch.cuda.synchronize()
+    got = a_d.cpu().numpy()
+    assert rel_l2(got, ref) < tol
+    # boundary layer (eq. "bdrytstep") and interior layers separately
+    assert rel_l2(got[:, 0], ref[:, 0]) < tol
+    assert rel_l2(got[:, 1:], ref[:, 1:]) < tol
+    h.close()
+
+
+@pytest.mark.parametrize("name, nsteps", [("small", 500), ("ragged", 300)])
+def test_traces_match_oracle(name, nsteps):
+    from paper_1406_6923_amd import sfm
+    h, cfg, cs = _loaded(name)
+    dt = 0.9 * cs.cfl_dt()
+    wav = W.ricker(cfg.f_peak, dt, nsteps)[:, None]
+    ref = cs.run(dt, wav)
+    w_d = torch.tensor(wav, dtype=torch.float32, device="cuda")
+    tr_d = torch.zeros((len(cs.receivers), nsteps), dtype=torch.float32, device="cuda")
+    sfm.sfm_step(h.ctx, nsteps, dt, w_d, tr_d)
+    torch.cuda.synchronize()
+    got = tr_d.cpu().numpy()
+    err = rel_l2(got, ref)
+    print(f"{name}: traces rel-L2 = {err:.3e}")
+    assert err < 1e-3
+    # the last sample equals an explicit record of the final state
+    out = torch.empty(len(cs.receivers), dtype=torch.float32, device="cuda")
+    sfm.sfm_record_receivers(h.ctx, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), got[:, -1])
+    h.close()
+
+
+def test_cfl_estimate_matches_oracle():
+    from paper_1406_6923_amd import sfm
+    h, cfg, cs = _loaded("small")
+    dt_gpu = sfm.sfm_cfl_dt(h.ctx, iters=400)
+    dt_ref = cs.cfl_dt()
+    assert dt_gpu == pytest.approx(dt_ref, rel=0.02)
+    assert dt_gpu >= dt_ref * (1 - 1e-6)       # power iteration bounds rho from below
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_step(h.ctx, 1, 1.01 * dt_gpu, torch.zeros((1, 1), device="cuda"))
+    assert ei.value.status == sfm.SFM_EUNSTABLE
+    h.close()
+
+
+def test_checkpoint_resume_and_determinism():
+    from paper_1406_6923_amd import sfm
+    h, cfg, cs = _loaded("small")
+    dt = 0.9 * cs.cfl_dt()
+    wav = torch.tensor(W.ricker(cfg.f_peak, dt, 200)[:, None], dtype=torch.float32, device="cuda")
+    sfm.sfm_step(h.ctx, 200, dt, wav)
+    u_full, d_full, n = sfm.sfm_get_state(h.ctx)
+    assert n == 200
+    # same run again, interrupted by a checkpoint at 120
+    sfm.sfm_set_state(h.ctx, None, None, 0)
+    sfm.sfm_step(h.ctx, 120, dt, wav[:120].contiguous())
+    u, d, n = sfm.sfm_get_state(h.ctx)
+    sfm.sfm_set_state(h.ctx, np.zeros_like(u), np.zeros_like(d), 0)
+    sfm.sfm_set_state(h.ctx, u, d, n)
+    sfm.sfm_step(h.ctx, 80, dt, wav[120:].contiguous())
+    u2, d2, n2 = sfm.sfm_get_state(h.ctx)
+    assert n2 == 200
+    assert np.array_equal(u2, u_full) and np.array_equal(d2, d_full)
+    # shared boundary entries stay bit-identical on both sides of every face
+    X = cs.gather(list(u2.astype(np.float64)))
+    assert np.array_equal(np.stack(cs.scatter(X)).astype(np.float32), u2)
+    h.close()
+
+
+def test_bf16_traces_report():
+    """BF16 coefficient storage (FP32 accumulation): traces stay within 5e-2 of FP64."""
+    from paper_1406_6923_amd import sfm
+    h, cfg, cs = _loaded("small", precision=1)
+    dt = 0.9 * cs.cfl_dt()
+    nsteps = 500
+    wav = W.ricker(cfg.f_peak, dt, nsteps)[:, None]
+    ref = cs.run(dt, wav)
+    tr_d = torch.zeros((len(cs.receivers), nsteps), dtype=torch.float32, device="cuda")
+    sfm.sfm_step(h.ctx, nsteps, dt, torch.tensor(wav, dtype=torch.float32, device="cuda"), tr_d)
+    torch.cuda.synchronize()
+    err = rel_l2(tr_d.cpu().numpy(), ref)
+    print(f"bf16 traces rel-L2 = {err:.3e}")
+    assert err < 5e-2
+    h.close()
+
+
+def test_state_errors():
+    from paper_1406_6923_amd import sfm
+    cfg = W.CFG_SMALL
+    h = _ctx(cfg)
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_step(h.ctx, 1, 1e-3)
+    assert ei.value.status == sfm.SFM_ESTATE
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_load_roms(h.ctx, np.zeros((8, 8, 24, 24)), np.ones((8, 8, 24, 24)))
+    assert ei.value.status == sfm.SFM_EINVAL        # Gamma-hat_1 not diagonal
+    h.close()
