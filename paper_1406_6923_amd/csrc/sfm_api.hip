@@ -550,6 +550,7 @@ sfm_status sfm_apply_operator(sfm_ctx c, const float* u_dev, float* a_dev, void*
     return SFM_OK;
   }
   SFM_TRY_HIP(c, hipMemsetAsync(c->work_a_d, 0, (size_t)t.S * t.k * P16 * sizeof(float), st));
+  SFM_TRY_HIP(c, hipMemsetAsync(c->work_b_d, 0, (size_t)t.S * t.k * P16 * sizeof(float), st));
   SFM_TRY_HIP(c, hipMemcpy2DAsync(c->work_a_d, P16 * sizeof(float), u_dev, t.p * sizeof(float),
                                   t.p * sizeof(float), (size_t)t.S * t.k, hipMemcpyDeviceToDevice, st));
   SFM_TRY_HIP(c, apply_operator(c, c->work_a_d, c->work_b_d, st));
@@ -583,6 +584,8 @@ sfm_status sfm_cfl_dt(sfm_ctx c, int32_t iters, double* dt_max, void* stream) {
       const int nb = t.nbr[(size_t)s * 6 + f];
       if (nb >= 0 && nb < s) v[(size_t)s * t.k * P16 + q] = v[(size_t)nb * t.k * P16 + (f ^ 1) * t.m + pat];
     }
+  // Padding entries of the boundary layer are never written by the operator: clear them.
+  SFM_TRY_HIP(c, hipMemsetAsync(c->work_b_d, 0, n * sizeof(float), st));
   SFM_TRY_HIP(c, hipMemcpyAsync(c->work_a_d, v.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
   SFM_TRY_HIP(c, launch_norm2(c->work_a_d, n, c->red_d, st));
   SFM_TRY_HIP(c, launch_scale(c->work_a_d, n, c->red_d, c->work_a_d, st));
