@@ -1,10 +1,678 @@
-// Stage 1 of Algorithm 1 on the device (ROM construction) -- entry point.
+// Stage 1 of Algorithm 1 on the device: one ROM per subdomain, built in batches.
+//
+//  a1  operator and basis: A_+ = M^{-1/2} K M^{-1/2} of the subdomain box (node-based
+//      7-point stencil with mirror closure on the box faces, shared interface nodes with
+//      halved dual volumes) and F = M^{-1/2} E (m piecewise-constant patches per face;
+//      each boundary node owned by one face, interface faces first).  Because the patch
+//      functions do not overlap, F^T F = diag(H) and Q_1 = F diag(H)^{-1/2}, B_1 = diag(H^{1/2}).
+//  a2  block Lanczos on (A_+, F) (polynomial Krylov space, the combined steps 1.1 + 1.2 of
+//      Algorithm 1): W = A_+ Q_j, two passes of classical Gram-Schmidt against all blocks
+//      so far (A_j from the projection coefficients), then two passes of Cholesky QR,
+//      W = Q_{j+1} B_{j+1} with B upper triangular, all in FP64.
+//  a3  S-fraction (eq. "GammaTrans"), FP64, with G_1 = B_1^T and
+//        Gamma-hat_j = G_j G_j^T,  Gamma_j = G_j^{-T} A_j G_j^{-1} - Gamma_{j-1},
+//        G_{j+1} = -Gamma_j^{-1} G_j^{-T} B_{j+1}^T,  G_{j+1}^{-1} = -B_{j+1}^{-T} G_j^T Gamma_j
+//      (the last identity keeps every inverse triangular or SPD: no pivoting).
+//  a4  projections (eq. "Uj"): s = G Z^T M^{-1/2} e_s, r = e_r^T M^{-1/2} Z G^{-1}, and
+//      U(0) = G Z^T M^{1/2} u0.
+// The reductions run in FP64 on the device; the large dense products (Z^T W, Z C, W^T W and the
+// triangular solves with N right-hand sides) are plain rocBLAS strided-batched DGEMM/DTRSM calls.
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <string>
+#include <vector>
+
 #include "sfm_internal.h"
+
+namespace sfm {
+namespace {
+
+// Relative Gram pivot below which a Lanczos block counts as rank deficient: the independent
+// part of a column is below ~3e-7 of its norm, where Cholesky QR can no longer orthogonalise it.
+constexpr double kGramRelTol = 1e-13;
+
+struct BoxGeo {
+  int sub[3];        // cells per edge
+  int n[3];          // nodes per edge
+  int m, m1, m2, p;
+  double h;
+};
+
+__device__ __forceinline__ void local_ijk(const BoxGeo& g, int64_t node, int& i, int& j, int& l) {
+  i = (int)(node % g.n[0]);
+  const int64_t r = node / g.n[0];
+  j = (int)(r % g.n[1]);
+  l = (int)(r / g.n[1]);
+}
+
+__device__ __forceinline__ double half_if(bool on) { return on ? 0.5 : 1.0; }
+
+// Owner face of a boundary node (-1 for interior nodes): among the faces whose plane holds
+// the node, the first interface face in the order x-, x+, y-, y+, z-, z+, else the first outer one.
+__device__ __forceinline__ int owner_face(const BoxGeo& g, int i, int j, int l, int nbmask) {
+  const bool on[6] = {i == 0, i == g.sub[0], j == 0, j == g.sub[1], l == 0, l == g.sub[2]};
+  for (int f = 0; f < 6; ++f)
+    if (on[f] && ((nbmask >> f) & 1)) return f;
+  for (int f = 0; f < 6; ++f)
+    if (on[f]) return f;
+  return -1;
+}
+
+// Patch index of a node on face f: strips min(floor(a m1 / n1), m1-1) x min(floor(b m2 / n2), m2-1)
+// over the tangential axes in increasing order.
+__device__ __forceinline__ int patch_of(const BoxGeo& g, int f, const int c[3]) {
+  const int d = f >> 1;
+  const int t1 = d == 0 ? 1 : 0;
+  const int t2 = d == 2 ? 1 : 2;
+  const int q1 = min(c[t1] * g.m1 / g.sub[t1], g.m1 - 1);
+  const int q2 = min(c[t2] * g.m2 / g.sub[t2], g.m2 - 1);
+  return q1 * g.m2 + q2;
+}
+
+// Dual face area of a boundary node inside its owner face: h^2 halved per tangential box plane.
+__device__ __forceinline__ double patch_weight(const BoxGeo& g, int f, const int c[3]) {
+  const int d = f >> 1;
+  double w = g.h * g.h;
+  for (int t = 0; t < 3; ++t)
+    if (t != d) w *= half_if(c[t] == 0 || c[t] == g.sub[t]);
+  return w;
+}
+
+// S = M^{-1/2} = c / sqrt(w h^3) at every node of every subdomain of the batch.
+__global__ void node_scale_kernel(BoxGeo g, const float* __restrict__ vel, int ncx, int ncy, const int32_t* __restrict__ org,
+                                  int64_t N, int nb, double* __restrict__ S, int* __restrict__ bad) {
+  const int64_t total = (int64_t)nb * N;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / N);
+    const int64_t n = idx - (int64_t)b * N;
+    int i, j, l;
+    local_ijk(g, n, i, j, l);
+    const int gi = org[3 * b] + i, gj = org[3 * b + 1] + j, gl = org[3 * b + 2] + l;
+    const double c = vel[((int64_t)gl * (ncy + 1) + gj) * (ncx + 1) + gi];
+    if (!(c > 0.0) || !isfinite(c)) *bad = 1;
+    const double w = half_if(i == 0 || i == g.sub[0]) * half_if(j == 0 || j == g.sub[1]) *
+                     half_if(l == 0 || l == g.sub[2]);
+    S[idx] = c / sqrt(w * g.h * g.h * g.h);
+  }
+}
+
+// H[b][col] = sum over the patch's owned nodes of (E S)^2 = (F^T F)_{col,col}.
+__global__ void face_mass_kernel(BoxGeo g, const double* __restrict__ S, const int32_t* __restrict__ nbmask, int64_t N,
+                                 int nb, double* __restrict__ H) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nb * g.p) return;
+  const int b = idx / g.p, col = idx - b * g.p;
+  const int f = col / g.m, q = col - f * g.m;
+  const int d = f >> 1;
+  const int t1 = d == 0 ? 1 : 0;
+  const int t2 = d == 2 ? 1 : 2;
+  double acc = 0.0;
+  for (int a = 0; a <= g.sub[t1]; ++a) {
+    if (min(a * g.m1 / g.sub[t1], g.m1 - 1) != q / g.m2) continue;
+    for (int bb = 0; bb <= g.sub[t2]; ++bb) {
+      if (min(bb * g.m2 / g.sub[t2], g.m2 - 1) != q % g.m2) continue;
+      int c[3];
+      c[d] = (f & 1) ? g.sub[d] : 0;
+      c[t1] = a;
+      c[t2] = bb;
+      if (owner_face(g, c[0], c[1], c[2], nbmask[b]) != f) continue;
+      const int64_t n = ((int64_t)c[2] * g.n[1] + c[1]) * g.n[0] + c[0];
+      const double e = patch_weight(g, f, c) * S[(int64_t)b * N + n];
+      acc += e * e;
+    }
+  }
+  H[idx] = acc;
+}
+
+// Q_1 = F diag(H)^{-1/2} into columns 0..p-1 of Z (node-major, ld = kp).
+__global__ void init_q1_kernel(BoxGeo g, const double* __restrict__ S, const int32_t* __restrict__ nbmask,
+                               const double* __restrict__ H, int64_t N, int kp, int nb, double* __restrict__ Z) {
+  const int64_t total = (int64_t)nb * N * g.p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int col = (int)(idx % g.p);
+    const int64_t bn = idx / g.p;
+    const int b = (int)(bn / N);
+    const int64_t n = bn - (int64_t)b * N;
+    int c[3];
+    local_ijk(g, n, c[0], c[1], c[2]);
+    double v = 0.0;
+    const int f = owner_face(g, c[0], c[1], c[2], nbmask[b]);
+    if (f >= 0 && col == f * g.m + patch_of(g, f, c))
+      v = patch_weight(g, f, c) * S[(int64_t)b * N + n] / sqrt(H[(int64_t)b * g.p + col]);
+    Z[((int64_t)b * N + n) * kp + col] = v;
+  }
+}
+
+// W = A_+ X = S K S X for the p columns of X (ld ldx) into W (ld ldw).
+// K is the geometric stiffness: coefficient h per edge, halved for every box plane holding the edge.
+__global__ void stencil_kernel(BoxGeo g, const double* __restrict__ S, int64_t N, int nb, const double* __restrict__ X,
+                               int ldx, int64_t sx, double* __restrict__ W, int ldw, int64_t sw) {
+  const int64_t total = (int64_t)nb * N * g.p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int col = (int)(idx % g.p);
+    const int64_t bn = idx / g.p;
+    const int b = (int)(bn / N);
+    const int64_t n = bn - (int64_t)b * N;
+    int i, j, l;
+    local_ijk(g, n, i, j, l);
+    const double* Sb = S + (int64_t)b * N;
+    const double* Xb = X + (int64_t)b * sx + col;
+    const double sn = Sb[n];
+    const double yn = sn * Xb[n * ldx];
+    const double wi = half_if(i == 0 || i == g.sub[0]);
+    const double wj = half_if(j == 0 || j == g.sub[1]);
+    const double wl = half_if(l == 0 || l == g.sub[2]);
+    double acc = 0.0;
+    const int64_t sxn = 1, syn = g.n[0], szn = (int64_t)g.n[0] * g.n[1];
+    // x-edges lie in the planes normal to y and z that hold them
+    const double cx = g.h * wj * wl, cy = g.h * wi * wl, cz = g.h * wi * wj;
+    if (i > 0) acc += cx * (yn - Sb[n - sxn] * Xb[(n - sxn) * ldx]);
+    if (i < g.sub[0]) acc += cx * (yn - Sb[n + sxn] * Xb[(n + sxn) * ldx]);
+    if (j > 0) acc += cy * (yn - Sb[n - syn] * Xb[(n - syn) * ldx]);
+    if (j < g.sub[1]) acc += cy * (yn - Sb[n + syn] * Xb[(n + syn) * ldx]);
+    if (l > 0) acc += cz * (yn - Sb[n - szn] * Xb[(n - szn) * ldx]);
+    if (l < g.sub[2]) acc += cz * (yn - Sb[n + szn] * Xb[(n + szn) * ldx]);
+    W[(int64_t)b * sw + n * ldw + col] = sn * acc;
+  }
+}
+
+// Cholesky A = L L^T in place (column-major p x p, lower), one work-group per matrix.
+// A pivot d_c marks a breakdown of matrix b when d_c <= max(thr[b], rel * A_cc) with A_cc the
+// diagonal before factorisation.  For a Gram matrix W^T W the relative test catches a column
+// whose component independent of the previous ones has fallen to rounding level (forming the
+// Gram squares the condition number, so such a pivot is noise of size eps * A_cc, not ~0).
+__global__ __launch_bounds__(256) void cholesky_kernel(double* __restrict__ A, int p, int64_t stride,
+                                                       const double* __restrict__ thr, double rel,
+                                                       int* __restrict__ flag) {
+  double* a = A + (int64_t)blockIdx.x * stride;
+  __shared__ double piv;
+  __shared__ int bad;
+  __shared__ double diag0[kTile * kMaxNt];
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int c = tid; c < p; c += blockDim.x) diag0[c] = a[c + (int64_t)c * p];
+  for (int c = 0; c < p; ++c) {
+    __syncthreads();
+    if (tid == 0) {
+      double d = a[c + (int64_t)c * p];
+      const double t = fmax(thr ? thr[blockIdx.x] : 0.0, rel * diag0[c]);
+      if (!(d > t)) {
+        bad = 1;
+        d = 1.0;
+      }
+      piv = sqrt(d);
+      a[c + (int64_t)c * p] = piv;
+    }
+    __syncthreads();
+    const double inv = 1.0 / piv;
+    for (int i = c + 1 + tid; i < p; i += blockDim.x) a[i + (int64_t)c * p] *= inv;
+    __syncthreads();
+    const int nr = p - c - 1;
+    for (int e = tid; e < nr * nr; e += blockDim.x) {
+      const int ii = e % nr, jj = e / nr;
+      if (ii >= jj) {
+        const int i = c + 1 + ii, j = c + 1 + jj;
+        a[i + (int64_t)j * p] -= a[i + (int64_t)c * p] * a[j + (int64_t)c * p];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < p * p; e += blockDim.x) {
+    const int i = e % p, j = e / p;
+    if (i < j) a[e] = 0.0;
+  }
+  if (tid == 0 && bad) flag[blockIdx.x] = 1;
+}
+
+// out_j = sym(C1 block j + C2 block j) (projection coefficients of W on Q_j) -> A_j.
+__global__ void accum_a_kernel(const double* __restrict__ C1, const double* __restrict__ C2, int p, int64_t sc,
+                               int off, double* __restrict__ A, int64_t sa, int nb) {
+  const int64_t total = (int64_t)nb * p * p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / ((int64_t)p * p));
+    const int e = (int)(idx - (int64_t)b * p * p);
+    const int r = e % p, c = e / p;
+    const double* c1 = C1 + b * sc + (int64_t)off * p;
+    const double* c2 = C2 ? C2 + b * sc + (int64_t)off * p : nullptr;
+    double v = c1[r + c * p] + c1[c + r * p];
+    if (c2) v += c2[r + c * p] + c2[c + r * p];
+    A[b * sa + e] = 0.5 * v;
+  }
+}
+
+__global__ void symmetrize_kernel(double* __restrict__ A, int p, int64_t stride, int nb) {
+  const int64_t total = (int64_t)nb * p * p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / ((int64_t)p * p));
+    const int e = (int)(idx - (int64_t)b * p * p);
+    const int r = e % p, c = e / p;
+    if (r < c) {
+      double* a = A + b * stride;
+      const double v = 0.5 * (a[r + c * p] + a[c + r * p]);
+      a[r + c * p] = v;
+      a[c + r * p] = v;
+    }
+  }
+}
+
+// diag(v) or diag(1/v) (column-major p x p) from H: G_1 = B_1^T = diag(H^{1/2}), G_1^{-1}, and B_1^T.
+__global__ void diag_kernel(const double* __restrict__ H, int p, int nb, double* __restrict__ D, int64_t sd, int mode) {
+  const int64_t total = (int64_t)nb * p * p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / ((int64_t)p * p));
+    const int e = (int)(idx - (int64_t)b * p * p);
+    const int r = e % p, c = e / p;
+    double v = 0.0;
+    if (r == c) {
+      const double s = sqrt(H[(int64_t)b * p + r]);
+      v = mode == 0 ? s : 1.0 / s;
+    }
+    D[b * sd + e] = v;
+  }
+}
+
+__global__ void copy_blocks_kernel(const double* __restrict__ src, int64_t ss, double* __restrict__ dst, int64_t sd,
+                                   int64_t n, int nb, double scale) {
+  const int64_t total = (int64_t)nb * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / n);
+    const int64_t e = idx - (int64_t)b * n;
+    dst[b * sd + e] = scale * src[b * ss + e];
+  }
+}
+
+// Source vectors s_j = G_j z_j and receiver rows r_j = z_j^T G_j^{-1} with z = M^{-1/2} Z^T e_node.
+__global__ void project_points_kernel(const double* __restrict__ Z, const double* __restrict__ S, int64_t N, int k, int p,
+                                      const double* __restrict__ G, const double* __restrict__ Gi, int64_t sg,
+                                      const int32_t* __restrict__ pb, const int32_t* __restrict__ pnode,
+                                      const int32_t* __restrict__ pid, int npts, int mode, double* __restrict__ out) {
+  const int64_t total = (int64_t)npts * k * p;
+  const int kp = k * p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(idx % p);
+    const int64_t pj = idx / p;
+    const int j = (int)(pj % k);
+    const int pt = (int)(pj / k);
+    const int b = pb[pt];
+    const int64_t n = pnode[pt];
+    const double sn = S[(int64_t)b * N + n];
+    const double* z = Z + ((int64_t)b * N + n) * kp + (int64_t)j * p;
+    const double* M = (mode == 0 ? G : Gi) + b * sg + (int64_t)j * p * p;
+    double acc = 0.0;
+    if (mode == 0) {
+      for (int c = 0; c < p; ++c) acc += M[e + (int64_t)c * p] * z[c];       // (G_j z_j)[e]
+    } else {
+      for (int r = 0; r < p; ++r) acc += z[r] * M[r + (int64_t)e * p];       // (z_j^T G_j^{-1})[e]
+    }
+    out[((int64_t)pid[pt] * k + j) * p + e] = sn * acc;
+  }
+}
+
+// y[b][col] = sum_n Z[b][n][col] u(n) / S_n for col < kp (Z^T M^{1/2} u).
+__global__ void project_field_kernel(BoxGeo g, const double* __restrict__ Z, const double* __restrict__ S, int64_t N,
+                                     int kp, int nb, const float* __restrict__ u, int ncx, int ncy,
+                                     const int32_t* __restrict__ org, double* __restrict__ y) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nb * kp) return;
+  const int b = idx / kp, col = idx - b * kp;
+  double acc = 0.0;
+  for (int64_t n = 0; n < N; ++n) {
+    int i, j, l;
+    local_ijk(g, n, i, j, l);
+    const int gi = org[3 * b] + i, gj = org[3 * b + 1] + j, gl = org[3 * b + 2] + l;
+    const double un = u[((int64_t)gl * (ncy + 1) + gj) * (ncx + 1) + gi];
+    acc += Z[((int64_t)b * N + n) * kp + col] * un / S[(int64_t)b * N + n];
+  }
+  y[idx] = acc;
+}
+
+// U_j = G_j y_j into the FP32 state layout [S][k][P16].
+__global__ void apply_g_kernel(const double* __restrict__ y, const double* __restrict__ G, int64_t sg, int k, int p,
+                               int P16, int nb, int s0, float* __restrict__ U) {
+  const int64_t total = (int64_t)nb * k * p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(idx % p);
+    const int64_t bj = idx / p;
+    const int j = (int)(bj % k);
+    const int b = (int)(bj / k);
+    const double* M = G + b * sg + (int64_t)j * p * p;
+    const double* yj = y + (int64_t)b * k * p + (int64_t)j * p;
+    double acc = 0.0;
+    for (int c = 0; c < p; ++c) acc += M[e + (int64_t)c * p] * yj[c];
+    U[(((int64_t)(s0 + b)) * k + j) * P16 + e] = (float)acc;
+  }
+}
+
+// Boundary-layer entries shared with a lower-index neighbour take that neighbour's value.
+__global__ void unify_ports_kernel(const int32_t* __restrict__ nbr, int S, int k, int p, int m, int P16,
+                                   float* __restrict__ U) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)S * p) return;
+  const int s = (int)(idx / p), q = (int)(idx - (int64_t)s * p);
+  const int f = q / m, pat = q - f * m;
+  const int nb = nbr[s * 6 + f];
+  if (nb >= 0 && nb < s) U[(int64_t)s * k * P16 + q] = U[(int64_t)nb * k * P16 + (f ^ 1) * m + pat];
+}
+
+unsigned grid_for(int64_t n, int threads = 256) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + threads - 1) / threads, 1 << 20));
+}
+
+}  // namespace
+
+void destroy_blas(sfm_ctx c) {
+  if (c->blas) {
+    rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
+    c->blas = nullptr;
+  }
+}
+
+}  // namespace sfm
+
+using namespace sfm;
+
+#define B_TRY_HIP(call)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) return c->fail(SFM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define B_TRY_BLAS(call)                                                                      \
+  do {                                                                                        \
+    rocblas_status s_ = (call);                                                               \
+    if (s_ != rocblas_status_success)                                                         \
+      return c->fail(SFM_EHIP, std::string(#call) + ": " + rocblas_status_to_string(s_));     \
+  } while (0)
+
+#define B_LAUNCH(kernel, n, ...)                                                              \
+  do {                                                                                        \
+    hipLaunchKernelGGL(kernel, dim3(grid_for(n)), dim3(256), 0, st, __VA_ARGS__);             \
+    B_TRY_HIP(hipGetLastError());                                                             \
+  } while (0)
 
 extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t nsrc, const int32_t* src_ijk,
                                      int32_t nrec, const int32_t* rec_ijk, const float* u0_dev,
                                      const float* v0_dev, void* stream) {
-  (void)vel_dev; (void)nsrc; (void)src_ijk; (void)nrec; (void)rec_ijk; (void)u0_dev; (void)v0_dev; (void)stream;
   if (!c) return SFM_EINVAL;
-  return c->fail(SFM_EINVAL, "device ROM build is not available in this build");
+  c->err.clear();
+  if (!vel_dev) return c->fail(SFM_EINVAL, "vel_dev is NULL");
+  const auto t_start = std::chrono::steady_clock::now();
+  B_TRY_HIP(hipSetDevice(c->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const Topology& t = c->topo;
+  const int S = t.S, k = t.k, p = t.p, kp = k * p, P16 = c->geo.P16;
+  const int64_t N = t.N_local;
+  const int64_t pp = (int64_t)p * p;
+  std::vector<int32_t> src_sub, src_local, rec_sub, rec_local;
+  sfm_status rc = locate_points(c, nsrc, src_ijk, nrec, rec_ijk, src_sub, src_local, rec_sub, rec_local);
+  if (rc != SFM_OK) return rc;
+
+  if (!c->blas) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return c->fail(SFM_EHIP, "rocblas_create_handle failed");
+    c->blas = h;
+  }
+  rocblas_handle h = static_cast<rocblas_handle>(c->blas);
+  B_TRY_BLAS(rocblas_set_stream(h, st));
+  B_TRY_BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
+
+  release_roms(c);
+  hipError_t e = hipSuccess;
+  c->coef64_d = static_cast<double*>(c->dalloc((size_t)S * 2 * k * pp * sizeof(double), &e));
+  if (!c->coef64_d) return c->fail(SFM_ENOMEM, "FP64 coefficients: out of device memory");
+  if (nsrc > 0) c->src_vec64_d = static_cast<double*>(c->dalloc((size_t)nsrc * kp * sizeof(double), &e));
+  if (nrec > 0) c->rec_rows64_d = static_cast<double*>(c->dalloc((size_t)nrec * kp * sizeof(double), &e));
+  const bool ic = u0_dev || v0_dev;
+  if (ic) {
+    c->U0_d = static_cast<float*>(c->dalloc((size_t)S * k * P16 * sizeof(float), &e));
+    c->V0_d = static_cast<float*>(c->dalloc((size_t)S * k * P16 * sizeof(float), &e));
+    if (e == hipSuccess) e = hipMemsetAsync(c->U0_d, 0, (size_t)S * k * P16 * sizeof(float), st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->V0_d, 0, (size_t)S * k * P16 * sizeof(float), st);
+  }
+  if (e != hipSuccess) return c->fail(SFM_ENOMEM, "projection buffers: out of device memory");
+
+  // batch size from the free device memory
+  const int64_t per_sub = (int64_t)sizeof(double) *
+                          (N * kp + N * p + N + 2 * (int64_t)kp * p + 7 * (int64_t)k * pp + 6 * pp + kp + 8);
+  int nbmax = c->cfg.build_batch;
+  if (nbmax <= 0) {
+    size_t fr = 0, tot = 0;
+    B_TRY_HIP(hipMemGetInfo(&fr, &tot));
+    nbmax = (int)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(0.6 * (double)fr) / per_sub));
+  }
+  nbmax = std::min(nbmax, S);
+  std::vector<void*> scratch;
+  auto salloc = [&](size_t bytes) -> double* {
+    void* ptr = c->dalloc(bytes, &e);
+    if (ptr) scratch.push_back(ptr);
+    return static_cast<double*>(ptr);
+  };
+  double* Z = salloc((size_t)nbmax * N * kp * sizeof(double));
+  double* Wl = salloc((size_t)nbmax * N * p * sizeof(double));
+  double* Sd = salloc((size_t)nbmax * N * sizeof(double));
+  double* C1 = salloc((size_t)nbmax * kp * p * sizeof(double));
+  double* C2 = salloc((size_t)nbmax * kp * p * sizeof(double));
+  double* A = salloc((size_t)nbmax * k * pp * sizeof(double));
+  double* Bt = salloc((size_t)nbmax * k * pp * sizeof(double));
+  double* G = salloc((size_t)nbmax * k * pp * sizeof(double));
+  double* Gi = salloc((size_t)nbmax * k * pp * sizeof(double));
+  double* Gam = salloc((size_t)nbmax * k * pp * sizeof(double));
+  double* Gh = salloc((size_t)nbmax * k * pp * sizeof(double));
+  double* L1 = salloc((size_t)nbmax * pp * sizeof(double));
+  double* L2 = salloc((size_t)nbmax * pp * sizeof(double));
+  double* T1 = salloc((size_t)nbmax * pp * sizeof(double));
+  double* Hb = salloc((size_t)nbmax * p * sizeof(double));
+  double* thr = salloc((size_t)nbmax * sizeof(double));
+  double* ybuf = salloc((size_t)nbmax * kp * sizeof(double));
+  int32_t* flags = reinterpret_cast<int32_t*>(salloc((size_t)(nbmax + 1) * sizeof(int32_t)));
+  int32_t* meta = reinterpret_cast<int32_t*>(salloc((size_t)nbmax * 4 * sizeof(int32_t)));
+  int32_t* pts = reinterpret_cast<int32_t*>(salloc((size_t)(std::max(nsrc, nrec) + 1) * 3 * sizeof(int32_t)));
+  auto cleanup = [&]() {
+    for (void* ptr : scratch) c->dfree(ptr);
+    scratch.clear();
+  };
+  if (e != hipSuccess) {
+    cleanup();
+    return c->fail(SFM_ENOMEM, "ROM build scratch: out of device memory (lower build_batch)");
+  }
+  const BoxGeo g{{t.sub[0], t.sub[1], t.sub[2]}, {t.nodes_local[0], t.nodes_local[1], t.nodes_local[2]},
+                 t.m, t.m1, t.m2, p, c->cfg.h};
+  std::vector<double> Hall((size_t)S * p);
+  const double one = 1.0, zero = 0.0, mone = -1.0;
+  const rocblas_operation NN = rocblas_operation_none, TT = rocblas_operation_transpose;
+
+  sfm_status status = SFM_OK;
+  for (int s0 = 0; s0 < S && status == SFM_OK; s0 += nbmax) {
+    const int nb = std::min(nbmax, S - s0);
+    // batch metadata: origins and neighbour masks
+    std::vector<int32_t> org(3 * nb), mask(nb);
+    for (int b = 0; b < nb; ++b) {
+      int o[3];
+      t.origin(s0 + b, o);
+      org[3 * b] = o[0]; org[3 * b + 1] = o[1]; org[3 * b + 2] = o[2];
+      int mk = 0;
+      for (int f = 0; f < 6; ++f)
+        if (t.nbr[(size_t)(s0 + b) * 6 + f] >= 0) mk |= 1 << f;
+      mask[b] = mk;
+    }
+    int32_t* org_d = meta;
+    int32_t* mask_d = meta + 3 * nbmax;
+    B_TRY_HIP(hipMemcpyAsync(org_d, org.data(), org.size() * 4, hipMemcpyHostToDevice, st));
+    B_TRY_HIP(hipMemcpyAsync(mask_d, mask.data(), mask.size() * 4, hipMemcpyHostToDevice, st));
+    B_TRY_HIP(hipMemsetAsync(flags, 0, (size_t)(nbmax + 1) * sizeof(int32_t), st));
+
+    // a1: scaling, face masses, Q_1
+    B_LAUNCH(node_scale_kernel, (int64_t)nb * N, g, vel_dev, t.ncell[0], t.ncell[1], org_d, N, nb, Sd, flags + nbmax);
+    B_LAUNCH(face_mass_kernel, (int64_t)nb * p, g, Sd, mask_d, N, nb, Hb);
+    B_TRY_HIP(hipMemcpyAsync(Hall.data() + (size_t)s0 * p, Hb, (size_t)nb * p * sizeof(double), hipMemcpyDeviceToHost, st));
+    B_TRY_HIP(hipStreamSynchronize(st));
+    std::vector<double> thr_h(nb);
+    for (int b = 0; b < nb; ++b) {
+      double hm = 0.0;
+      for (int q = 0; q < p; ++q) {
+        const double hv = Hall[(size_t)(s0 + b) * p + q];
+        if (!(hv > 0.0)) {
+          cleanup();
+          return c->fail(SFM_EBREAKDOWN, "subdomain " + std::to_string(s0 + b) + ": empty boundary patch " +
+                                             std::to_string(q) + " (rank-deficient start block)");
+        }
+        hm = std::max(hm, hv);
+      }
+      thr_h[b] = 1e-24 * hm;   // |diag B| < 1e-12 |B_1|
+    }
+    B_TRY_HIP(hipMemcpyAsync(thr, thr_h.data(), nb * sizeof(double), hipMemcpyHostToDevice, st));
+    B_LAUNCH(init_q1_kernel, (int64_t)nb * N * p, g, Sd, mask_d, Hb, N, kp, nb, Z);
+    B_LAUNCH(diag_kernel, (int64_t)nb * pp, Hb, p, nb, Bt, (int64_t)k * pp, 0);   // B_1^T = diag(H^{1/2})
+
+    // a2: block Lanczos with two-pass CGS and two-pass Cholesky QR
+    const int64_t sZ = N * kp;
+    for (int jj = 0; jj < k; ++jj) {
+      const bool last = jj + 1 == k;
+      double* W = last ? Wl : Z + (int64_t)(jj + 1) * p;
+      const int ldw = last ? p : kp;
+      const int64_t sW = last ? N * p : sZ;
+      B_LAUNCH(stencil_kernel, (int64_t)nb * N * p, g, Sd, N, nb, Z + (int64_t)jj * p, kp, sZ, W, ldw, sW);
+      const int nprev = (jj + 1) * p;
+      // C1 = Z_{1..j}^T W  (column-major p x nprev, C1[r + c p] = (Z^T W)[c][r])
+      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, nprev, (int)N, &one, W, ldw, sW, Z, kp, sZ, &zero, C1, p,
+                                               (int64_t)kp * p, nb));
+      if (last) {
+        B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, (const double*)nullptr, p, (int64_t)kp * p, jj * p,
+                 A + (int64_t)jj * pp, (int64_t)k * pp, nb);
+        break;
+      }
+      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)N, nprev, &mone, C1, p, (int64_t)kp * p, Z, kp, sZ,
+                                               &one, W, ldw, sW, nb));
+      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, nprev, (int)N, &one, W, ldw, sW, Z, kp, sZ, &zero, C2, p,
+                                               (int64_t)kp * p, nb));
+      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)N, nprev, &mone, C2, p, (int64_t)kp * p, Z, kp, sZ,
+                                               &one, W, ldw, sW, nb));
+      B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, C2, p, (int64_t)kp * p, jj * p, A + (int64_t)jj * pp,
+               (int64_t)k * pp, nb);
+      // Cholesky QR, twice: W = Q (L1 L2)^T
+      double* Ls[2] = {L1, L2};
+      for (int pass = 0; pass < 2; ++pass) {
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, p, (int)N, &one, W, ldw, sW, W, ldw, sW, &zero, Ls[pass],
+                                                 p, pp, nb));
+        hipLaunchKernelGGL(cholesky_kernel, dim3(nb), dim3(256), 0, st, Ls[pass], p, pp,
+                           pass == 0 ? (const double*)thr : (const double*)nullptr, kGramRelTol, flags);
+        B_TRY_HIP(hipGetLastError());
+        B_TRY_BLAS(rocblas_dtrsm_strided_batched(h, rocblas_side_left, rocblas_fill_lower, NN, rocblas_diagonal_non_unit,
+                                                 p, (int)N, &one, Ls[pass], p, pp, W, ldw, sW, nb));
+      }
+      // B_{j+1}^T = L1 L2
+      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, p, p, &one, L1, p, pp, L2, p, pp, &zero,
+                                               Bt + (int64_t)(jj + 1) * pp, p, (int64_t)k * pp, nb));
+    }
+    // a3: S-fraction
+    const int64_t sk = (int64_t)k * pp;
+    B_LAUNCH(diag_kernel, (int64_t)nb * pp, Hb, p, nb, G, sk, 0);
+    B_LAUNCH(diag_kernel, (int64_t)nb * pp, Hb, p, nb, Gi, sk, 1);
+    for (int jj = 0; jj < k; ++jj) {
+      double* Gj = G + jj * pp;
+      double* Gij = Gi + jj * pp;
+      double* Gamj = Gam + jj * pp;
+      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, p, p, &one, Gj, p, sk, Gj, p, sk, &zero, Gh + jj * pp, p, sk,
+                                               nb));
+      B_LAUNCH(symmetrize_kernel, (int64_t)nb * pp, Gh + jj * pp, p, sk, nb);
+      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, p, p, &one, A + jj * pp, p, sk, Gij, p, sk, &zero, T1, p, pp,
+                                               nb));
+      if (jj == 0) {
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, p, p, &one, Gij, p, sk, T1, p, pp, &zero, Gamj, p, sk, nb));
+      } else {
+        B_LAUNCH(copy_blocks_kernel, (int64_t)nb * pp, Gam + (jj - 1) * pp, sk, Gamj, sk, pp, nb, 1.0);
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, p, p, &one, Gij, p, sk, T1, p, pp, &mone, Gamj, p, sk, nb));
+      }
+      B_LAUNCH(symmetrize_kernel, (int64_t)nb * pp, Gamj, p, sk, nb);
+      if (jj + 1 == k) break;
+      // Cholesky of Gamma_j (must be SPD for j < k)
+      B_LAUNCH(copy_blocks_kernel, (int64_t)nb * pp, Gamj, sk, L1, pp, pp, nb, 1.0);
+      hipLaunchKernelGGL(cholesky_kernel, dim3(nb), dim3(256), 0, st, L1, p, pp, (const double*)nullptr, 0.0, flags);
+      B_TRY_HIP(hipGetLastError());
+      double* Gn = G + (jj + 1) * pp;
+      double* Gin = Gi + (jj + 1) * pp;
+      double* Btn = Bt + (jj + 1) * pp;
+      // G_{j+1} = -Gamma_j^{-1} G_j^{-T} B_{j+1}^T
+      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, p, p, &one, Gij, p, sk, Btn, p, sk, &zero, Gn, p, sk, nb));
+      B_TRY_BLAS(rocblas_dtrsm_strided_batched(h, rocblas_side_left, rocblas_fill_lower, NN, rocblas_diagonal_non_unit,
+                                               p, p, &mone, L1, p, pp, Gn, p, sk, nb));
+      B_TRY_BLAS(rocblas_dtrsm_strided_batched(h, rocblas_side_left, rocblas_fill_lower, TT, rocblas_diagonal_non_unit,
+                                               p, p, &one, L1, p, pp, Gn, p, sk, nb));
+      // G_{j+1}^{-1} = -B_{j+1}^{-T} G_j^T Gamma_j
+      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, p, p, &one, Gj, p, sk, Gamj, p, sk, &zero, Gin, p, sk, nb));
+      B_TRY_BLAS(rocblas_dtrsm_strided_batched(h, rocblas_side_left, rocblas_fill_lower, NN, rocblas_diagonal_non_unit,
+                                               p, p, &mone, Btn, p, sk, Gin, p, sk, nb));
+    }
+    // coefficients to the FP64 store [S][2][k][p][p] (symmetric: column-major = row-major)
+    B_LAUNCH(copy_blocks_kernel, (int64_t)nb * sk, Gam, sk, c->coef64_d + (int64_t)s0 * 2 * sk, 2 * sk, sk, nb, 1.0);
+    B_LAUNCH(copy_blocks_kernel, (int64_t)nb * sk, Gh, sk, c->coef64_d + (int64_t)s0 * 2 * sk + sk, 2 * sk, sk, nb, 1.0);
+
+    // a4: projections of the points of this batch
+    for (int mode = 0; mode < 2; ++mode) {
+      const std::vector<int32_t>& sub = mode == 0 ? src_sub : rec_sub;
+      const std::vector<int32_t>& loc = mode == 0 ? src_local : rec_local;
+      std::vector<int32_t> pb, pn, pid;
+      for (size_t i = 0; i < sub.size(); ++i)
+        if (sub[i] >= s0 && sub[i] < s0 + nb) {
+          pb.push_back(sub[i] - s0);
+          pn.push_back(loc[i]);
+          pid.push_back((int32_t)i);
+        }
+      const int npts = (int)pb.size();
+      if (npts == 0) continue;
+      std::vector<int32_t> packed;
+      packed.insert(packed.end(), pb.begin(), pb.end());
+      packed.insert(packed.end(), pn.begin(), pn.end());
+      packed.insert(packed.end(), pid.begin(), pid.end());
+      B_TRY_HIP(hipMemcpyAsync(pts, packed.data(), packed.size() * 4, hipMemcpyHostToDevice, st));
+      B_LAUNCH(project_points_kernel, (int64_t)npts * kp, Z, Sd, N, k, p, G, Gi, sk, pts, pts + npts, pts + 2 * npts,
+               npts, mode, mode == 0 ? c->src_vec64_d : c->rec_rows64_d);
+      B_TRY_HIP(hipStreamSynchronize(st));   // pts is reused
+    }
+    if (ic) {
+      const float* fields[2] = {u0_dev, v0_dev};
+      float* outs[2] = {c->U0_d, c->V0_d};
+      for (int fi = 0; fi < 2; ++fi) {
+        if (!fields[fi]) continue;
+        hipLaunchKernelGGL(project_field_kernel, dim3((nb * kp + 255) / 256), dim3(256), 0, st, g, Z, Sd, N, kp, nb,
+                           fields[fi], t.ncell[0], t.ncell[1], org_d, ybuf);
+        B_TRY_HIP(hipGetLastError());
+        B_LAUNCH(apply_g_kernel, (int64_t)nb * kp, ybuf, G, sk, k, p, P16, nb, s0, outs[fi]);
+      }
+    }
+    // breakdown flags of this batch
+    std::vector<int32_t> fl(nbmax + 1);
+    B_TRY_HIP(hipMemcpyAsync(fl.data(), flags, fl.size() * 4, hipMemcpyDeviceToHost, st));
+    B_TRY_HIP(hipStreamSynchronize(st));
+    if (fl[nbmax]) status = c->fail(SFM_EINVAL, "sound speed must be positive and finite at every node");
+    for (int b = 0; b < nb && status == SFM_OK; ++b)
+      if (fl[b])
+        status = c->fail(SFM_EBREAKDOWN, "subdomain " + std::to_string(s0 + b) +
+                                             ": block Lanczos breakdown or non-SPD Gamma_j");
+  }
+  cleanup();
+  if (status != SFM_OK) {
+    release_roms(c);
+    return status;
+  }
+  std::vector<double> sv;
+  if (nsrc > 0) {
+    sv.resize((size_t)nsrc * kp);
+    B_TRY_HIP(hipMemcpy(sv.data(), c->src_vec64_d, sv.size() * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  if (ic) {
+    // Both sides of a shared face projected the same trace; keep one copy so the shared
+    // boundary entries start (and stay) bit-identical.
+    for (int fi = 0; fi < 2; ++fi) {
+      float* arr = fi == 0 ? c->U0_d : c->V0_d;
+      B_LAUNCH(unify_ports_kernel, (int64_t)S * p, c->nbr_d, S, k, p, t.m, P16, arr);
+    }
+  }
+  rc = finalize_roms(c, Hall, src_sub, sv, rec_sub, st);
+  if (rc != SFM_OK) return rc;
+  c->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return SFM_OK;
 }

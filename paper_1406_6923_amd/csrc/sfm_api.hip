@@ -61,7 +61,7 @@ void sfm_ctx_s::dfree_all() {
 namespace sfm {
 
 // Drop every ROM-dependent buffer (before a new build or load).
-static void release_roms(sfm_ctx c) {
+void release_roms(sfm_ctx c) {
   void* bufs[] = {c->tiles_d, c->coef64_d, c->src_vec_d, c->src_vec64_d, c->src_off_d, c->src_ids_d,
                   c->sw_off_d, c->sw_q_d, c->sw_src_d, c->sw_w_d, c->rec_sub_d, c->rec_rows_d,
                   c->rec_rows64_d, c->U0_d, c->V0_d};
@@ -296,6 +296,7 @@ void sfm_destroy(sfm_ctx c) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  destroy_blas(c);
   c->dfree_all();
   (void)hipSetDevice(cur);
   delete c;

@@ -123,6 +123,15 @@ size_t step_lds_bytes(const StepParams& prm);
 hipError_t launch_norm2(const float* x, int64_t n, double* out, hipStream_t st);
 hipError_t launch_scale(const float* x, int64_t n, const double* num, float* y, hipStream_t st);
 
+sfm_status locate_points(sfm_ctx c, int32_t nsrc, const int32_t* src_ijk, int32_t nrec, const int32_t* rec_ijk,
+                         std::vector<int32_t>& src_sub, std::vector<int32_t>& src_local,
+                         std::vector<int32_t>& rec_sub, std::vector<int32_t>& rec_local);
+sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vector<int32_t>& src_sub,
+                         const std::vector<double>& src_vec_host, const std::vector<int32_t>& rec_sub,
+                         hipStream_t st);
+void release_roms(sfm_ctx c);
+void destroy_blas(sfm_ctx c);
+
 }  // namespace sfm
 
 // ----------------------------------------------------------------------------- context
@@ -170,6 +179,7 @@ struct sfm_ctx_s {
   int64_t n = 0;
   double dt_max = -1.0;
   double build_seconds = 0.0;
+  void* blas = nullptr;             // rocblas_handle of the ROM build (created on first use)
 
   sfm_status fail(sfm_status code, const std::string& msg) {
     err = msg;

@@ -29,6 +29,8 @@ def oracle_case(name: str = "small", sigma: float = np.inf):
                                           radius_range=(2.0, 8.0))
     else:
         c = cfg.velocity_model()
+    # The library takes the sound speed as FP32; the oracle starts from the same rounded values.
+    c = c.astype(np.float32).astype(np.float64)
     subs = subdomains.decompose(c, cfg.h, cfg.sub_cells, cfg.m)
     roms = rom.build_all(subs, cfg.k, sigma)
     src = cfg.sources()

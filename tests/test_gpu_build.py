@@ -1,0 +1,152 @@
+"""GPU parity of Stage 1 (device ROM build) against the FP64 oracle.
+
+The S-fraction coefficients, source projections and receiver rows are unique
+(independent of the Lanczos block rotations), so they are compared entry-wise
+with the oracle's; the Krylov bases are not compared.  Both sides compute in
+FP64, so agreement is limited only by the conditioning of the deep S-fraction
+levels: block j is held to 1e-8 * 10^(j/2) relative (max-norm of the block),
+the NtD maps at eight frequencies to 1e-5, projections to 1e-7, and traces of
+the GPU-built ROMs stepped on the GPU to 1e-5 against the oracle's ROMs stepped
+by the oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sfraction
+from tests.cases import oracle_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _build(name, **kw):
+    from paper_1406_6923_amd import sfm
+    cfg, c, subs, roms, cs = oracle_case(name)
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k, **kw)
+    vel = torch.tensor(c, dtype=torch.float32, device="cuda")
+    sfm.sfm_build_roms(h.ctx, vel, cfg.sources(), cfg.receivers())
+    return h, cfg, c, subs, roms, cs
+
+
+def _block_tol(j):
+    return 1e-8 * 10 ** (j / 2)
+
+
+@pytest.mark.parametrize("name", ["small", "ragged", "mid"])
+def test_build_coefficients_match_oracle(name):
+    from paper_1406_6923_amd import sfm
+    h, cfg, c, subs, roms, cs = _build(name)
+    gam, hat = sfm.sfm_export_roms(h.ctx)
+    worst = []
+    for s, r in enumerate(roms):
+        for j in range(cfg.k):
+            for got, ref in ((gam[s, j], r.sf.gamma[j]), (hat[s, j], r.sf.gamma_hat[j])):
+                err = np.abs(got - ref).max() / np.abs(ref).max()
+                worst.append((err, s, j))
+                assert err < _block_tol(j), (s, j, err)
+    print(f"{name}: worst block error {max(worst)}")
+    info = sfm.sfm_query(h.ctx)
+    print(f"{name}: build {info['build_seconds']:.3f} s for {info['n_subdomains']} subdomains")
+    h.close()
+
+
+@pytest.mark.parametrize("name", ["small", "mid"])
+def test_build_ntd_maps_match(name):
+    """NtD map of the GPU-built ROM vs the exact resolvent at 8 frequencies, compared with the oracle ROM."""
+    from paper_1406_6923_amd import sfm
+    h, cfg, c, subs, roms, cs = _build(name)
+    gam, hat = sfm.sfm_export_roms(h.ctx)
+    freqs = sfraction.ntd_frequencies(cfg.f_peak)
+    worst = 0.0
+    for s in (0, len(roms) - 1):
+        sf = sfraction.SFraction(gamma=list(gam[s]), gamma_hat=list(hat[s]), G=[])
+        for sv in freqs:
+            a = sfraction.ntd_continued_fraction(sf, sv)
+            b = sfraction.ntd_continued_fraction(roms[s].sf, sv)
+            worst = max(worst, np.linalg.norm(a - b) / np.linalg.norm(b))
+    print(f"{name}: NtD map GPU ROM vs oracle ROM, worst rel-F {worst:.2e}")
+    assert worst < 1e-5
+    h.close()
+
+
+@pytest.mark.parametrize("name", ["small", "ragged"])
+def test_build_projections_match_oracle(name):
+    from paper_1406_6923_amd import sfm
+    h, cfg, c, subs, roms, cs = _build(name)
+    src, rec = sfm.sfm_export_projections(h.ctx)
+    ref_src = np.stack([v for (_, v, _) in cs.sources])
+    ref_rec = np.stack([r for (_, r) in cs.receivers])
+    assert rel_l2(src, ref_src) < 1e-7
+    assert rel_l2(rec, ref_rec) < 1e-7
+    h.close()
+
+
+@pytest.mark.parametrize("name, nsteps", [("small", 500), ("mid", 150)])
+def test_end_to_end_traces(name, nsteps):
+    """GPU build + GPU leapfrog vs oracle build + oracle leapfrog (the whole hot path)."""
+    from paper_1406_6923_amd import sfm
+    h, cfg, c, subs, roms, cs = _build(name)
+    dt = 0.9 * cs.cfl_dt()
+    wav = W.ricker(cfg.f_peak, dt, nsteps)[:, None]
+    ref = cs.run(dt, wav)
+    tr = torch.zeros((len(cs.receivers), nsteps), dtype=torch.float32, device="cuda")
+    sfm.sfm_step(h.ctx, nsteps, dt, torch.tensor(wav, dtype=torch.float32, device="cuda"), tr)
+    torch.cuda.synchronize()
+    err = rel_l2(tr.cpu().numpy(), ref)
+    print(f"{name}: end-to-end traces rel-L2 = {err:.3e}")
+    assert err < 1e-5
+    h.close()
+
+
+def test_initial_conditions_projection_and_run():
+    """Step 1.4: U(0) = G Z^T M^{1/2} u0 and the leapfrog start U^{-1} = U(0) - dt U_t(0)."""
+    from paper_1406_6923_amd import sfm
+    cfg, c, subs, roms, cs = oracle_case("small")
+    nz, ny, nx = c.shape
+    l, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    u0 = np.exp(-((i - 12.0) ** 2 + (j - 20.0) ** 2 + (l - 10.0) ** 2) / 18.0)
+    v0 = 0.3 * np.exp(-((i - 20.0) ** 2 + (j - 9.0) ** 2 + (l - 22.0) ** 2) / 12.0) * 1500.0 / 10.0
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
+    dev = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")
+    sfm.sfm_build_roms(h.ctx, dev(c), None, cfg.receivers(), dev(u0), dev(v0))
+    U0 = []
+    V0 = []
+    for sd, r in zip(subs, roms):
+        sl = (slice(sd.origin[2], sd.origin[2] + sd.shape[0]), slice(sd.origin[1], sd.origin[1] + sd.shape[1]),
+              slice(sd.origin[0], sd.origin[0] + sd.shape[2]))
+        U0.append(r.project_state(sd, u0[sl]))
+        V0.append(r.project_state(sd, v0[sl]))
+    u, d, n = sfm.sfm_get_state(h.ctx)
+    assert n == 0 and not d.any()
+    assert rel_l2(u, np.stack(U0)) < 1e-6
+    dt = 0.9 * cs.cfl_dt()
+    sfm.sfm_reset_state(h.ctx, dt)
+    nsteps = 200
+    tr = torch.zeros((len(cs.receivers), nsteps), dtype=torch.float32, device="cuda")
+    sfm.sfm_step(h.ctx, nsteps, dt, None, tr)
+    torch.cuda.synchronize()
+    from oracle import coupled
+    cs0 = coupled.CoupledSystem(subs, roms, (), cfg.receivers())
+    U0c = cs0.scatter(cs0.gather(U0))
+    Upc = [a - dt * b for a, b in zip(U0c, cs0.scatter(cs0.gather(V0)))]
+    ref = cs0.run(dt, np.zeros((nsteps, 0)), U0=U0c, U_prev=Upc)
+    err = rel_l2(tr.cpu().numpy(), ref)
+    print(f"initial-condition run: traces rel-L2 = {err:.3e}")
+    assert err < 1e-5
+    h.close()
+
+
+def test_breakdown_is_reported():
+    """A homogeneous cube: the symmetric Krylov space is exhausted at k = 3 (oracle raises too)."""
+    from paper_1406_6923_amd import sfm
+    h = sfm.Sfm((4, 4, 4), (4, 4, 4), 10.0, 1, 3)
+    vel = torch.full((5, 5, 5), 2000.0, device="cuda")
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_build_roms(h.ctx, vel)
+    assert ei.value.status == sfm.SFM_EBREAKDOWN
+    vel[2, 2, 2] = -1.0
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_build_roms(h.ctx, vel)
+    assert ei.value.status in (sfm.SFM_EINVAL, sfm.SFM_EBREAKDOWN)
+    h.close()

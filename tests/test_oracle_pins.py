@@ -304,6 +304,16 @@ def test_breakdown_on_rank_deficient_basis():
         lanczos.lanczos_infinite(sd.A_plus(), F, 3)
 
 
+def test_homogeneous_cube_exhausts_krylov_space():
+    """Cube symmetry confines the block Krylov space of a homogeneous box: with 4^3 cells and one
+    patch per face the space stops growing at the third block (breakdown is an error)."""
+    c = np.full((5, 5, 5), 2000.0)
+    sd = subdomains.decompose(c, 10.0, (4, 4, 4), m=1)[0]
+    rom.build_rom(sd, 2)
+    with pytest.raises(lanczos.LanczosBreakdown):
+        rom.build_rom(sd, 3)
+
+
 def test_finite_shift_subspace_contains_resolvent_solutions():
     """Rational space: (A_+ + sigma)^{-1} F lies in span(Z) and F does too (Stage 1, K_n(sigma) with F added)."""
     c = tiny_box((4, 4, 4), seed=8)
