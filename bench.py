@@ -1,0 +1,251 @@
+"""Throughput of the S-fraction multiscale ROM time stepping on one MI355X.
+
+Runs the whole hot path on the 512^3 layered-plus-inclusions workload (16^3 subdomains
+of 32^3 cells, m = 16 boundary functions per face, k = 16 S-fraction levels, FP32):
+device ROM build for every subdomain (timed separately: ROM builds/s), the CFL step of
+the coupled ROM, W untimed warm-up steps and K timed leapfrog steps with all 65,536
+surface receivers recorded every step.  Prints one JSON line.
+
+value = fine-grid-equivalent cell updates per second:
+    N_cells * K * (dt_ROM / dt_fine) / wall,   dt_fine = 0.9 h / (sqrt(3) c_max)
+(the fine grid's leapfrog limit for the same medium), inputs resident in HBM.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "step_main_counters.json")
+STEP_SRC = os.path.join(ROOT, "paper_1406_6923_amd", "csrc", "step_kernels.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name: str) -> W.Workload:
+    if name == "large":
+        return W.CFG_LARGE
+    if name == "small":
+        return W.CFG_SMALL
+    if name.startswith("scaled"):
+        n = int(name[len("scaled"):] or 4)
+        return W.scaled_large((n, n, n), nsteps=2000)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def step_kernel_sha() -> str:
+    with open(STEP_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(launch_bytes_alg: float):
+    """HBM bytes per main-kernel launch from committed rocprofv3 counters, if they match this kernel."""
+    if not os.path.exists(COUNTERS):
+        return None, "no committed counters"
+    with open(COUNTERS) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_sha") != step_kernel_sha():
+        return None, "counters predate the current step kernel"
+    return rec.get("bytes_per_launch"), rec.get("note", "")
+
+
+def cpu_baseline(cfg: W.Workload, c_full: np.ndarray, dt_ratio: float, nsub=(2, 2, 1), nsteps=200):
+    """The FP64 oracle on a bounded sample of the same workload (host cores)."""
+    from oracle import coupled, rom, subdomains
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    sx, sy, sz = cfg.sub_cells
+    box = c_full[:nsub[2] * sz + 1, :nsub[1] * sy + 1, :nsub[0] * sx + 1].astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    subs = subdomains.decompose(box, cfg.h, cfg.sub_cells, cfg.m)
+    roms = rom.build_all(subs, cfg.k)
+    t_build = time.perf_counter() - t0
+    cs = coupled.CoupledSystem(subs, roms)
+    rng = np.random.default_rng(0)
+    U = cs.scatter(rng.standard_normal(cs._dof_layout()[1]) * 1e-6)
+    dt = 0.9 * cs.cfl_dt()
+    t0 = time.perf_counter()
+    cs.run(dt, np.zeros((nsteps, 0)), U0=U, U_prev=U)
+    t_step = time.perf_counter() - t0
+    cells = nsub[0] * sx * nsub[1] * sy * nsub[2] * sz
+    return {
+        "value": cells * nsteps * dt_ratio / t_step / 1e9,
+        "unit": "Gcell-updates/s (fine-grid-equivalent)",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"{nsub[0]}x{nsub[1]}x{nsub[2]} subdomains ({cells} cells) cut from the same velocity model, "
+                   f"same subdomain size and ROM sizes; oracle ROM build of those subdomains "
+                   f"({len(subs) / t_build:.3f} builds/s, not in value) then {nsteps} FP64 leapfrog steps "
+                   f"of the coupled ROMs timed; dt ratio taken from the GPU run"),
+        "builds_per_s": len(subs) / t_build,
+        "step_seconds": t_step,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="large")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--build-batch", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-receivers", action="store_true")
+    ap.add_argument("--cfl-iters", type=int, default=200)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, copy a buffer of this size 3 times (reference kernel for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU split of this "
+              f"method is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1406_6923_amd import sfm
+
+    cfg = workload(args.workload)
+    prec = sfm.SFM_PREC_FP32 if args.precision == "fp32" else sfm.SFM_PREC_BF16_FP32ACC
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+
+    log(f"[bench] workload {cfg.name}: generating velocity {cfg.nodes}")
+    t0 = time.perf_counter()
+    c = cfg.velocity_model()
+    c_max = float(c.max())
+    vel = torch.from_numpy(c.astype(np.float32)).to(dev)
+    log(f"[bench] velocity ready ({time.perf_counter() - t0:.1f} s), c in [{c.min():.0f}, {c_max:.0f}]")
+    src = cfg.sources()
+    rec = cfg.receivers()
+
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k, precision=prec, build_batch=args.build_batch)
+    info = h.info()
+    S = info["n_subdomains"]
+    log(f"[bench] building {S} ROMs (p = {info['p']}, k = {info['k']}) on the GPU")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sfm.sfm_build_roms(h.ctx, vel, src, rec, stream=stream)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    log(f"[bench] build {t_build:.2f} s ({S / t_build:.1f} builds/s)")
+
+    dt_max = sfm.sfm_cfl_dt(h.ctx, args.cfl_iters, stream=stream)
+    dt = 0.9 * dt_max
+    dt_fine = 0.9 * cfg.h / (math.sqrt(3.0) * c_max)
+    ratio = dt / dt_fine
+    log(f"[bench] dt_ROM = {dt:.4e} s, dt_fine = {dt_fine:.4e} s, ratio {ratio:.3f}")
+
+    nrec = 0 if args.no_receivers else len(rec)
+    total = args.warmup + args.steps
+    wav = torch.tensor(W.ricker(cfg.f_peak, dt, total)[:, None], dtype=torch.float32, device=dev)
+    traces = torch.zeros((max(nrec, 1), max(args.steps, 1)), dtype=torch.float32, device=dev) if nrec else None
+    warm_tr = torch.zeros((max(nrec, 1), max(args.warmup, 1)), dtype=torch.float32, device=dev) if nrec else None
+
+    if args.warmup:
+        sfm.sfm_step(h.ctx, args.warmup, dt, wav[:args.warmup].contiguous(), warm_tr, stream=stream)
+    torch.cuda.synchronize()
+    log(f"[bench] warm-up {args.warmup} steps done; timing {args.steps} steps")
+    t0 = time.perf_counter()
+    sfm.sfm_step(h.ctx, args.steps, dt, wav[args.warmup:].contiguous(), traces, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"[bench] timed {args.steps} steps: {wall:.3f} s")
+
+    # Per-kernel device times inside the same kind of steps (separate, event-instrumented pass).
+    nprof = min(args.steps, 200)
+    sfm.sfm_set_timing(h.ctx, True)
+    sfm.sfm_step(h.ctx, nprof, dt, wav[args.warmup:args.warmup + nprof].contiguous(),
+                 traces[:, :nprof].contiguous() if traces is not None else None, stream=stream)
+    info = h.info()
+    sfm.sfm_set_timing(h.ctx, False)
+    main_ms = info["timed_main_ms"] / max(info["timed_steps"], 1)
+    face_ms = info["timed_face_ms"] / max(info["timed_steps"], 1)
+    rec_ms = info["timed_record_ms"] / max(info["timed_steps"], 1)
+    k, p = info["k"], info["p"]
+    elem = 4 if prec == sfm.SFM_PREC_FP32 else 2
+    bytes_per_sub = (2 * k - 1) * p * (p + 1) // 2 * elem + 3 * k * p * 4
+    launch_bytes = S * bytes_per_sub
+    achieved = launch_bytes / (main_ms * 1e-3) / 1e9
+    traffic, traffic_note = traffic_from_profiles(launch_bytes)
+    log(f"[bench] main kernel {main_ms:.4f} ms ({achieved:.0f} GB/s algorithmic), face {face_ms:.4f} ms, "
+        f"receivers {rec_ms:.4f} ms")
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    finite = bool(torch.isfinite(traces).all().item()) if traces is not None else True
+    ms_per_step = wall / max(args.steps, 1) * 1e3
+    value = cfg.n_cells * args.steps * ratio / wall / 1e9
+    out = {
+        "metric": "fine-grid-equiv Gcell-updates/s",
+        "value": value,
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == sfm.SFM_PREC_FP32 else "bf16-coef/f32-acc",
+        "data": "synthetic",
+        "config": {
+            "workload": cfg.name,
+            "ncell": list(cfg.ncell), "sub_cells": list(cfg.sub_cells), "subdomains": S,
+            "m": cfg.m, "k": cfg.k, "p": p, "h": cfg.h, "receivers": nrec, "sources": len(src),
+            "velocity": "seeded 20-layer model (1500-4500 m/s) + 50 spheres (+-30%)",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "step_main_kernel",
+            "algorithmic_bytes_per_launch": launch_bytes,
+            "avg_launch_ms": main_ms,
+            "traffic_note": traffic_note,
+        },
+        "rom_builds_per_s": S / t_build,
+        "build_seconds": t_build,
+        "dt_rom": dt,
+        "dt_fine": dt_fine,
+        "dt_ratio": ratio,
+        "raw_gcell_per_s": cfg.n_cells * args.steps / wall / 1e9,
+        "face_kernel_ms": face_ms,
+        "receiver_kernel_ms": rec_ms,
+        "traces_finite": finite,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline: oracle on a 2x2x1-subdomain sample")
+        out["cpu_baseline"] = cpu_baseline(cfg, c, ratio)
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -80,6 +80,10 @@ typedef struct {
   int64_t coef_bytes_algorithmic;  /* (2k-1) p (p+1)/2 words per subdomain in the stored precision */
   int64_t state_bytes;       /* one [S][k][p] FP32 state array */
   double build_seconds;      /* wall time of the last sfm_build_roms (device work included) */
+  int64_t timed_steps;       /* steps launched by sfm_step while timing was enabled */
+  double timed_main_ms;      /* summed device time of the step's main kernel over those steps */
+  double timed_face_ms;      /* summed device time of the boundary-layer kernel */
+  double timed_record_ms;    /* summed device time of the receiver kernel */
 } sfm_info;
 
 /* Validate cfg and allocate a context on the current device.
@@ -165,6 +169,12 @@ sfm_status sfm_record_receivers(sfm_ctx ctx, float* out_dev, void* stream);
  * (device, float [S][k][p] each; shared boundary entries of u must agree on both sides).
  * Errors: SFM_ESTATE. */
 sfm_status sfm_apply_operator(sfm_ctx ctx, const float* u_dev, float* a_dev, void* stream);
+
+/* Enable (1) or disable (0) per-kernel device timing inside sfm_step: hipEvents are recorded
+ * around every kernel of every step on the caller's stream and summed into the timed_* fields
+ * of sfm_info (sfm_query synchronizes the stream work and reads them).  Enabling resets the
+ * sums.  Adds two event records per kernel launch. */
+sfm_status sfm_set_timing(sfm_ctx ctx, int32_t enable);
 
 /* Checkpoint: copy U^n and the increment U^n - U^{n-1} (host, float [S][k][p] each; either
  * may be NULL) and n.  The increment is the stored leapfrog variable, so set_state of

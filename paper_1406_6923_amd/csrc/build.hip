@@ -22,6 +22,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -484,6 +486,8 @@ extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t ns
   const double one = 1.0, zero = 0.0, mone = -1.0;
   const rocblas_operation NN = rocblas_operation_none, TT = rocblas_operation_transpose;
 
+  const char* vb = std::getenv("SFM_VERBOSE");
+  const bool verbose = vb && vb[0] && vb[0] != '0';
   sfm_status status = SFM_OK;
   for (int s0 = 0; s0 < S && status == SFM_OK; s0 += nbmax) {
     const int nb = std::min(nbmax, S - s0);
@@ -647,6 +651,11 @@ extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t ns
     std::vector<int32_t> fl(nbmax + 1);
     B_TRY_HIP(hipMemcpyAsync(fl.data(), flags, fl.size() * 4, hipMemcpyDeviceToHost, st));
     B_TRY_HIP(hipStreamSynchronize(st));
+    if (verbose) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+      std::fprintf(stderr, "[sfm] ROM build: subdomains %d..%d of %d done, %.2f s\n", s0, s0 + nb - 1, S, el);
+      std::fflush(stderr);
+    }
     if (fl[nbmax]) status = c->fail(SFM_EINVAL, "sound speed must be positive and finite at every node");
     for (int b = 0; b < nb && status == SFM_OK; ++b)
       if (fl[b])

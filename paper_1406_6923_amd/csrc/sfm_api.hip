@@ -296,6 +296,7 @@ void sfm_destroy(sfm_ctx c) {
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   destroy_blas(c);
   c->dfree_all();
   (void)hipSetDevice(cur);
@@ -304,8 +305,51 @@ void sfm_destroy(sfm_ctx c) {
 
 const char* sfm_last_error(sfm_ctx c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
-sfm_status sfm_query(sfm_ctx c, sfm_info* out) {
+namespace sfm {
+// Fold recorded step events into the timing sums (synchronizes on the last event).
+static sfm_status drain_timing(sfm_ctx c) {
+  if (c->ev.empty()) return SFM_OK;
+  SFM_TRY_HIP(c, hipEventSynchronize(c->ev.back()));
+  for (size_t s = 0; s < c->ev_rec.size(); ++s) {
+    hipEvent_t* e = &c->ev[4 * s];
+    float ms = 0.f;
+    for (int q = 0; q < 3; ++q) {
+      SFM_TRY_HIP(c, hipEventElapsedTime(&ms, e[q], e[q + 1]));
+      c->timed_ms[q] += ms;
+    }
+    c->timed_steps++;
+  }
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  c->ev_rec.clear();
+  return SFM_OK;
+}
+}  // namespace sfm
+
+extern "C" sfm_status sfm_set_timing(sfm_ctx c, int32_t enable) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  sfm_status rc = drain_timing(c);
+  if (rc != SFM_OK) return rc;
+  c->timing = enable != 0;
+  if (c->timing) {
+    c->timed_steps = 0;
+    c->timed_ms[0] = c->timed_ms[1] = c->timed_ms[2] = 0.0;
+  }
+  return SFM_OK;
+}
+
+extern "C" sfm_status sfm_query(sfm_ctx c, sfm_info* out) {
   if (!c || !out) return SFM_EINVAL;
+  if (c->timing || !c->ev.empty()) {
+    sfm_status rc = drain_timing(c);
+    if (rc != SFM_OK) return rc;
+  }
+  out->timed_steps = c->timed_steps;
+  out->timed_main_ms = c->timed_ms[0];
+  out->timed_face_ms = c->timed_ms[1];
+  out->timed_record_ms = c->timed_ms[2];
   const Topology& t = c->topo;
   out->n_subdomains = t.S;
   out->p = t.p;
@@ -504,12 +548,25 @@ sfm_status sfm_step(sfm_ctx c, int32_t nsteps, double dt, const float* wavelet_d
   r.ld = ld;
   for (int32_t i = 0; i < nsteps; ++i) {
     prm.step = f.step = i;
+    const bool rec = traces_dev && c->nrec > 0;
+    hipEvent_t* e = nullptr;
+    if (c->timing) {
+      const size_t base = c->ev.size();
+      c->ev.resize(base + 4);
+      for (int q = 0; q < 4; ++q) SFM_TRY_HIP(c, hipEventCreate(&c->ev[base + q]));
+      c->ev_rec.push_back(rec ? 1 : 0);
+      e = &c->ev[base];
+      SFM_TRY_HIP(c, hipEventRecord(e[0], st));
+    }
     SFM_TRY_HIP(c, launch_step_main(prm, c->cfg.precision, st));
+    if (e) SFM_TRY_HIP(c, hipEventRecord(e[1], st));
     SFM_TRY_HIP(c, launch_step_face(f, st));
-    if (traces_dev && c->nrec > 0) {
+    if (e) SFM_TRY_HIP(c, hipEventRecord(e[2], st));
+    if (rec) {
       r.col = i;
       SFM_TRY_HIP(c, launch_record(r, st));
     }
+    if (e) SFM_TRY_HIP(c, hipEventRecord(e[3], st));
   }
   c->n += nsteps;
   return SFM_OK;

@@ -180,6 +180,12 @@ struct sfm_ctx_s {
   double dt_max = -1.0;
   double build_seconds = 0.0;
   void* blas = nullptr;             // rocblas_handle of the ROM build (created on first use)
+  // per-kernel timing of sfm_step (events recorded on the caller's stream)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;       // 4 events per timed step: main start, face start, record start, end
+  std::vector<uint8_t> ev_rec;      // whether the record kernel ran in that step
+  int64_t timed_steps = 0;
+  double timed_ms[3] = {0, 0, 0};
 
   sfm_status fail(sfm_status code, const std::string& msg) {
     err = msg;

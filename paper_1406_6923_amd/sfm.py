@@ -41,7 +41,9 @@ class sfm_info(ctypes.Structure):
                 ("nsrc", ctypes.c_int32), ("nrec", ctypes.c_int32), ("has_roms", ctypes.c_int32),
                 ("steps_done", ctypes.c_int64), ("coef_bytes", ctypes.c_int64),
                 ("coef_bytes_algorithmic", ctypes.c_int64), ("state_bytes", ctypes.c_int64),
-                ("build_seconds", ctypes.c_double)]
+                ("build_seconds", ctypes.c_double), ("timed_steps", ctypes.c_int64),
+                ("timed_main_ms", ctypes.c_double), ("timed_face_ms", ctypes.c_double),
+                ("timed_record_ms", ctypes.c_double)]
 
 
 class SfmError(RuntimeError):
@@ -71,6 +73,7 @@ SIGNATURES = {
     "sfm_step": (_I32, [_VP, _I32, _D, _VP, _VP, _I64, _VP]),
     "sfm_record_receivers": (_I32, [_VP, _VP, _VP]),
     "sfm_apply_operator": (_I32, [_VP, _VP, _VP, _VP]),
+    "sfm_set_timing": (_I32, [_VP, _I32]),
     "sfm_get_state": (_I32, [_VP, _VP, _VP, ctypes.POINTER(_I64)]),
     "sfm_set_state": (_I32, [_VP, _VP, _VP, _I64]),
 }
@@ -213,6 +216,10 @@ def sfm_record_receivers(ctx: int, out, stream=None) -> None:
 
 def sfm_apply_operator(ctx: int, u, a, stream=None) -> None:
     _check(ctx, load_library().sfm_apply_operator(ctx, _dev(u), _dev(a), _stream(stream)))
+
+
+def sfm_set_timing(ctx: int, enable: bool) -> None:
+    _check(ctx, load_library().sfm_set_timing(ctx, 1 if enable else 0))
 
 
 def sfm_get_state(ctx: int):

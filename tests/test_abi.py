@@ -35,7 +35,7 @@ def test_struct_layouts_match_header():
     # sfm_config: 3 + 3 int32, a double (8-aligned), 4 int32 -> 48 bytes
     assert ctypes.sizeof(sfm.sfm_config) == 48
     assert sfm.sfm_config.h.offset == 24
-    assert ctypes.sizeof(sfm.sfm_info) == 64
+    assert ctypes.sizeof(sfm.sfm_info) == 96
 
 
 @pytest.mark.parametrize("kwargs, fragment", [
