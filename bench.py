@@ -63,7 +63,7 @@ def traffic_from_profiles(launch_bytes_alg: float):
     return rec.get("bytes_per_launch"), rec.get("note", "")
 
 
-def cpu_baseline(cfg: W.Workload, c_full: np.ndarray, dt_ratio: float, nsub=(2, 2, 1), nsteps=200):
+def cpu_baseline(cfg: W.Workload, c_full: np.ndarray, dt_ratio: float, nsub=(1, 1, 1), nsteps=2000):
     """The FP64 oracle on a bounded sample of the same workload (host cores)."""
     from oracle import coupled, rom, subdomains
     try:
@@ -110,8 +110,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-receivers", action="store_true")
     ap.add_argument("--cfl-iters", type=int, default=200)
-    ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="after timing, copy a buffer of this size 3 times (reference kernel for HBM counters)")
+    ap.add_argument("--copy-probe-mib", type=int, default=2048,
+                    help="size of the device copy timed as the practical HBM bandwidth reference")
+    ap.add_argument("--no-comparators", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU split of this "
@@ -163,17 +164,14 @@ def main():
         sfm.sfm_step(h.ctx, args.warmup, dt, wav[:args.warmup].contiguous(), warm_tr, stream=stream)
     torch.cuda.synchronize()
     log(f"[bench] warm-up {args.warmup} steps done; timing {args.steps} steps")
+    # Per-kernel device times are taken live in the timed region: the library records a
+    # hipEvent pair around every kernel of every step on the stream it launches on.
+    sfm.sfm_set_timing(h.ctx, True)
     t0 = time.perf_counter()
     sfm.sfm_step(h.ctx, args.steps, dt, wav[args.warmup:].contiguous(), traces, stream=stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"[bench] timed {args.steps} steps: {wall:.3f} s")
-
-    # Per-kernel device times inside the same kind of steps (separate, event-instrumented pass).
-    nprof = min(args.steps, 200)
-    sfm.sfm_set_timing(h.ctx, True)
-    sfm.sfm_step(h.ctx, nprof, dt, wav[args.warmup:args.warmup + nprof].contiguous(),
-                 traces[:, :nprof].contiguous() if traces is not None else None, stream=stream)
     info = h.info()
     sfm.sfm_set_timing(h.ctx, False)
     main_ms = info["timed_main_ms"] / max(info["timed_steps"], 1)
@@ -188,15 +186,44 @@ def main():
     log(f"[bench] main kernel {main_ms:.4f} ms ({achieved:.0f} GB/s algorithmic), face {face_ms:.4f} ms, "
         f"receivers {rec_ms:.4f} ms")
 
-    if args.copy_probe_mib:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
     finite = bool(torch.isfinite(traces).all().item()) if traces is not None else True
+
+    # Measured device-copy bandwidth (reads + writes) as the practical HBM reference.
+    n = max(args.copy_probe_mib, 2048) * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 4 * n * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    log(f"[bench] device copy {copy_gbs:.0f} GB/s")
+
+    comparators = {}
+    if not args.no_comparators:
+        # fine-grid FDTD on the same grid at its own stability limit
+        nf = min(args.steps, 200)
+        wf = torch.tensor(W.ricker(cfg.f_peak, dt_fine, nf)[:, None], dtype=torch.float32, device=dev)
+        secs = sfm.sfm_fdtd_run(cfg.ncell, cfg.h, vel, dt_fine, nf, src, wf, None, None, stream=stream)
+        fdtd_rate = cfg.n_cells * nf / secs / 1e9
+        log(f"[bench] fine-grid FDTD: {secs / nf * 1e3:.4f} ms/step, {fdtd_rate:.1f} Gcell-updates/s")
+        # plain per-subdomain ROM stepping (same math, one launch per subdomain per step)
+        npl = 3
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sfm.sfm_step_plain(h.ctx, npl, dt, wav[:npl].contiguous(), stream=stream)
+        torch.cuda.synchronize()
+        tpl = (time.perf_counter() - t1) / npl
+        plain_rate = cfg.n_cells * ratio / tpl / 1e9
+        log(f"[bench] plain per-subdomain stepping: {tpl * 1e3:.2f} ms/step")
+        comparators = {
+            "fine_fdtd_gcell_per_s": fdtd_rate, "fine_fdtd_ms_per_step": secs / nf * 1e3,
+            "plain_rom_gcell_per_s": plain_rate, "plain_rom_ms_per_step": tpl * 1e3,
+        }
     ms_per_step = wall / max(args.steps, 1) * 1e3
     value = cfg.n_cells * args.steps * ratio / wall / 1e9
     out = {
@@ -239,9 +266,15 @@ def main():
         "face_kernel_ms": face_ms,
         "receiver_kernel_ms": rec_ms,
         "traces_finite": finite,
+        "copy_gbs": copy_gbs,
+        "frac_of_copy": achieved / copy_gbs,
     }
+    if comparators:
+        comparators["speedup_vs_fine_fdtd"] = value / comparators["fine_fdtd_gcell_per_s"]
+        comparators["speedup_vs_plain_rom"] = value / comparators["plain_rom_gcell_per_s"]
+        out["comparators"] = comparators
     if not args.no_cpu_baseline:
-        log("[bench] CPU baseline: oracle on a 2x2x1-subdomain sample")
+        log("[bench] CPU baseline: oracle on a one-subdomain sample")
         out["cpu_baseline"] = cpu_baseline(cfg, c, ratio)
     h.close()
     print(json.dumps(out), flush=True)

@@ -184,6 +184,32 @@ sfm_status sfm_get_state(sfm_ctx ctx, float* u_now, float* u_incr, int64_t* n);
 /* Restore a checkpoint written by sfm_get_state (NULL arrays mean zero).  Synchronizes. */
 sfm_status sfm_set_state(sfm_ctx ctx, const float* u_now, const float* u_incr, int64_t n);
 
+/* ------------------------------------------------------------------------------------------
+ * Comparators on the same GPU (baselines, not the method's hot path)
+ * ------------------------------------------------------------------------------------------ */
+
+/* Leapfrog on the reference fine grid itself (the scheme the ROMs reduce; Introduction, eq.
+ * "wave"): M (u^{n+1} - 2u^n + u^{n-1}) / dt^2 = -K u^n + sum_s e_s f_s(t_n) with the node-based
+ * 7-point operator and mirrored (Neumann) outer boundary, zero initial state, FP32.
+ *   ncell      host, int32[3] cells (nodes = ncell + 1)
+ *   vel_dev    device, float nodal sound speed [nz+1][ny+1][nx+1]
+ *   wavelet_dev device, float [nsteps][nsrc]
+ *   traces_dev device, float [nrec][ld] (may be NULL): u^{n+1} at the receivers after step n
+ *   seconds    host, wall time of the step loop (may be NULL)
+ * Allocates its own work arrays (3 nodal FP32 fields) for the duration of the call and
+ * synchronizes.  Errors: SFM_EINVAL, SFM_EHIP (message in sfm_fdtd_last_error()). */
+sfm_status sfm_fdtd_run(const int32_t* ncell, double h, const float* vel_dev, double dt, int32_t nsteps,
+                        int32_t nsrc, const int32_t* src_ijk, const float* wavelet_dev, int32_t nrec,
+                        const int32_t* rec_ijk, float* traces_dev, int64_t ld, double* seconds, void* stream);
+
+/* Message of the last failing sfm_fdtd_run on this thread. */
+const char* sfm_fdtd_last_error(void);
+
+/* The same coupled leapfrog as sfm_step (eqs. "intrtstep", "bdrytstep"), done plainly: one kernel
+ * launch per subdomain per step, full row-major FP32 p x p blocks (allocated on first use,
+ * (2k-1) p^2 words per subdomain), one thread per row, no receivers.  Advances the context state. */
+sfm_status sfm_step_plain(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet_dev, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,12 +64,16 @@ namespace sfm {
 void release_roms(sfm_ctx c) {
   void* bufs[] = {c->tiles_d, c->coef64_d, c->src_vec_d, c->src_vec64_d, c->src_off_d, c->src_ids_d,
                   c->sw_off_d, c->sw_q_d, c->sw_src_d, c->sw_w_d, c->rec_sub_d, c->rec_rows_d,
-                  c->rec_rows64_d, c->U0_d, c->V0_d};
+                  c->rec_rows64_d, c->U0_d, c->V0_d, c->rec_perm_d, c->rs_off_d, c->hist_slot_d,
+                  c->hist_d, c->plain_blocks_d};
   for (void* b : bufs) c->dfree(b);
   c->tiles_d = nullptr; c->coef64_d = nullptr; c->src_vec_d = nullptr; c->src_vec64_d = nullptr;
   c->src_off_d = nullptr; c->src_ids_d = nullptr; c->sw_off_d = nullptr; c->sw_q_d = nullptr;
   c->sw_src_d = nullptr; c->sw_w_d = nullptr; c->rec_sub_d = nullptr; c->rec_rows_d = nullptr;
-  c->rec_rows64_d = nullptr; c->U0_d = nullptr; c->V0_d = nullptr;
+  c->rec_rows64_d = nullptr; c->U0_d = nullptr; c->V0_d = nullptr; c->rec_perm_d = nullptr;
+  c->rs_off_d = nullptr; c->hist_slot_d = nullptr; c->hist_d = nullptr; c->plain_blocks_d = nullptr;
+  c->n_rs = 0;
+  c->rs_max = 0;
   c->has_roms = false;
   c->nsrc = c->nrec = 0;
   c->src_sub.clear();
@@ -205,14 +209,45 @@ sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vec
     if (e != hipSuccess) return c->fail(SFM_ENOMEM, "source buffers: out of device memory");
     SFM_TRY_HIP(c, launch_pad_rows(c->src_vec64_d, (int64_t)nsrc * k, p, P16, c->src_vec_d, st));
   }
-  // receivers
+  // receivers, sorted by subdomain (stable), with the per-subdomain history ring
   const int nrec = (int)rec_sub.size();
   c->nrec = nrec;
   if (nrec > 0) {
-    c->rec_sub_d = alloc_copy(c, rec_sub, &e);
+    std::vector<int32_t> perm(nrec);
+    for (int i = 0; i < nrec; ++i) perm[i] = i;
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return rec_sub[a] < rec_sub[b]; });
+    std::vector<int32_t> sub_sorted(nrec), slot_of(S, -1), rs_off;
+    for (int i = 0; i < nrec; ++i) {
+      const int s = rec_sub[perm[i]];
+      sub_sorted[i] = s;
+      if (slot_of[s] < 0) {
+        slot_of[s] = (int)rs_off.size();
+        rs_off.push_back(i);
+      }
+    }
+    rs_off.push_back(nrec);
+    c->n_rs = (int)rs_off.size() - 1;
+    for (int q = 0; q < c->n_rs; ++q) c->rs_max = std::max(c->rs_max, rs_off[q + 1] - rs_off[q]);
+    c->rec_sub_d = alloc_copy(c, sub_sorted, &e);
+    c->rec_perm_d = alloc_copy(c, perm, &e);
+    c->rs_off_d = alloc_copy(c, rs_off, &e);
+    c->hist_slot_d = alloc_copy(c, slot_of, &e);
+    const size_t hist_bytes = (size_t)kHistWindow * c->n_rs * k * P16 * sizeof(float);
+    c->hist_d = static_cast<float*>(c->dalloc(hist_bytes, &e));
     c->rec_rows_d = static_cast<float*>(c->dalloc((size_t)nrec * k * P16 * sizeof(float), &e));
     if (e != hipSuccess) return c->fail(SFM_ENOMEM, "receiver buffers: out of device memory");
-    SFM_TRY_HIP(c, launch_pad_rows(c->rec_rows64_d, (int64_t)nrec * k, p, P16, c->rec_rows_d, st));
+    SFM_TRY_HIP(c, hipMemsetAsync(c->hist_d, 0, hist_bytes, st));   // padding entries stay zero
+    // FP64 rows (caller order) -> FP32 padded rows (sorted order)
+    std::vector<int32_t> inv(nrec);
+    for (int i = 0; i < nrec; ++i) inv[i] = perm[i];
+    int32_t* gather_d = alloc_copy(c, inv, &e);
+    double* tmp = static_cast<double*>(c->dalloc((size_t)nrec * k * p * sizeof(double), &e));
+    if (e != hipSuccess) return c->fail(SFM_ENOMEM, "receiver buffers: out of device memory");
+    SFM_TRY_HIP(c, launch_gather_rows(c->rec_rows64_d, gather_d, nrec, (int64_t)k * p, tmp, st));
+    SFM_TRY_HIP(c, launch_pad_rows(tmp, (int64_t)nrec * k, p, P16, c->rec_rows_d, st));
+    SFM_TRY_HIP(c, hipStreamSynchronize(st));
+    c->dfree(tmp);
+    c->dfree(gather_d);
   }
   const int64_t nstate = (int64_t)S * k * P16;
   SFM_TRY_HIP(c, hipMemsetAsync(c->exch_d, 0, (size_t)S * P16 * sizeof(float), st));
@@ -537,18 +572,27 @@ sfm_status sfm_step(sfm_ctx c, int32_t nsteps, double dt, const float* wavelet_d
     f.sw_src = c->sw_src_d;
     f.sw_w = c->sw_w_d;
   }
-  RecParams r{};
-  r.nrec = c->nrec;
+  RecWindowParams r{};
+  r.n_rs = c->n_rs;
   r.k = c->topo.k;
   r.P16 = c->geo.P16;
-  r.rec_sub = c->rec_sub_d;
+  r.rs_off = c->rs_off_d;
+  r.perm = c->rec_perm_d;
   r.rows = c->rec_rows_d;
-  r.U = c->U_d;
-  r.out = traces_dev;
+  r.hist = c->hist_d;
+  r.traces = traces_dev;
   r.ld = ld;
+  const bool recording = traces_dev && c->nrec > 0;
+  if (recording) {
+    prm.hist = f.hist = c->hist_d;
+    prm.hist_slot = f.hist_slot = c->hist_slot_d;
+  }
+  const int64_t slot_stride = (int64_t)c->n_rs * c->topo.k * c->geo.P16;
   for (int32_t i = 0; i < nsteps; ++i) {
     prm.step = f.step = i;
-    const bool rec = traces_dev && c->nrec > 0;
+    const int t = i % kHistWindow;
+    prm.hist_off = f.hist_off = t * slot_stride;
+    const bool rec = recording && (t == kHistWindow - 1 || i + 1 == nsteps);
     hipEvent_t* e = nullptr;
     if (c->timing) {
       const size_t base = c->ev.size();
@@ -563,8 +607,9 @@ sfm_status sfm_step(sfm_ctx c, int32_t nsteps, double dt, const float* wavelet_d
     SFM_TRY_HIP(c, launch_step_face(f, st));
     if (e) SFM_TRY_HIP(c, hipEventRecord(e[2], st));
     if (rec) {
-      r.col = i;
-      SFM_TRY_HIP(c, launch_record(r, st));
+      r.w = t + 1;
+      r.col0 = i - t;
+      SFM_TRY_HIP(c, launch_record_window(r, st, c->rs_max));
     }
     if (e) SFM_TRY_HIP(c, hipEventRecord(e[3], st));
   }
@@ -583,6 +628,7 @@ sfm_status sfm_record_receivers(sfm_ctx c, float* out_dev, void* stream) {
   r.k = c->topo.k;
   r.P16 = c->geo.P16;
   r.rec_sub = c->rec_sub_d;
+  r.perm = c->rec_perm_d;
   r.rows = c->rec_rows_d;
   r.U = c->U_d;
   r.out = out_dev;

@@ -81,6 +81,9 @@ struct StepParams {
   int64_t step;
   float dt2;
   int mode;                   // 0 = leapfrog step, 1 = apply operator
+  float* hist;                // receiver-subdomain state history [Tw][n_rs][k][P16] (or null)
+  const int32_t* hist_slot;   // [S] history slot of each subdomain, -1 if it holds no receiver
+  int64_t hist_off;           // offset of this step's time slot in hist
 };
 
 struct FaceParams {
@@ -100,26 +103,47 @@ struct FaceParams {
   float* D;
   float* Aout;
   int mode;
+  float* hist;
+  const int32_t* hist_slot;
+  int64_t hist_off;
 };
 
+// Receivers are stored sorted by subdomain (CSR over the receiver subdomains); perm maps the
+// sorted position back to the caller's receiver index.
 struct RecParams {
   int nrec, k, P16;
-  const int32_t* rec_sub;
-  const float* rows;          // [nrec][k][P16]
+  const int32_t* rec_sub;     // [nrec] subdomain of each sorted receiver
+  const int32_t* perm;        // [nrec] caller index of each sorted receiver
+  const float* rows;          // [nrec][k][P16] (sorted)
   const float* U;             // [S][k][P16]
-  float* out;                 // out[r * ld + col]
+  float* out;                 // out[perm[r] * ld + col]
   int64_t ld, col;
 };
+
+// traces[perm[r]][col0 + t] = rows[r] . hist[t][slot(r)] for t < w (one GEMM per window).
+struct RecWindowParams {
+  int n_rs, k, P16, w;
+  const int32_t* rs_off;      // [n_rs + 1] CSR of sorted receivers per receiver subdomain
+  const int32_t* perm;
+  const float* rows;
+  const float* hist;          // [Tw][n_rs][k][P16]
+  float* traces;
+  int64_t ld, col0;
+};
+constexpr int kHistWindow = 64;
 
 hipError_t launch_step_main(const StepParams& prm, int precision, hipStream_t st);
 hipError_t launch_step_face(const FaceParams& prm, hipStream_t st);
 hipError_t launch_record(const RecParams& prm, hipStream_t st);
+hipError_t launch_record_window(const RecWindowParams& prm, hipStream_t st, int max_per_slot);
 hipError_t launch_pack(const double* blocks, int64_t nblocks_total, int blocks_per_sub_in,
                        int k, int p, const TileGeometry& geo, const int32_t* wrow,
                        const int32_t* wcol, void* tiles, int precision, int S, hipStream_t st);
 hipError_t launch_pad_rows(const double* src, int64_t nrows, int p, int P16, float* dst,
                            hipStream_t st);
 size_t step_lds_bytes(const StepParams& prm);
+hipError_t launch_gather_rows(const double* src, const int32_t* idx, int n, int64_t width, double* dst,
+                              hipStream_t st);
 hipError_t launch_norm2(const float* x, int64_t n, double* out, hipStream_t st);
 hipError_t launch_scale(const float* x, int64_t n, const double* num, float* y, hipStream_t st);
 
@@ -167,8 +191,15 @@ struct sfm_ctx_s {
   float* sw_w_d = nullptr;
   // receivers
   int nrec = 0;
-  int32_t* rec_sub_d = nullptr;
-  float* rec_rows_d = nullptr;      // [nrec][k][P16]
+  int32_t* rec_sub_d = nullptr;     // sorted receivers: subdomain
+  int32_t* rec_perm_d = nullptr;    // sorted receivers: caller index
+  float* rec_rows_d = nullptr;      // [nrec][k][P16], sorted by subdomain
+  int n_rs = 0;                     // subdomains that hold receivers
+  int rs_max = 0;                   // most receivers in one subdomain
+  int32_t* rs_off_d = nullptr;      // [n_rs + 1]
+  int32_t* hist_slot_d = nullptr;   // [S]
+  float* hist_d = nullptr;          // [kHistWindow][n_rs][k][P16]
+  float* plain_blocks_d = nullptr;  // comparator only: full FP32 blocks [S][2k-1][p][p]
   double* rec_rows64_d = nullptr;   // [nrec][k][p]
   // scratch
   double* red_d = nullptr;          // reduction scratch

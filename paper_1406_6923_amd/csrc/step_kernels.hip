@@ -227,6 +227,7 @@ __global__ __launch_bounds__(kStepThreads) void step_main_kernel(StepParams prm)
   __syncthreads();
   run_phase<T>(tiles + (size_t)k * prm.words_per_block, k - 1, prm, xs, vstride, part, tid);
   __syncthreads();
+  const int slot = (prm.mode == 0 && prm.hist) ? prm.hist_slot[s] : -1;
   const int s0 = prm.src_off ? prm.src_off[s] : 0;
   const int s1 = prm.src_off ? prm.src_off[s + 1] : 0;
   for (int e = tid; e < (k - 1) * P; e += kStepThreads) {
@@ -239,8 +240,10 @@ __global__ __launch_bounds__(kStepThreads) void step_main_kernel(StepParams prm)
     const size_t idx = sbase + (size_t)(b + 1) * P + i;
     if (prm.mode == 0) {
       const float d = fmaf(prm.dt2, a, prm.D[idx]);
+      const float un = prm.U[idx] + d;
       prm.D[idx] = d;
-      prm.U[idx] = prm.U[idx] + d;
+      prm.U[idx] = un;
+      if (slot >= 0) prm.hist[prm.hist_off + ((size_t)slot * k + b + 1) * P + i] = un;
     } else {
       prm.Aout[idx] = a;
     }
@@ -265,26 +268,16 @@ __global__ void step_face_kernel(FaceParams prm) {
   const size_t u = (size_t)s * prm.k * prm.P16 + q;
   if (prm.mode == 0) {
     const float d = fmaf(prm.dt2, a, prm.D[u]);
+    const float un = prm.U[u] + d;
     prm.D[u] = d;
-    prm.U[u] = prm.U[u] + d;
+    prm.U[u] = un;
+    if (prm.hist) {
+      const int slot = prm.hist_slot[s];
+      if (slot >= 0) prm.hist[prm.hist_off + (size_t)slot * prm.k * prm.P16 + q] = un;
+    }
   } else {
     prm.Aout[u] = a;
   }
-}
-
-// One wave per receiver: out = rows[r] . U[rec_sub[r]].
-__global__ __launch_bounds__(256) void record_kernel(RecParams prm) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r = blockIdx.x * 4 + wave;
-  if (r >= prm.nrec) return;
-  const int n = prm.k * prm.P16;
-  const float* row = prm.rows + (size_t)r * n;
-  const float* u = prm.U + (size_t)prm.rec_sub[r] * n;
-  float acc = 0.f;
-  for (int e = lane; e < n; e += 64) acc = fmaf(row[e], u[e], acc);
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-  if (lane == 0) prm.out[(size_t)r * prm.ld + prm.col] = acc;
 }
 
 // Pack full FP64 blocks into the tile stream: out[s][b][w] = blk(s, b)[wrow[w]][wcol[w]].
@@ -311,6 +304,16 @@ __global__ void pack_kernel(const double* __restrict__ blocks, int k, int p, int
     } else {
       out[idx] = __bfloat16_as_ushort(__float2bfloat16((float)v));
     }
+  }
+}
+
+// dst[i] = src[idx[i]] for rows of `width` doubles.
+__global__ void gather_rows_kernel(const double* __restrict__ src, const int32_t* __restrict__ idx, int n,
+                                   int64_t width, double* __restrict__ dst) {
+  const int64_t total = (int64_t)n * width;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = q / width;
+    dst[q] = src[(int64_t)idx[i] * width + (q - i * width)];
   }
 }
 
@@ -369,12 +372,6 @@ hipError_t launch_step_face(const FaceParams& prm, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_record(const RecParams& prm, hipStream_t st) {
-  if (prm.nrec == 0) return hipSuccess;
-  hipLaunchKernelGGL(record_kernel, dim3((prm.nrec + 3) / 4), dim3(256), 0, st, prm);
-  return hipGetLastError();
-}
-
 hipError_t launch_pack(const double* blocks, int64_t /*nblocks_total*/, int /*blocks_per_sub_in*/, int k, int p,
                        const TileGeometry& geo, const int32_t* wrow, const int32_t* wcol, void* tiles,
                        int precision, int S, hipStream_t st) {
@@ -397,6 +394,15 @@ hipError_t launch_pad_rows(const double* src, int64_t nrows, int p, int P16, flo
   const int64_t total = nrows * P16;
   const unsigned grid = (unsigned)std::min<int64_t>((total + threads - 1) / threads, 65536);
   hipLaunchKernelGGL(pad_rows_kernel, dim3(grid), dim3(threads), 0, st, src, nrows, p, P16, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const double* src, const int32_t* idx, int n, int64_t width, double* dst,
+                              hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int threads = 256;
+  const unsigned grid = (unsigned)std::min<int64_t>((n * width + threads - 1) / threads, 65536);
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(grid), dim3(threads), 0, st, src, idx, n, width, dst);
   return hipGetLastError();
 }
 

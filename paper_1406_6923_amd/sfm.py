@@ -76,6 +76,9 @@ SIGNATURES = {
     "sfm_set_timing": (_I32, [_VP, _I32]),
     "sfm_get_state": (_I32, [_VP, _VP, _VP, ctypes.POINTER(_I64)]),
     "sfm_set_state": (_I32, [_VP, _VP, _VP, _I64]),
+    "sfm_fdtd_run": (_I32, [_VP, _D, _VP, _D, _I32, _I32, _VP, _VP, _I32, _VP, _VP, _I64, ctypes.POINTER(_D), _VP]),
+    "sfm_fdtd_last_error": (ctypes.c_char_p, []),
+    "sfm_step_plain": (_I32, [_VP, _I32, _D, _VP, _VP]),
 }
 
 _lib = None
@@ -236,6 +239,27 @@ def sfm_set_state(ctx: int, u_now=None, u_incr=None, n: int = 0) -> None:
     u = _host(u_now, np.float32)
     d = _host(u_incr, np.float32)
     _check(ctx, load_library().sfm_set_state(ctx, _ptr(u), _ptr(d), int(n)))
+
+
+def sfm_fdtd_run(ncell, h: float, vel, dt: float, nsteps: int, src_ijk=None, wavelet=None, rec_ijk=None,
+                 traces=None, stream=None) -> float:
+    """Fine-grid FDTD comparator; returns the wall time of the step loop in seconds."""
+    lib = load_library()
+    nc = _host(np.asarray(ncell), np.int32)
+    src = _host(np.zeros((0, 3)) if src_ijk is None else src_ijk, np.int32).reshape(-1, 3)
+    rec = _host(np.zeros((0, 3)) if rec_ijk is None else rec_ijk, np.int32).reshape(-1, 3)
+    ld = traces.shape[-1] if traces is not None else 0
+    secs = _D()
+    status = lib.sfm_fdtd_run(_ptr(nc), float(h), _dev(vel), float(dt), int(nsteps), len(src), _ptr(src),
+                              _dev(wavelet), len(rec), _ptr(rec), _dev(traces), int(ld), ctypes.byref(secs),
+                              _stream(stream))
+    if status != SFM_OK:
+        raise SfmError(status, lib.sfm_fdtd_last_error().decode())
+    return secs.value
+
+
+def sfm_step_plain(ctx: int, nsteps: int, dt: float, wavelet=None, stream=None) -> None:
+    _check(ctx, load_library().sfm_step_plain(ctx, int(nsteps), float(dt), _dev(wavelet), _stream(stream)))
 
 
 class Sfm:

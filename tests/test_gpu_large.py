@@ -1,0 +1,143 @@
+"""The 512^3 layered workload at full size (16^3 subdomains of 33^3 nodes, m = 16, k = 16), in the
+launch configuration bench.py times: device build of all 4096 ROMs, then sampled parity.
+
+The oracle cannot build 4096 ROMs, so it builds two sampled subdomains (a corner one that holds
+receivers and an interior one) from the same FP32 velocity and checks, entry-wise:
+  * their S-fraction coefficients (the block tolerance of test_gpu_build);
+  * their receiver rows;
+  * one application of the step operator, on every entry that depends only on that subdomain
+    (interior layers j >= 2, and outer-face entries of the boundary layer, eq. "bdrytstep" with
+    one side), to a random consistent state (2e-4) and to the projection of a smooth field (2e-5).
+Properties that hold at any size are checked on the whole run: finite traces, bit-identical
+shared boundary entries on both sides of every face, and bit-reproducible reruns.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import coupled, rom, subdomains
+from tests.cases import rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def large():
+    from paper_1406_6923_amd import sfm
+    cfg = W.CFG_LARGE
+    c = cfg.velocity_model().astype(np.float32)
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
+    vel = torch.from_numpy(c).cuda()
+    sfm.sfm_build_roms(h.ctx, vel, cfg.sources(), cfg.receivers())
+    del vel
+    yield cfg, c.astype(np.float64), h
+    h.close()
+
+
+def _oracle_sub(cfg, c, s):
+    bx, by, bz = s % 16, (s // 16) % 16, s // 256
+    sx, sy, sz = cfg.sub_cells
+    box = c[bz * sz: bz * sz + sz + 1, by * sy: by * sy + sy + 1, bx * sx: bx * sx + sx + 1]
+    # decompose the box alone, then give it the neighbour pattern of its position in the full grid
+    sd = subdomains.decompose(box, cfg.h, cfg.sub_cells, cfg.m)[0]
+    nb = []
+    for f in range(6):
+        d, side = divmod(f, 2)
+        b = [bx, by, bz]
+        b[d] += 1 if side else -1
+        nb.append(-1 if not (0 <= b[d] < 16) else (b[2] * 16 + b[1]) * 16 + b[0])
+    E, keys = subdomains._basis(sd.shape, cfg.sub_cells, (bx, by, bz), (16, 16, 16), nb, cfg.h, cfg.m,
+                                *subdomains.factor_patches(cfg.m), "patches", sd.origin, cfg.nodes, s)
+    sd.E, sd.port_keys, sd.neighbours = E, keys, tuple(nb)
+    sd.origin = (bx * sx, by * sy, bz * sz)
+    sd.index = s
+    return sd, rom.build_rom(sd, cfg.k), nb
+
+
+@pytest.mark.parametrize("s", [0, 16 * 16 * 8 + 16 * 7 + 9])
+def test_sampled_subdomains_match_oracle(large, s):
+    from paper_1406_6923_amd import sfm
+    cfg, c, h = large
+    sd, r, nb = _oracle_sub(cfg, c, s)
+    gam, hat = sfm.sfm_export_roms(h.ctx)
+    for j in range(cfg.k):
+        tol = 1e-8 * 10 ** (j / 2)
+        assert np.abs(gam[s, j] - r.sf.gamma[j]).max() / np.abs(r.sf.gamma[j]).max() < tol
+        assert np.abs(hat[s, j] - r.sf.gamma_hat[j]).max() / np.abs(r.sf.gamma_hat[j]).max() < tol
+    # receiver rows of this subdomain
+    rec = cfg.receivers()
+    _, rows = sfm.sfm_export_projections(h.ctx)
+    owner = [i for i, x in enumerate(rec) if sd.contains(x) and
+             all((x[d] // cfg.sub_cells[d]) - (1 if x[d] % cfg.sub_cells[d] == 0 and x[d] > 0 else 0)
+                 == (sd.origin[d] // cfg.sub_cells[d]) for d in range(3))]
+    for i in owner[:32]:
+        ref = r.receiver_row(sd, sd.local_index(rec[i]))
+        assert rel_l2(rows[i], ref) < 1e-6
+    # one operator application: entries that depend only on subdomain s.  A random state excites
+    # the stiffest ROM modes, where the FP32-stored deep levels (Gamma-hat_k condition up to 1e10)
+    # amplify rounding; a smooth wavefield is the physically relevant input.
+    S, k, p, m = 4096, cfg.k, 6 * cfg.m, cfg.m
+    rng = np.random.default_rng(3)
+    random_state = rng.standard_normal((S, k, p)).astype(np.float32)
+    l, jj, i = np.meshgrid(np.arange(sd.shape[0]), np.arange(sd.shape[1]), np.arange(sd.shape[2]), indexing="ij")
+    smooth = (np.cos(2 * np.pi * (i + 3) / 40.0) * np.cos(2 * np.pi * (jj + 5) / 55.0) * np.cos(2 * np.pi * l / 47.0)
+              + 0.5 * np.exp(-((i - 12.0) ** 2 + (jj - 20.0) ** 2 + (l - 17.0) ** 2) / 50.0))
+    wave_state = np.zeros((S, k, p), dtype=np.float32)
+    wave_state[s] = r.project_state(sd, smooth).astype(np.float32)
+    for name, U, tol in (("random", random_state, 2e-4), ("smooth", wave_state, 2e-5)):
+        # shared boundary entries consistent on both sides: the lower-index side's value wins,
+        # except that subdomain s keeps its own (its neighbours take it)
+        for a in range(S):
+            bx, by, bz = a % 16, (a // 16) % 16, a // 256
+            for f in range(6):
+                d, side = divmod(f, 2)
+                b = [bx, by, bz]
+                b[d] += 1 if side else -1
+                if 0 <= b[d] < 16:
+                    nbi = (b[2] * 16 + b[1]) * 16 + b[0]
+                    if nbi == s or (nbi < a and a != s):
+                        U[a, 0, f * m:(f + 1) * m] = U[nbi, 0, (f ^ 1) * m:((f ^ 1) + 1) * m]
+        u_d = torch.from_numpy(U).cuda()
+        a_d = torch.empty_like(u_d)
+        sfm.sfm_apply_operator(h.ctx, u_d, a_d)
+        got = a_d[s].cpu().numpy()
+        Us = U[s].astype(np.float64)
+        dU = np.vstack([Us[1:], np.zeros((1, p))]) - Us
+        phi = np.stack([r.sf.gamma[j] @ dU[j] for j in range(k)])
+        ref_int = np.stack([r.sf.gamma_hat[j] @ (phi[j] - phi[j - 1]) for j in range(1, k)])
+        err_int = rel_l2(got[1:], ref_int)
+        H = np.diag(r.sf.gamma_hat[0])
+        outer = [q for q in range(p) if nb[q // m] < 0]
+        print(f"subdomain {s}, {name} state: interior layers rel-L2 {err_int:.2e}; {len(outer)} outer-face entries")
+        assert err_int < tol
+        if outer:
+            assert rel_l2(got[0][outer], H[outer] * phi[0][outer]) < tol
+
+
+def test_full_size_run_properties(large):
+    from paper_1406_6923_amd import sfm
+    cfg, c, h = large
+    dt = 0.9 * sfm.sfm_cfl_dt(h.ctx, 100)
+    nsteps = 300
+    wav = torch.tensor(W.ricker(cfg.f_peak, dt, nsteps)[:, None], dtype=torch.float32, device="cuda")
+    nrec = len(cfg.receivers())
+    runs = []
+    for _ in range(2):
+        sfm.sfm_set_state(h.ctx, None, None, 0)
+        tr = torch.zeros((nrec, nsteps), dtype=torch.float32, device="cuda")
+        sfm.sfm_step(h.ctx, nsteps, dt, wav, tr)
+        runs.append(tr.cpu().numpy())
+    assert np.isfinite(runs[0]).all() and np.abs(runs[0]).max() > 0
+    assert np.array_equal(runs[0], runs[1])
+    u, d, n = sfm.sfm_get_state(h.ctx)
+    m = cfg.m
+    for a in range(0, 4096, 7):
+        bx, by, bz = a % 16, (a // 16) % 16, a // 256
+        for f in range(6):
+            dd, side = divmod(f, 2)
+            b = [bx, by, bz]
+            b[dd] += 1 if side else -1
+            if 0 <= b[dd] < 16:
+                nbi = (b[2] * 16 + b[1]) * 16 + b[0]
+                assert np.array_equal(u[a, 0, f * m:(f + 1) * m], u[nbi, 0, (f ^ 1) * m:((f ^ 1) + 1) * m])

@@ -70,11 +70,12 @@ def test_traces_match_oracle(name, nsteps):
     err = rel_l2(got, ref)
     print(f"{name}: traces rel-L2 = {err:.3e}")
     assert err < 1e-3
-    # the last sample equals an explicit record of the final state
+    # the last sample (windowed product) equals an explicit record of the final state (dot
+    # products in another order)
     out = torch.empty(len(cs.receivers), dtype=torch.float32, device="cuda")
     sfm.sfm_record_receivers(h.ctx, out)
     torch.cuda.synchronize()
-    assert np.array_equal(out.cpu().numpy(), got[:, -1])
+    np.testing.assert_allclose(out.cpu().numpy(), got[:, -1], rtol=1e-5, atol=1e-6 * np.abs(got).max())
     h.close()
 
 
