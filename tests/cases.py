@@ -4,9 +4,10 @@ from __future__ import annotations
 import functools
 
 import numpy as np
+import scipy.sparse as sp
 
 import workloads as W
-from oracle import coupled, grid, rom, subdomains
+from oracle import coupled, grid, lanczos, rom, sfraction, subdomains
 
 
 @functools.lru_cache(maxsize=4)
@@ -59,3 +60,40 @@ def rel_l2(a, b) -> float:
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def perturbation_profile(sd, r, delta: float = 1e-15, seed: int = 1) -> np.ndarray:
+    """Per-level reproducibility of the S-fraction coefficients in FP64.
+
+    The subdomain operator's entries are perturbed by a symmetric relative noise of size delta
+    and the oracle ROM is rebuilt; the returned array holds, for each level j, the largest
+    relative change (max-norm) of Gamma_j and Gamma-hat_j.  Deep levels of a polynomial-Krylov
+    S-fraction respond to rounding-size perturbations of the operator by orders of magnitude
+    more than shallow ones, so two correct FP64 builds can only agree to about this level."""
+    A = sd.A_plus().tocoo()
+    rng = np.random.default_rng(seed)
+    upper = A.row <= A.col
+    noise = np.zeros(A.nnz)
+    noise[upper] = delta * rng.standard_normal(int(upper.sum()))
+    Ap = sp.coo_matrix((A.data * (1 + noise), (A.row, A.col)), shape=A.shape).tocsr()
+    Ap = (sp.triu(Ap) + sp.triu(Ap, 1).T).tocsr()
+    sf = sfraction.sfraction(lanczos.lanczos_infinite(Ap, sd.F(), r.k))
+    out = np.empty(r.k)
+    for j in range(r.k):
+        out[j] = max(np.abs(sf.gamma[j] - r.sf.gamma[j]).max() / np.abs(r.sf.gamma[j]).max(),
+                     np.abs(sf.gamma_hat[j] - r.sf.gamma_hat[j]).max() / np.abs(r.sf.gamma_hat[j]).max())
+    return out
+
+
+def level_tolerance(profile: np.ndarray) -> np.ndarray:
+    """Coefficient tolerance per level: 30 times the FP64 reproducibility, at least 1e-14."""
+    return np.maximum(30.0 * profile, 1e-14)
+
+
+@functools.lru_cache(maxsize=4)
+def case_level_tolerance(name: str) -> np.ndarray:
+    """Per-level tolerance of a named case: the worst perturbation response over two subdomains."""
+    cfg, c, subs, roms, cs = oracle_case(name)
+    picks = sorted({0, len(subs) - 1})
+    prof = np.max([perturbation_profile(subs[i], roms[i]) for i in picks], axis=0)
+    return level_tolerance(prof)

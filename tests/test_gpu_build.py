@@ -3,8 +3,9 @@
 The S-fraction coefficients, source projections and receiver rows are unique
 (independent of the Lanczos block rotations), so they are compared entry-wise
 with the oracle's; the Krylov bases are not compared.  Both sides compute in
-FP64, so agreement is limited only by the conditioning of the deep S-fraction
-levels: block j is held to 1e-8 * 10^(j/2) relative (max-norm of the block),
+FP64, so agreement is limited only by the FP64 reproducibility of the deep S-fraction
+levels: block j is held to 30 times the relative change the oracle's own level j shows
+when the subdomain operator is perturbed by 1e-15 (tests.cases.perturbation_profile),
 the NtD maps at eight frequencies to 1e-5, projections to 1e-7, and traces of
 the GPU-built ROMs stepped on the GPU to 1e-5 against the oracle's ROMs stepped
 by the oracle.
@@ -14,7 +15,7 @@ import pytest
 
 import workloads as W
 from oracle import sfraction
-from tests.cases import oracle_case, rel_l2
+from tests.cases import case_level_tolerance, oracle_case, rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -29,23 +30,23 @@ def _build(name, **kw):
     return h, cfg, c, subs, roms, cs
 
 
-def _block_tol(j):
-    return 1e-8 * 10 ** (j / 2)
-
-
 @pytest.mark.parametrize("name", ["small", "ragged", "mid"])
 def test_build_coefficients_match_oracle(name):
     from paper_1406_6923_amd import sfm
     h, cfg, c, subs, roms, cs = _build(name)
     gam, hat = sfm.sfm_export_roms(h.ctx)
+    tol = case_level_tolerance(name)
+    print(f"{name}: level tolerances " + " ".join(f"{x:.1e}" for x in tol))
     worst = []
     for s, r in enumerate(roms):
         for j in range(cfg.k):
             for got, ref in ((gam[s, j], r.sf.gamma[j]), (hat[s, j], r.sf.gamma_hat[j])):
                 err = np.abs(got - ref).max() / np.abs(ref).max()
                 worst.append((err, s, j))
-                assert err < _block_tol(j), (s, j, err)
+                assert err < tol[j], (s, j, err, tol[j])
     print(f"{name}: worst block error {max(worst)}")
+    per_level = [max(e for e, _, j in worst if j == jj) for jj in range(cfg.k)]
+    print(f"{name}: worst error per level " + " ".join(f"{e:.1e}" for e in per_level))
     info = sfm.sfm_query(h.ctx)
     print(f"{name}: build {info['build_seconds']:.3f} s for {info['n_subdomains']} subdomains")
     h.close()

@@ -3,11 +3,15 @@ launch configuration bench.py times: device build of all 4096 ROMs, then sampled
 
 The oracle cannot build 4096 ROMs, so it builds two sampled subdomains (a corner one that holds
 receivers and an interior one) from the same FP32 velocity and checks, entry-wise:
-  * their S-fraction coefficients (the block tolerance of test_gpu_build);
+  * their S-fraction coefficients, per level within 30x the oracle's own response to a 1e-15
+    perturbation of the subdomain operator (as in test_gpu_build);
   * their receiver rows;
   * one application of the step operator, on every entry that depends only on that subdomain
     (interior layers j >= 2, and outer-face entries of the boundary layer, eq. "bdrytstep" with
-    one side), to a random consistent state (2e-4) and to the projection of a smooth field (2e-5).
+    one side), to a random consistent state and to the projection of a smooth field, held
+    elementwise to a forward error bound derived from FP32 storage and dot-product rounding plus
+    the per-level FP64 coefficient tolerance (a plain relative bar would measure the cancellation
+    in the acceleration of a smooth field, not the kernel).
 Properties that hold at any size are checked on the whole run: finite traces, bit-identical
 shared boundary entries on both sides of every face, and bit-reproducible reruns.
 """
@@ -16,7 +20,7 @@ import pytest
 
 import workloads as W
 from oracle import coupled, rom, subdomains
-from tests.cases import rel_l2
+from tests.cases import level_tolerance, perturbation_profile, rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -61,10 +65,10 @@ def test_sampled_subdomains_match_oracle(large, s):
     cfg, c, h = large
     sd, r, nb = _oracle_sub(cfg, c, s)
     gam, hat = sfm.sfm_export_roms(h.ctx)
+    tau = level_tolerance(perturbation_profile(sd, r))
     for j in range(cfg.k):
-        tol = 1e-8 * 10 ** (j / 2)
-        assert np.abs(gam[s, j] - r.sf.gamma[j]).max() / np.abs(r.sf.gamma[j]).max() < tol
-        assert np.abs(hat[s, j] - r.sf.gamma_hat[j]).max() / np.abs(r.sf.gamma_hat[j]).max() < tol
+        assert np.abs(gam[s, j] - r.sf.gamma[j]).max() / np.abs(r.sf.gamma[j]).max() < tau[j], j
+        assert np.abs(hat[s, j] - r.sf.gamma_hat[j]).max() / np.abs(r.sf.gamma_hat[j]).max() < tau[j], j
     # receiver rows of this subdomain
     rec = cfg.receivers()
     _, rows = sfm.sfm_export_projections(h.ctx)
@@ -85,7 +89,7 @@ def test_sampled_subdomains_match_oracle(large, s):
               + 0.5 * np.exp(-((i - 12.0) ** 2 + (jj - 20.0) ** 2 + (l - 17.0) ** 2) / 50.0))
     wave_state = np.zeros((S, k, p), dtype=np.float32)
     wave_state[s] = r.project_state(sd, smooth).astype(np.float32)
-    for name, U, tol in (("random", random_state, 2e-4), ("smooth", wave_state, 2e-5)):
+    for name, U in (("random", random_state), ("smooth", wave_state)):
         # shared boundary entries consistent on both sides: the lower-index side's value wins,
         # except that subdomain s keeps its own (its neighbours take it)
         for a in range(S):
@@ -106,13 +110,41 @@ def test_sampled_subdomains_match_oracle(large, s):
         dU = np.vstack([Us[1:], np.zeros((1, p))]) - Us
         phi = np.stack([r.sf.gamma[j] @ dU[j] for j in range(k)])
         ref_int = np.stack([r.sf.gamma_hat[j] @ (phi[j] - phi[j - 1]) for j in range(1, k)])
-        err_int = rel_l2(got[1:], ref_int)
+        bound = _forward_error_bound(r, dU, phi, p, tau)
+        err = np.abs(got[1:] - ref_int)
+        ratio = float(np.max(err / bound))
         H = np.diag(r.sf.gamma_hat[0])
         outer = [q for q in range(p) if nb[q // m] < 0]
-        print(f"subdomain {s}, {name} state: interior layers rel-L2 {err_int:.2e}; {len(outer)} outer-face entries")
-        assert err_int < tol
+        print(f"subdomain {s}, {name} state: interior layers rel-L2 {rel_l2(got[1:], ref_int):.2e}, "
+              f"max error / bound {ratio:.3f}; {len(outer)} outer-face entries")
+        assert ratio < 1.0
         if outer:
-            assert rel_l2(got[0][outer], H[outer] * phi[0][outer]) < tol
+            b0 = H[outer] * (((p + 2) * U32 + tau[0]) * (np.abs(r.sf.gamma[0]) @ np.abs(dU[0]))[outer]) + U32 * np.abs(H[outer] * phi[0][outer])
+            assert np.all(np.abs(got[0][outer] - H[outer] * phi[0][outer]) <= 2 * b0 + 1e-30)
+
+
+U32 = 2.0 ** -24
+
+
+def _forward_error_bound(r, dU, phi, p, tau):
+    """Elementwise first-order bound, times 2, on |a_gpu - a_oracle| for the interior layers.
+
+    The kernel rounds the stored coefficients to FP32 (relative u = 2^-24), forms
+    x_j = U_{j+1} - U_j (one rounding), phi_j = Gamma_j x_j and a_j = Gamma-hat_j (phi_j - phi_{j-1})
+    as FP32 dot products of length p (gamma_p <= p u); its coefficients come from its own FP64
+    build, within tau[j] of the oracle's.  Propagating these perturbations gives the bound."""
+    k = len(r.sf.gamma)
+    dphi = []
+    for j in range(k):
+        G = np.abs(r.sf.gamma[j])
+        dphi.append(((p + 2) * U32 + tau[j]) * (G @ np.abs(dU[j])) + U32 * np.abs(phi[j]))
+    out = []
+    for j in range(1, k):
+        y = phi[j] - phi[j - 1]
+        dy = dphi[j] + dphi[j - 1] + U32 * np.abs(y)
+        Gh = np.abs(r.sf.gamma_hat[j])
+        out.append(Gh @ dy + ((p + 1) * U32 + tau[j]) * (Gh @ np.abs(y)))
+    return 2.0 * np.stack(out) + 1e-30
 
 
 def test_full_size_run_properties(large):
