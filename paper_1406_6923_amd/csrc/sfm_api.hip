@@ -296,7 +296,7 @@ sfm_status sfm_create(const sfm_config* cfg, sfm_ctx* out) {
   }
   c->cfg = *cfg;
   c->topo = topo;
-  c->geo.init(topo.p);
+  c->geo.init(topo.p, cfg->precision == SFM_PREC_BF16_FP32ACC ? 2 : 4);
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     g_create_error = "hipGetDevice failed";
@@ -496,6 +496,7 @@ static StepParams make_step_params(sfm_ctx c) {
   prm.words_per_block = g.words_per_block;
   prm.words_per_sub = (int64_t)(2 * c->topo.k - 1) * g.words_per_block;
   std::memcpy(prm.job_off, g.job_off, sizeof(prm.job_off));
+  prm.tail_off = g.tail_off;
   prm.S = c->topo.S;
   prm.k = c->topo.k;
   prm.P16 = g.P16;

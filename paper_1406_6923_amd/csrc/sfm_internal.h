@@ -8,16 +8,19 @@
 // rows 16I.. and columns 16J.., lane i (0..15) holds W_t[i] = A(16I + i, 16J + (i + t) mod 16).
 //   * off-diagonal tile (I < J): t = 0..15, 256 words, stored [v][lane][4] with t = 4v + e
 //     (FP32) or [v][lane][8] (BF16), so each load instruction of a 16-lane row is contiguous;
-//   * diagonal tile (I = J): t = 0..8 (t = 8 repeats the half-diagonal once), 144 words,
-//     stored [t 0..3][lane][4], [t 4..7][lane][4], [t = 8][lane] (FP32) or
-//     [t 0..7][lane][8], [t = 8][lane] (BF16).
+//   * diagonal tile (I = J): t = 0..7 in the tile, 128 words, stored [t 0..3][lane][4],
+//     [t 4..7][lane][4] (FP32) or [t 0..7][lane][8] (BF16); its t = 8 half-diagonal (16 lanes,
+//     each entry present twice) sits in the block's tail, [I][lane], after all tiles, padded
+//     to whole 128-byte lines.  Every tile then starts on a 128-byte line of HBM: a stream
+//     whose rows start 64 bytes into a line reads about 10% slower.
 // The symmetric product y = A x then needs each stored word once: W_t[i] multiplies
 // x_J[i + t] into y_I[i], and, rotated by t lanes, x_I[c - t] into y_J[c] (DPP row
 // rotations inside a 16-lane row).
 // Tiles are grouped into "jobs" of one or two tile strips: job g covers strip g and
 // strip nt - 1 - g (diagonal tile first, then the tiles to its right), so every job of
 // an even-nt block holds nt + 1 tiles.  A block is the concatenation of its jobs and a
-// subdomain stream is [Gamma_1 .. Gamma_k, Gamma-hat_2 .. Gamma-hat_k].
+// subdomain stream is [Gamma_1 .. Gamma_k, Gamma-hat_2 .. Gamma-hat_k], each block being
+// [job 0 .. job npairs-1][tail].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,18 +34,21 @@
 namespace sfm {
 
 constexpr int kTile = 16;
-constexpr int kDiagWords = 144;
+constexpr int kDiagWords = 128;        // t = 0..7 of a diagonal tile
+constexpr int kHalfDiagWords = 16;     // t = 8 of a diagonal tile, in the block tail
 constexpr int kOffWords = 256;
+constexpr int kLineBytes = 128;
 constexpr int kStepThreads = 256;      // 16 rows of 16 lanes per subdomain work-group
 constexpr int kMaxNt = 16;             // p <= 256
 
 // Geometry of the tile stream of one block.
 struct TileGeometry {
   int p = 0, P16 = 0, nt = 0, npairs = 0, nslots = 0;
-  int64_t words_per_block = 0;
+  int64_t words_per_block = 0;           // in stored elements (4 bytes FP32, 2 bytes BF16)
   int32_t job_off[kMaxNt / 2 + 1] = {};   // word offset of job g inside a block
+  int32_t tail_off = 0;                   // word offset of the half-diagonals [nt][16]
 
-  void init(int p_);
+  void init(int p_, int elem_bytes);
   // (row, col) of every stored word of a block, in stream order (row, col may be >= p: padding).
   void word_map(std::vector<int32_t>& rows, std::vector<int32_t>& cols, bool bf16) const;
 };
@@ -67,6 +73,7 @@ struct StepParams {
   int64_t words_per_sub;
   int64_t words_per_block;
   int32_t job_off[kMaxNt / 2 + 1];
+  int32_t tail_off;
   int S, k, P16, nt, npairs, nslots;
   float* U;                   // [S][k][P16] state U^n (updated in place for layers 2..k)
   float* D;                   // [S][k][P16] increment U^n - U^{n-1} (step mode)

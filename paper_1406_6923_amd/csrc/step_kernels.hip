@@ -53,13 +53,15 @@ template <>
 struct TileIO<float> {
   static constexpr int kDiag = kDiagWords;
   static constexpr int kOff = kOffWords;
-  __device__ __forceinline__ static void diag(const float* __restrict__ p, int lane, float (&w)[9]) {
+  // p: the tile (t = 0..7); h: its half-diagonal t = 8 in the block tail
+  __device__ __forceinline__ static void diag(const float* __restrict__ p, const float* __restrict__ h,
+                                              int lane, float (&w)[9]) {
     const f32x4* q = reinterpret_cast<const f32x4*>(p);
     f32x4 a = __builtin_nontemporal_load(q + lane);
     f32x4 b = __builtin_nontemporal_load(q + 16 + lane);
     w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
     w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
-    w[8] = __builtin_nontemporal_load(p + 128 + lane);
+    w[8] = __builtin_nontemporal_load(h + lane);
   }
   __device__ __forceinline__ static void off(const float* __restrict__ p, int lane, float (&w)[16]) {
     const f32x4* q = reinterpret_cast<const f32x4*>(p);
@@ -79,11 +81,12 @@ struct TileIO<uint16_t> {
     w[0] = bf16_lo(a.x); w[1] = bf16_hi(a.x); w[2] = bf16_lo(a.y); w[3] = bf16_hi(a.y);
     w[4] = bf16_lo(a.z); w[5] = bf16_hi(a.z); w[6] = bf16_lo(a.w); w[7] = bf16_hi(a.w);
   }
-  __device__ __forceinline__ static void diag(const uint16_t* __restrict__ p, int lane, float (&w)[9]) {
+  __device__ __forceinline__ static void diag(const uint16_t* __restrict__ p, const uint16_t* __restrict__ h,
+                                              int lane, float (&w)[9]) {
     const u32x4* q = reinterpret_cast<const u32x4*>(p);
     u32x4 a = __builtin_nontemporal_load(q + lane);
     unpack8(a, w);
-    uint32_t t8 = __builtin_nontemporal_load(p + 128 + lane);
+    uint32_t t8 = __builtin_nontemporal_load(h + lane);
     w[8] = __uint_as_float(t8 << 16);
   }
   __device__ __forceinline__ static void off(const uint16_t* __restrict__ p, int lane, float (&w)[16]) {
@@ -127,11 +130,11 @@ __device__ __forceinline__ int tri_index(int I, int J, int nt) {
 // block's partial-sum slots (LDS): slot I = row sums of strip I, slot nt + tri(I,J) =
 // transposed contribution of tile (I, J) to segment J.
 template <typename T>
-__device__ __forceinline__ void run_job(const T* __restrict__ tiles, int g, int nt,
+__device__ __forceinline__ void run_job(const T* __restrict__ blk, int job_off, int tail_off, int g, int nt,
                                         const float* __restrict__ x, float* __restrict__ part, int lane) {
   const int I0 = g, I1 = nt - 1 - g;
   const int nstrip = (I0 == I1) ? 1 : 2;
-  const T* ptr = tiles;
+  const T* ptr = blk + job_off;
   for (int st = 0; st < nstrip; ++st) {
     const int I = st ? I1 : I0;
     const float xI = x[kTile * I + lane];
@@ -144,7 +147,7 @@ __device__ __forceinline__ void run_job(const T* __restrict__ tiles, int g, int 
     float yI = 0.f;
     {
       float w[9];
-      TileIO<T>::diag(ptr, lane, w);
+      TileIO<T>::diag(ptr, blk + tail_off + kHalfDiagWords * I, lane, w);
       ptr += TileIO<T>::kDiag;
       diag_tile(w, xI, xr, yI);
     }
@@ -179,7 +182,7 @@ __device__ __forceinline__ void run_phase(const T* __restrict__ tiles, int nb, c
     const int g = grp / per_g;
     const int b = (grp - g * per_g) * 4 + rw;
     if (b < nb) {
-      run_job<T>(tiles + b * prm.words_per_block + prm.job_off[g], g, prm.nt, xs + b * vstride,
+      run_job<T>(tiles + b * prm.words_per_block, prm.job_off[g], prm.tail_off, g, prm.nt, xs + b * vstride,
                  part + b * prm.nslots * kTile, lane);
     }
   }

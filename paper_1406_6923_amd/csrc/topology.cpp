@@ -14,7 +14,7 @@
 
 namespace sfm {
 
-void TileGeometry::init(int p_) {
+void TileGeometry::init(int p_, int elem_bytes) {
   p = p_;
   P16 = (p + kTile - 1) / kTile * kTile;
   nt = P16 / kTile;
@@ -27,12 +27,13 @@ void TileGeometry::init(int p_) {
     off += strip_words(g);
     if (g != nt - 1 - g) off += strip_words(nt - 1 - g);
   }
-  words_per_block = off;
+  tail_off = (int32_t)off;
+  const int64_t line = kLineBytes / elem_bytes;
+  words_per_block = off + ((int64_t)kHalfDiagWords * nt + line - 1) / line * line;
 }
 
 // Lane and diagonal index (t) of word w of a diagonal / off-diagonal tile in the stored order.
 static void diag_word(int w, bool bf16, int& lane, int& t) {
-  if (w >= 128) { lane = w - 128; t = 8; return; }
   if (bf16) { lane = w / 8; t = w % 8; return; }
   const int v = w / 64, rem = w % 64;
   lane = rem / 4;
@@ -76,6 +77,15 @@ void TileGeometry::word_map(std::vector<int32_t>& rows, std::vector<int32_t>& co
         }
       }
     }
+  }
+  for (int I = 0; I < nt; ++I)
+    for (int lane = 0; lane < kTile; ++lane) {
+      rows.push_back(kTile * I + lane);
+      cols.push_back(kTile * I + (lane + 8) % kTile);
+    }
+  while ((int64_t)rows.size() < words_per_block) {   // padding: outside the block, stored as 0
+    rows.push_back(P16);
+    cols.push_back(P16);
   }
 }
 
