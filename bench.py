@@ -99,13 +99,58 @@ def cpu_baseline(cfg: W.Workload, c_full: np.ndarray, dt_ratio: float, nsub=(1, 
     }
 
 
+def finite_shift_probe(torch, sfm, dev, stream, n: int = 4, steps: int = 200, sigma_factor: float = 16.0):
+    """Finite-shift ROMs on an n^3-subdomain sample with the large workload's subdomain and ROM
+    shape (33^3 nodes, m = 16, k = 16): device build rate (Jacobi-PCG shifted solves), the CFL
+    step against sigma = infinity ROMs of the same sample, and the FP64-coefficient step rate."""
+    cfg = W.scaled_large((n, n, n), nsteps=steps)
+    c = cfg.velocity_model()
+    vel = torch.from_numpy(c.astype(np.float32)).to(dev)
+    sigma = sigma_factor * (2.0 * math.pi * cfg.f_peak) ** 2
+    out = {"workload": cfg.name, "subdomains": n ** 3, "sigma": sigma,
+           "sigma_over_peak_omega_sq": sigma_factor, "coefficients": "f64"}
+    h_inf = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sfm.sfm_build_roms(h_inf.ctx, vel, stream=stream)
+    torch.cuda.synchronize()
+    out["sigma_inf_builds_per_s"] = n ** 3 / (time.perf_counter() - t0)
+    dt_inf = sfm.sfm_cfl_dt(h_inf.ctx, 200, stream=stream)
+    h_inf.close()
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k, precision=sfm.SFM_PREC_FP64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = sfm.sfm_build_roms_shifted(h.ctx, sigma, vel, stream=stream)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    out.update(build_seconds=t_b, builds_per_s=n ** 3 / t_b, cg_iters_max=iters)
+    dt_sh = sfm.sfm_cfl_dt(h.ctx, 200, stream=stream)
+    out["dt_ratio_vs_sigma_inf"] = dt_sh / dt_inf
+    dt = 0.9 * dt_sh
+    wav = torch.tensor(W.ricker(cfg.f_peak, dt, steps)[:, None], dtype=torch.float32, device=dev)
+    sfm.sfm_step(h.ctx, 20, dt, wav[:20].contiguous(), None, stream=stream)
+    sfm.sfm_set_timing(h.ctx, True)
+    sfm.sfm_step(h.ctx, steps, dt, wav, None, stream=stream)
+    torch.cuda.synchronize()
+    info = h.info()
+    main_ms = info["timed_main_ms"] / max(info["timed_steps"], 1)
+    k, p = info["k"], info["p"]
+    bytes_per_launch = n ** 3 * ((2 * k - 1) * p * (p + 1) // 2 * 8 + 3 * k * p * 4)
+    out.update(fp64_main_ms=main_ms, fp64_main_gbs=bytes_per_launch / (main_ms * 1e-3) / 1e9)
+    h.close()
+    log(f"[bench] finite shift sigma = {sigma:.3g}: {out['builds_per_s']:.1f} builds/s "
+        f"(sigma = inf {out['sigma_inf_builds_per_s']:.1f}), at most {iters} CG iterations, "
+        f"dt x{out['dt_ratio_vs_sigma_inf']:.3f}, FP64 step kernel {main_ms:.4f} ms ({out['fp64_main_gbs']:.0f} GB/s)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="large")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--build-batch", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-receivers", action="store_true")
@@ -113,6 +158,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=2048,
                     help="size of the device copy timed as the practical HBM bandwidth reference")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--no-finite-shift", action="store_true",
+                    help="skip the finite-shift ROM probe (4^3-subdomain sample of the same ROM shape)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU split of this "
@@ -123,7 +170,7 @@ def main():
     from paper_1406_6923_amd import sfm
 
     cfg = workload(args.workload)
-    prec = sfm.SFM_PREC_FP32 if args.precision == "fp32" else sfm.SFM_PREC_BF16_FP32ACC
+    prec = {"fp32": sfm.SFM_PREC_FP32, "bf16": sfm.SFM_PREC_BF16_FP32ACC, "fp64": sfm.SFM_PREC_FP64}[args.precision]
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
@@ -178,11 +225,14 @@ def main():
     face_ms = info["timed_face_ms"] / max(info["timed_steps"], 1)
     rec_ms = info["timed_record_ms"] / max(info["timed_steps"], 1)
     k, p = info["k"], info["p"]
-    elem = 4 if prec == sfm.SFM_PREC_FP32 else 2
+    elem = {sfm.SFM_PREC_FP32: 4, sfm.SFM_PREC_BF16_FP32ACC: 2, sfm.SFM_PREC_FP64: 8}[prec]
     bytes_per_sub = (2 * k - 1) * p * (p + 1) // 2 * elem + 3 * k * p * 4
     launch_bytes = S * bytes_per_sub
     achieved = launch_bytes / (main_ms * 1e-3) / 1e9
-    traffic, traffic_note = traffic_from_profiles(launch_bytes)
+    if prec == sfm.SFM_PREC_FP32:
+        traffic, traffic_note = traffic_from_profiles(launch_bytes)
+    else:
+        traffic, traffic_note = None, "committed counters cover the FP32 kernel only"
     log(f"[bench] main kernel {main_ms:.4f} ms ({achieved:.0f} GB/s algorithmic), face {face_ms:.4f} ms, "
         f"receivers {rec_ms:.4f} ms")
 
@@ -237,7 +287,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == sfm.SFM_PREC_FP32 else "bf16-coef/f32-acc",
+        "dtype": {sfm.SFM_PREC_FP32: "f32", sfm.SFM_PREC_BF16_FP32ACC: "bf16-coef/f32-acc",
+                  sfm.SFM_PREC_FP64: "f64-coef/f32-state"}[prec],
         "data": "synthetic",
         "config": {
             "workload": cfg.name,
@@ -273,6 +324,8 @@ def main():
         comparators["speedup_vs_fine_fdtd"] = value / comparators["fine_fdtd_gcell_per_s"]
         comparators["speedup_vs_plain_rom"] = value / comparators["plain_rom_gcell_per_s"]
         out["comparators"] = comparators
+    if not args.no_finite_shift:
+        out["finite_shift"] = finite_shift_probe(torch, sfm, dev, stream)
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline: oracle on a one-subdomain sample")
         out["cpu_baseline"] = cpu_baseline(cfg, c, ratio)

@@ -51,12 +51,16 @@ typedef enum {
   SFM_ENOMEM = -3,      /* device allocation failed */
   SFM_EBREAKDOWN = -4,  /* block Lanczos breakdown or non-SPD S-fraction level */
   SFM_ESTATE = -5,      /* call out of order (e.g. step before ROMs exist) */
-  SFM_EUNSTABLE = -6    /* time step above the stability limit */
+  SFM_EUNSTABLE = -6,   /* time step above the stability limit */
+  SFM_ENOCONV = -7      /* an iterative inner solve did not reach its tolerance */
 } sfm_status;
 
 typedef enum {
-  SFM_PREC_FP32 = 0,        /* coefficient blocks stored FP32 */
-  SFM_PREC_BF16_FP32ACC = 1 /* coefficient blocks stored BF16, FP32 accumulation */
+  SFM_PREC_FP32 = 0,         /* coefficient blocks stored FP32 */
+  SFM_PREC_BF16_FP32ACC = 1, /* coefficient blocks stored BF16, FP32 accumulation */
+  SFM_PREC_FP64 = 2          /* coefficient blocks stored FP64, FP64 products and sums (the
+                                state arrays stay FP32): for ROMs whose S-fraction blocks are
+                                too ill-conditioned for FP32 storage, e.g. finite-shift ROMs */
 } sfm_precision;
 
 typedef struct {
@@ -120,6 +124,35 @@ sfm_status sfm_query(sfm_ctx ctx, sfm_info* out);
 sfm_status sfm_build_roms(sfm_ctx ctx, const float* vel_dev, int32_t nsrc, const int32_t* src_ijk,
                           int32_t nrec, const int32_t* rec_ijk, const float* u0_dev,
                           const float* v0_dev, void* stream);
+
+/* Stage 1 with the rational projection subspace of a finite shift sigma > 0 (Stage 1
+ * section: the Krylov space of the resolvent at one real shift, taken n times, with F
+ * added as the coupling requires; the paper's K_n(0) with the shift moved off the null
+ * space of a floating subdomain).  Per subdomain:
+ *   1. V = orthonormal basis of span{F, (A_+ + sigma)^{-1} F, ..., (A_+ + sigma)^{-(k-1)} F}
+ *      from block Lanczos on ((A_+ + sigma I)^{-1}, F) with the same FP64 two-pass
+ *      re-orthogonalisation as sfm_build_roms; every shifted solve is a Jacobi-
+ *      preconditioned conjugate-gradient iteration, one per column, stopped when
+ *      |b - (A_+ + sigma) x| <= cg_rtol |b| (2-norms);
+ *   2. the reduced pair (V^T A_+ V, V^T F) is tridiagonalised by block Lanczos
+ *      (Algorithm 1, step 1.2); then steps 1.3 and 1.4 as in sfm_build_roms.
+ * The result is the ROM whose transfer function interpolates the fine one at s^2 = sigma
+ * (to the accuracy of the inner solves).  Arguments as sfm_build_roms, plus
+ *   sigma        shift, positive and finite, in the units of A_+ (1/s^2)
+ *   cg_rtol      relative residual of every inner solve, 0 < cg_rtol < 1
+ *   cg_max_iter  iteration limit of every inner solve (>= 1)
+ *   cg_iters     host, may be NULL: the largest iteration count of any inner solve
+ * The context must store coefficients in FP64 (SFM_PREC_FP64): every subdomain is floating
+ * (Neumann on its box faces), the rational space holds its constant mode, and the last
+ * level Gamma_k is singular along it; rounding the blocks to FP32 or BF16 makes it
+ * indefinite and the leapfrog diverges.
+ * Synchronizes.  Errors: as sfm_build_roms, SFM_EINVAL for a context whose precision is not
+ * SFM_PREC_FP64, and SFM_ENOCONV when an inner solve stops at cg_max_iter above cg_rtol (the
+ * context then holds no ROMs). */
+sfm_status sfm_build_roms_shifted(sfm_ctx ctx, double sigma, double cg_rtol, int32_t cg_max_iter,
+                                  const float* vel_dev, int32_t nsrc, const int32_t* src_ijk, int32_t nrec,
+                                  const int32_t* rec_ijk, const float* u0_dev, const float* v0_dev,
+                                  int32_t* cg_iters, void* stream);
 
 /* Restart from the projected initial conditions with step dt: U^0 = U(0) and
  * U^{-1} = U(0) - dt U_t(0) (first-order start, as the fine-grid leapfrog), n = 0.

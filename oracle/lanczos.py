@@ -89,8 +89,11 @@ def block_lanczos(apply_op: Callable[[np.ndarray], np.ndarray], F: np.ndarray, k
 
     Q_1 B_1 = F.  For j = 1..k:  W = op Q_j - Q_{j-1} B_j^T,  A_j = Q_j^T op Q_j,
     W -= Q_j A_j, then W -= Z (Z^T W) twice against every block so far, and
-    Q_{j+1} B_{j+1} = W (not formed after the last block).  A block whose
-    smallest |diag B| falls below ``breakdown_tol * ||B_1||`` is a breakdown.
+    Q_{j+1} B_{j+1} = W (not formed after the last block).  The start block is rank
+    deficient when its smallest |diag B_1| falls below ``breakdown_tol * ||B_1||``; a later
+    block breaks down when its smallest |diag B_{j+1}| falls below ``breakdown_tol * ||op Q_j||``
+    (the new directions are negligible against what the operator produced; relative to the
+    operator's own scale, so the test means the same for A_+ and for a resolvent of norm 1/sigma).
     """
     F = np.asarray(F.toarray() if sp.issparse(F) else F, dtype=np.float64)
     N, p = F.shape
@@ -118,7 +121,7 @@ def block_lanczos(apply_op: Callable[[np.ndarray], np.ndarray], F: np.ndarray, k
         for _ in range(2):
             W = W - Z @ (Z.T @ W)
         Qn, Bn = qr_positive(W)
-        if np.min(np.abs(np.diag(Bn))) < breakdown_tol * scale:
+        if np.min(np.abs(np.diag(Bn))) < breakdown_tol * np.linalg.norm(AQ, 2):
             raise LanczosBreakdown(f"block {j + 2}: min |diag B| = {np.min(np.abs(np.diag(Bn))):.3e}")
         Qs.append(Qn)
         Bs.append(Bn)
@@ -130,15 +133,23 @@ def lanczos_infinite(A_plus: sp.spmatrix, F, k: int) -> BlockTridiagonal:
     return block_lanczos(lambda X: A_plus @ X, F, k)
 
 
-def lanczos_rational(A_plus: sp.spmatrix, F, k: int, sigma: float) -> BlockTridiagonal:
+def lanczos_rational(A_plus: sp.spmatrix, F, k: int, sigma: float,
+                     solve_hook: Callable[[Callable, np.ndarray], np.ndarray] = None) -> BlockTridiagonal:
     """Finite sigma: V spans {F, (A_+ + sigma)^{-1}F, ...}; then T from block Lanczos on (V^T A_+ V, V^T F).
 
     The shifted solves use one sparse LU factorisation reused for all blocks
     (Stage 1 section: a precomputed factorisation can be reused).  Returns Z = V Q.
+    solve_hook(solve, X), if given, replaces solve(X) (the tests use it to model inexact solves).
     """
     N = A_plus.shape[0]
-    lu = spla.splu((A_plus + sigma * sp.identity(N)).tocsc())
-    rational = block_lanczos(lambda X: lu.solve(X), F, k)
+    # A_+ + sigma I is symmetric positive definite: diagonal pivots and a symmetric
+    # fill-reducing ordering give an exact factorisation with far less fill than COLAMD.
+    lu = spla.splu((A_plus + sigma * sp.identity(N)).tocsc(), permc_spec="MMD_AT_PLUS_A",
+                   diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
+    if solve_hook is None:
+        rational = block_lanczos(lambda X: lu.solve(X), F, k)
+    else:
+        rational = block_lanczos(lambda X: solve_hook(lu.solve, X), F, k)
     V = rational.Z
     A_rom = V.T @ (A_plus @ V)
     A_rom = 0.5 * (A_rom + A_rom.T)

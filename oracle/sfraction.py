@@ -100,7 +100,9 @@ def ntd_resolvent(A_plus, F, s: float) -> np.ndarray:
     Fd = np.asarray(F.toarray() if sp.issparse(F) else F)
     N = A_plus.shape[0]
     if sp.issparse(A_plus):
-        X = spla.splu((A_plus + s * s * sp.identity(N)).tocsc()).solve(Fd)
+        # symmetric positive definite for s > 0: diagonal pivots, symmetric fill-reducing ordering
+        X = spla.splu((A_plus + s * s * sp.identity(N)).tocsc(), permc_spec="MMD_AT_PLUS_A",
+                      diag_pivot_thresh=0.0, options=dict(SymmetricMode=True)).solve(Fd)
     else:
         X = np.linalg.solve(A_plus + s * s * np.eye(N), Fd)
     return Fd.T @ X

@@ -148,10 +148,10 @@ __global__ void init_q1_kernel(BoxGeo g, const double* __restrict__ S, const int
   }
 }
 
-// W = A_+ X = S K S X for the p columns of X (ld ldx) into W (ld ldw).
+// W = (A_+ + shift I) X = S K S X + shift X for the p columns of X (ld ldx) into W (ld ldw).
 // K is the geometric stiffness: coefficient h per edge, halved for every box plane holding the edge.
 __global__ void stencil_kernel(BoxGeo g, const double* __restrict__ S, int64_t N, int nb, const double* __restrict__ X,
-                               int ldx, int64_t sx, double* __restrict__ W, int ldw, int64_t sw) {
+                               int ldx, int64_t sx, double* __restrict__ W, int ldw, int64_t sw, double shift) {
   const int64_t total = (int64_t)nb * N * g.p;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     const int col = (int)(idx % g.p);
@@ -177,7 +177,221 @@ __global__ void stencil_kernel(BoxGeo g, const double* __restrict__ S, int64_t N
     if (j < g.sub[1]) acc += cy * (yn - Sb[n + syn] * Xb[(n + syn) * ldx]);
     if (l > 0) acc += cz * (yn - Sb[n - szn] * Xb[(n - szn) * ldx]);
     if (l < g.sub[2]) acc += cz * (yn - Sb[n + szn] * Xb[(n + szn) * ldx]);
-    W[(int64_t)b * sw + n * ldw + col] = sn * acc;
+    W[(int64_t)b * sw + n * ldw + col] = sn * acc + shift * Xb[n * ldx];
+  }
+}
+
+// Jacobi preconditioner of A_+ + sigma I: dinv = 1 / (S_n^2 sum of the node's edge coefficients + sigma).
+__global__ void shifted_diag_kernel(BoxGeo g, const double* __restrict__ S, int64_t N, int nb, double sigma,
+                                    double* __restrict__ dinv) {
+  const int64_t total = (int64_t)nb * N;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = idx % N;
+    int i, j, l;
+    local_ijk(g, n, i, j, l);
+    const double wi = half_if(i == 0 || i == g.sub[0]);
+    const double wj = half_if(j == 0 || j == g.sub[1]);
+    const double wl = half_if(l == 0 || l == g.sub[2]);
+    const int nx = (i > 0) + (i < g.sub[0]), ny = (j > 0) + (j < g.sub[1]), nz = (l > 0) + (l < g.sub[2]);
+    const double ksum = g.h * (nx * wj * wl + ny * wi * wl + nz * wi * wj);
+    const double sn = S[idx];
+    dinv[idx] = 1.0 / (sn * sn * ksum + sigma);
+  }
+}
+
+// ---------------------------------------------------------------- batched Jacobi PCG
+// Solves (A_+ + sigma I) X = B for the p columns of every subdomain of a batch, one CG
+// recurrence per column.  Vectors R, P, Q are node-major [b][N][p]; X and B may be column
+// blocks of a wider node-major array (ld, stride).  Column sums over the N nodes are taken in
+// two stages: a chunk kernel writes partial sums part[.][b][chunk][col] (block (chunk, b);
+// thread t handles column t % p of every (256 / p)-th row of the chunk), then a per-column
+// kernel adds the chunks in order, so every sum is reproducible.  A column stops (alpha = 0)
+// once |r| <= rtol |b|; it is never updated again.
+struct CgVec {
+  int64_t N;
+  int p, nchunk, nb;
+};
+
+__device__ __forceinline__ void chunk_range(const CgVec& v, int chunk, int64_t& n0, int64_t& n1) {
+  const int64_t rows = (v.N + v.nchunk - 1) / v.nchunk;
+  n0 = (int64_t)chunk * rows;
+  n1 = min(v.N, n0 + rows);
+}
+
+// Sums s[0..NS) of each column over the rows of this block into part[q][b][chunk][col].
+template <int NS>
+__device__ __forceinline__ void chunk_col_sums(const CgVec& v, const double (&sv)[NS], double* __restrict__ part) {
+  __shared__ double red[NS][256];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) red[q][t] = sv[q];
+  __syncthreads();
+  const int rpp = 256 / v.p;
+  if (t < v.p) {
+    const int64_t slot = ((int64_t)blockIdx.y * v.nchunk + blockIdx.x) * v.p + t;
+    const int64_t plane = (int64_t)v.nb * v.nchunk * v.p;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+      double acc = 0.0;
+      for (int r = 0; r < rpp; ++r) acc += red[q][r * v.p + t];
+      part[q * plane + slot] = acc;
+    }
+  }
+}
+
+// x = 0, r = b, p = D^{-1} r; partial sums of r.z and r.r.
+__global__ __launch_bounds__(256) void cg_init_kernel(CgVec v, const double* __restrict__ B, int ldb, int64_t sb,
+                                                      const double* __restrict__ dinv, double* __restrict__ X, int ldx,
+                                                      int64_t sx, double* __restrict__ R, double* __restrict__ P,
+                                                      double* __restrict__ part) {
+  const int b = blockIdx.y, t = threadIdx.x;
+  const int rpp = 256 / v.p, col = t % v.p, r0 = t / v.p;
+  int64_t n0, n1;
+  chunk_range(v, blockIdx.x, n0, n1);
+  double sv[2] = {0.0, 0.0};
+  if (r0 < rpp) {
+    for (int64_t n = n0 + r0; n < n1; n += rpp) {
+      const double bv = B[(int64_t)b * sb + n * ldb + col];
+      const double z = dinv[(int64_t)b * v.N + n] * bv;
+      const int64_t e = ((int64_t)b * v.N + n) * v.p + col;
+      X[(int64_t)b * sx + n * ldx + col] = 0.0;
+      R[e] = bv;
+      P[e] = z;
+      sv[0] += bv * z;
+      sv[1] += bv * bv;
+    }
+  }
+  chunk_col_sums<2>(v, sv, part);
+}
+
+// partial sums of p.q
+__global__ __launch_bounds__(256) void cg_dot_kernel(CgVec v, const double* __restrict__ P, const double* __restrict__ Q,
+                                                     double* __restrict__ part) {
+  const int b = blockIdx.y, t = threadIdx.x;
+  const int rpp = 256 / v.p, col = t % v.p, r0 = t / v.p;
+  int64_t n0, n1;
+  chunk_range(v, blockIdx.x, n0, n1);
+  double sv[1] = {0.0};
+  if (r0 < rpp) {
+    for (int64_t n = n0 + r0; n < n1; n += rpp) {
+      const int64_t e = ((int64_t)b * v.N + n) * v.p + col;
+      sv[0] += P[e] * Q[e];
+    }
+  }
+  chunk_col_sums<1>(v, sv, part);
+}
+
+// x += alpha p, r -= alpha q; partial sums of r.z (z = D^{-1} r) and r.r.
+__global__ __launch_bounds__(256) void cg_update_kernel(CgVec v, const double* __restrict__ alpha,
+                                                        const double* __restrict__ dinv, const double* __restrict__ P,
+                                                        const double* __restrict__ Q, double* __restrict__ X, int ldx,
+                                                        int64_t sx, double* __restrict__ R, double* __restrict__ part) {
+  const int b = blockIdx.y, t = threadIdx.x;
+  const int rpp = 256 / v.p, col = t % v.p, r0 = t / v.p;
+  int64_t n0, n1;
+  chunk_range(v, blockIdx.x, n0, n1);
+  double sv[2] = {0.0, 0.0};
+  if (r0 < rpp) {
+    const double a = alpha[(int64_t)b * v.p + col];
+    for (int64_t n = n0 + r0; n < n1; n += rpp) {
+      const int64_t e = ((int64_t)b * v.N + n) * v.p + col;
+      double* x = X + (int64_t)b * sx + n * ldx + col;
+      *x = fma(a, P[e], *x);
+      const double r = fma(-a, Q[e], R[e]);
+      R[e] = r;
+      sv[0] += r * dinv[(int64_t)b * v.N + n] * r;
+      sv[1] += r * r;
+    }
+  }
+  chunk_col_sums<2>(v, sv, part);
+}
+
+// Per-column scalars sc = [rz][bb][alpha][beta] ([4][nb * p]) and active flags.
+__device__ __forceinline__ double sum_chunks(const CgVec& v, const double* part, int q, int b, int col) {
+  const int64_t plane = (int64_t)v.nb * v.nchunk * v.p;
+  const double* pp = part + q * plane + (int64_t)b * v.nchunk * v.p + col;
+  double acc = 0.0;
+  for (int ch = 0; ch < v.nchunk; ++ch) acc += pp[(int64_t)ch * v.p];
+  return acc;
+}
+
+__global__ void cg_start_kernel(CgVec v, const double* __restrict__ part, double* __restrict__ sc, int* __restrict__ active) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = v.nb * v.p;
+  if (idx >= n) return;
+  const int b = idx / v.p, col = idx - b * v.p;
+  const double rz = sum_chunks(v, part, 0, b, col);
+  const double bb = sum_chunks(v, part, 1, b, col);
+  sc[idx] = rz;
+  sc[n + idx] = bb;
+  sc[2 * n + idx] = 0.0;
+  sc[3 * n + idx] = 0.0;
+  active[idx] = bb > 0.0 ? 1 : 0;
+}
+
+__global__ void cg_alpha_kernel(CgVec v, const double* __restrict__ part, double* __restrict__ sc,
+                                const int* __restrict__ active) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = v.nb * v.p;
+  if (idx >= n) return;
+  const int b = idx / v.p, col = idx - b * v.p;
+  const double pq = sum_chunks(v, part, 0, b, col);
+  sc[2 * n + idx] = (active[idx] && pq > 0.0) ? sc[idx] / pq : 0.0;
+}
+
+__global__ void cg_beta_kernel(CgVec v, const double* __restrict__ part, double* __restrict__ sc, int* __restrict__ active,
+                               double rtol2) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = v.nb * v.p;
+  if (idx >= n) return;
+  const int b = idx / v.p, col = idx - b * v.p;
+  double beta = 0.0;
+  if (active[idx]) {
+    const double rzn = sum_chunks(v, part, 0, b, col);
+    const double rr = sum_chunks(v, part, 1, b, col);
+    const double rz = sc[idx];
+    beta = rz > 0.0 ? rzn / rz : 0.0;
+    sc[idx] = rzn;
+    if (rr <= rtol2 * sc[n + idx]) active[idx] = 0;
+  }
+  sc[3 * n + idx] = beta;
+}
+
+// p = D^{-1} r + beta p
+__global__ void cg_dir_kernel(CgVec v, const double* __restrict__ dinv, const double* __restrict__ R,
+                              const double* __restrict__ beta, double* __restrict__ P) {
+  const int64_t total = (int64_t)v.nb * v.N * v.p;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int col = (int)(e % v.p);
+    const int64_t bn = e / v.p;
+    const int b = (int)(bn / v.N);
+    P[e] = fma(dinv[bn], R[e], beta[(int64_t)b * v.p + col] * P[e]);
+  }
+}
+
+// count[0] = number of active columns (one work-group)
+__global__ __launch_bounds__(256) void count_active_kernel(const int* __restrict__ active, int n, int* __restrict__ count) {
+  __shared__ int red[256];
+  int acc = 0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += active[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[0] = red[0];
+}
+
+// First block of the reduced-space Lanczos basis: columns 0..p-1 of the identity (rows kp, ld kp).
+__global__ void eye_block_kernel(int kp, int p, int nb, double* __restrict__ Z, int64_t sz) {
+  const int64_t total = (int64_t)nb * kp * p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int col = (int)(idx % p);
+    const int64_t bn = idx / p;
+    const int b = (int)(bn / kp);
+    const int n = (int)(bn - (int64_t)b * kp);
+    Z[(int64_t)b * sz + (int64_t)n * kp + col] = n == col ? 1.0 : 0.0;
   }
 }
 
@@ -395,12 +609,40 @@ using namespace sfm;
     B_TRY_HIP(hipGetLastError());                                                             \
   } while (0)
 
-extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t nsrc, const int32_t* src_ijk,
-                                     int32_t nrec, const int32_t* rec_ijk, const float* u0_dev,
-                                     const float* v0_dev, void* stream) {
-  if (!c) return SFM_EINVAL;
+namespace {
+
+// Device scratch of one build, released on every return path.
+struct Scratch {
+  sfm_ctx c;
+  hipError_t e = hipSuccess;
+  std::vector<void*> ptrs;
+  explicit Scratch(sfm_ctx ctx) : c(ctx) {}
+  ~Scratch() {
+    for (void* ptr : ptrs) c->dfree(ptr);
+  }
+  template <typename T = double>
+  T* get(size_t count) {
+    void* ptr = c->dalloc(count * sizeof(T), &e);
+    if (ptr) ptrs.push_back(ptr);
+    return static_cast<T*>(ptr);
+  }
+};
+
+// Shift and inner-solver settings of one build; sigma = +inf selects the polynomial space.
+struct ShiftSpec {
+  double sigma;
+  double rtol;
+  int max_iter;
+};
+
+constexpr int kCgCheck = 10;   // CG iterations between convergence checks on the host
+
+sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, int32_t nsrc, const int32_t* src_ijk,
+                      int32_t nrec, const int32_t* rec_ijk, const float* u0_dev, const float* v0_dev,
+                      int32_t* cg_iters_out, void* stream) {
   c->err.clear();
   if (!vel_dev) return c->fail(SFM_EINVAL, "vel_dev is NULL");
+  const bool finite = std::isfinite(shift.sigma);
   const auto t_start = std::chrono::steady_clock::now();
   B_TRY_HIP(hipSetDevice(c->device));
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -408,6 +650,7 @@ extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t ns
   const int S = t.S, k = t.k, p = t.p, kp = k * p, P16 = c->geo.P16;
   const int64_t N = t.N_local;
   const int64_t pp = (int64_t)p * p;
+  const int64_t kpkp = (int64_t)kp * kp;
   std::vector<int32_t> src_sub, src_local, rec_sub, rec_local;
   sfm_status rc = locate_points(c, nsrc, src_ijk, nrec, rec_ijk, src_sub, src_local, rec_sub, rec_local);
   if (rc != SFM_OK) return rc;
@@ -437,8 +680,10 @@ extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t ns
   if (e != hipSuccess) return c->fail(SFM_ENOMEM, "projection buffers: out of device memory");
 
   // batch size from the free device memory
-  const int64_t per_sub = (int64_t)sizeof(double) *
-                          (N * kp + N * p + N + 2 * (int64_t)kp * p + 7 * (int64_t)k * pp + 6 * pp + kp + 8);
+  int64_t per_sub = (int64_t)sizeof(double) *
+                    (N * kp + N * p + N + 2 * (int64_t)kp * p + 7 * (int64_t)k * pp + 6 * pp + kp + 8);
+  if (finite) per_sub += (int64_t)sizeof(double) * (3 * N * p + N + 2 * kpkp + 16 * (int64_t)p) +
+                         (int64_t)sizeof(double) * 2 * 1024 * p;
   int nbmax = c->cfg.build_batch;
   if (nbmax <= 0) {
     size_t fr = 0, tot = 0;
@@ -446,48 +691,56 @@ extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t ns
     nbmax = (int)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(0.6 * (double)fr) / per_sub));
   }
   nbmax = std::min(nbmax, S);
-  std::vector<void*> scratch;
-  auto salloc = [&](size_t bytes) -> double* {
-    void* ptr = c->dalloc(bytes, &e);
-    if (ptr) scratch.push_back(ptr);
-    return static_cast<double*>(ptr);
-  };
-  double* Z = salloc((size_t)nbmax * N * kp * sizeof(double));
-  double* Wl = salloc((size_t)nbmax * N * p * sizeof(double));
-  double* Sd = salloc((size_t)nbmax * N * sizeof(double));
-  double* C1 = salloc((size_t)nbmax * kp * p * sizeof(double));
-  double* C2 = salloc((size_t)nbmax * kp * p * sizeof(double));
-  double* A = salloc((size_t)nbmax * k * pp * sizeof(double));
-  double* Bt = salloc((size_t)nbmax * k * pp * sizeof(double));
-  double* G = salloc((size_t)nbmax * k * pp * sizeof(double));
-  double* Gi = salloc((size_t)nbmax * k * pp * sizeof(double));
-  double* Gam = salloc((size_t)nbmax * k * pp * sizeof(double));
-  double* Gh = salloc((size_t)nbmax * k * pp * sizeof(double));
-  double* L1 = salloc((size_t)nbmax * pp * sizeof(double));
-  double* L2 = salloc((size_t)nbmax * pp * sizeof(double));
-  double* T1 = salloc((size_t)nbmax * pp * sizeof(double));
-  double* Hb = salloc((size_t)nbmax * p * sizeof(double));
-  double* thr = salloc((size_t)nbmax * sizeof(double));
-  double* ybuf = salloc((size_t)nbmax * kp * sizeof(double));
-  int32_t* flags = reinterpret_cast<int32_t*>(salloc((size_t)(nbmax + 1) * sizeof(int32_t)));
-  int32_t* meta = reinterpret_cast<int32_t*>(salloc((size_t)nbmax * 4 * sizeof(int32_t)));
-  int32_t* pts = reinterpret_cast<int32_t*>(salloc((size_t)(std::max(nsrc, nrec) + 1) * 3 * sizeof(int32_t)));
-  auto cleanup = [&]() {
-    for (void* ptr : scratch) c->dfree(ptr);
-    scratch.clear();
-  };
-  if (e != hipSuccess) {
-    cleanup();
-    return c->fail(SFM_ENOMEM, "ROM build scratch: out of device memory (lower build_batch)");
+  // CG chunks: enough work-groups per column sum to fill the device, at most 1024
+  const int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(1024, std::min<int64_t>(N, (2048 + nbmax - 1) / nbmax)));
+  Scratch sc(c);
+  double* Z = sc.get((size_t)nbmax * N * kp);
+  double* Wl = sc.get((size_t)nbmax * N * p);
+  double* Sd = sc.get((size_t)nbmax * N);
+  double* C1 = sc.get((size_t)nbmax * kp * p);
+  double* C2 = sc.get((size_t)nbmax * kp * p);
+  double* A = sc.get((size_t)nbmax * k * pp);
+  double* Bt = sc.get((size_t)nbmax * k * pp);
+  double* G = sc.get((size_t)nbmax * k * pp);
+  double* Gi = sc.get((size_t)nbmax * k * pp);
+  double* Gam = sc.get((size_t)nbmax * k * pp);
+  double* Gh = sc.get((size_t)nbmax * k * pp);
+  double* L1 = sc.get((size_t)nbmax * pp);
+  double* L2 = sc.get((size_t)nbmax * pp);
+  double* T1 = sc.get((size_t)nbmax * pp);
+  double* Hb = sc.get((size_t)nbmax * p);
+  double* thr = sc.get((size_t)nbmax);
+  double* ybuf = sc.get((size_t)nbmax * kp);
+  int32_t* flags = sc.get<int32_t>((size_t)nbmax + 1);
+  int32_t* meta = sc.get<int32_t>((size_t)nbmax * 4);
+  int32_t* pts = sc.get<int32_t>((size_t)(std::max(nsrc, nrec) + 1) * 3);
+  // finite shift: PCG vectors, reduced operator and reduced-space basis
+  double *Dinv = nullptr, *Rv = nullptr, *Pv = nullptr, *Qv = nullptr, *part = nullptr, *cgs = nullptr;
+  double *At = nullptr, *Zh = nullptr;
+  int32_t *active = nullptr, *count = nullptr;
+  if (finite) {
+    Dinv = sc.get((size_t)nbmax * N);
+    Rv = sc.get((size_t)nbmax * N * p);
+    Pv = sc.get((size_t)nbmax * N * p);
+    Qv = sc.get((size_t)nbmax * N * p);
+    part = sc.get((size_t)2 * nbmax * nchunk * p);
+    cgs = sc.get((size_t)4 * nbmax * p);
+    At = sc.get((size_t)nbmax * kpkp);
+    Zh = sc.get((size_t)nbmax * kpkp);
+    active = sc.get<int32_t>((size_t)nbmax * p);
+    count = sc.get<int32_t>(1);
   }
+  if (sc.e != hipSuccess) return c->fail(SFM_ENOMEM, "ROM build scratch: out of device memory (lower build_batch)");
   const BoxGeo g{{t.sub[0], t.sub[1], t.sub[2]}, {t.nodes_local[0], t.nodes_local[1], t.nodes_local[2]},
                  t.m, t.m1, t.m2, p, c->cfg.h};
   std::vector<double> Hall((size_t)S * p);
   const double one = 1.0, zero = 0.0, mone = -1.0;
   const rocblas_operation NN = rocblas_operation_none, TT = rocblas_operation_transpose;
+  const int64_t sZ = N * kp;
 
   const char* vb = std::getenv("SFM_VERBOSE");
   const bool verbose = vb && vb[0] && vb[0] != '0';
+  int cg_iters_max = 0;
   sfm_status status = SFM_OK;
   for (int s0 = 0; s0 < S && status == SFM_OK; s0 += nbmax) {
     const int nb = std::min(nbmax, S - s0);
@@ -518,11 +771,9 @@ extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t ns
       double hm = 0.0;
       for (int q = 0; q < p; ++q) {
         const double hv = Hall[(size_t)(s0 + b) * p + q];
-        if (!(hv > 0.0)) {
-          cleanup();
+        if (!(hv > 0.0))
           return c->fail(SFM_EBREAKDOWN, "subdomain " + std::to_string(s0 + b) + ": empty boundary patch " +
                                              std::to_string(q) + " (rank-deficient start block)");
-        }
         hm = std::max(hm, hv);
       }
       thr_h[b] = 1e-24 * hm;   // |diag B| < 1e-12 |B_1|
@@ -531,45 +782,138 @@ extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t ns
     B_LAUNCH(init_q1_kernel, (int64_t)nb * N * p, g, Sd, mask_d, Hb, N, kp, nb, Z);
     B_LAUNCH(diag_kernel, (int64_t)nb * pp, Hb, p, nb, Bt, (int64_t)k * pp, 0);   // B_1^T = diag(H^{1/2})
 
-    // a2: block Lanczos with two-pass CGS and two-pass Cholesky QR
-    const int64_t sZ = N * kp;
-    for (int jj = 0; jj < k; ++jj) {
-      const bool last = jj + 1 == k;
-      double* W = last ? Wl : Z + (int64_t)(jj + 1) * p;
-      const int ldw = last ? p : kp;
-      const int64_t sW = last ? N * p : sZ;
-      B_LAUNCH(stencil_kernel, (int64_t)nb * N * p, g, Sd, N, nb, Z + (int64_t)jj * p, kp, sZ, W, ldw, sW);
-      const int nprev = (jj + 1) * p;
-      // C1 = Z_{1..j}^T W  (column-major p x nprev, C1[r + c p] = (Z^T W)[c][r])
-      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, nprev, (int)N, &one, W, ldw, sW, Z, kp, sZ, &zero, C1, p,
-                                               (int64_t)kp * p, nb));
-      if (last) {
-        B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, (const double*)nullptr, p, (int64_t)kp * p, jj * p,
-                 A + (int64_t)jj * pp, (int64_t)k * pp, nb);
-        break;
+    // a2: block Lanczos with two-pass CGS and two-pass Cholesky QR on a basis Zb of `rows` rows
+    // (node-major, ld kp).  apply(jj, W, ldw, sW) writes the operator applied to block jj.
+    // Steps jj < nsteps; the step jj = k - 1 only forms A_k.
+    auto lanczos = [&](double* Zb, int64_t rows, int nsteps, const double* thrp, auto&& apply) -> sfm_status {
+      const int64_t sZb = rows * kp;
+      for (int jj = 0; jj < nsteps; ++jj) {
+        const bool last = jj + 1 == k;
+        double* W = last ? Wl : Zb + (int64_t)(jj + 1) * p;
+        const int ldw = last ? p : kp;
+        const int64_t sW = last ? rows * p : sZb;
+        const sfm_status ra = apply(jj, W, ldw, sW);
+        if (ra != SFM_OK) return ra;
+        const int nprev = (jj + 1) * p;
+        // C1 = Zb_{1..j}^T W  (column-major p x nprev, C1[r + c p] = (Z^T W)[c][r])
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, nprev, (int)rows, &one, W, ldw, sW, Zb, kp, sZb, &zero,
+                                                 C1, p, (int64_t)kp * p, nb));
+        if (last) {
+          B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, (const double*)nullptr, p, (int64_t)kp * p, jj * p,
+                   A + (int64_t)jj * pp, (int64_t)k * pp, nb);
+          break;
+        }
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)rows, nprev, &mone, C1, p, (int64_t)kp * p, Zb, kp,
+                                                 sZb, &one, W, ldw, sW, nb));
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, nprev, (int)rows, &one, W, ldw, sW, Zb, kp, sZb, &zero,
+                                                 C2, p, (int64_t)kp * p, nb));
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)rows, nprev, &mone, C2, p, (int64_t)kp * p, Zb, kp,
+                                                 sZb, &one, W, ldw, sW, nb));
+        B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, C2, p, (int64_t)kp * p, jj * p, A + (int64_t)jj * pp,
+                 (int64_t)k * pp, nb);
+        // Cholesky QR, twice: W = Q (L1 L2)^T
+        double* Ls[2] = {L1, L2};
+        for (int pass = 0; pass < 2; ++pass) {
+          B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, p, (int)rows, &one, W, ldw, sW, W, ldw, sW, &zero,
+                                                   Ls[pass], p, pp, nb));
+          hipLaunchKernelGGL(cholesky_kernel, dim3(nb), dim3(256), 0, st, Ls[pass], p, pp,
+                             pass == 0 ? thrp : (const double*)nullptr, kGramRelTol, flags);
+          B_TRY_HIP(hipGetLastError());
+          B_TRY_BLAS(rocblas_dtrsm_strided_batched(h, rocblas_side_left, rocblas_fill_lower, NN,
+                                                   rocblas_diagonal_non_unit, p, (int)rows, &one, Ls[pass], p, pp, W,
+                                                   ldw, sW, nb));
+        }
+        // B_{j+1}^T = L1 L2
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, p, p, &one, L1, p, pp, L2, p, pp, &zero,
+                                                 Bt + (int64_t)(jj + 1) * pp, p, (int64_t)k * pp, nb));
       }
-      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)N, nprev, &mone, C1, p, (int64_t)kp * p, Z, kp, sZ,
-                                               &one, W, ldw, sW, nb));
-      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, nprev, (int)N, &one, W, ldw, sW, Z, kp, sZ, &zero, C2, p,
-                                               (int64_t)kp * p, nb));
-      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)N, nprev, &mone, C2, p, (int64_t)kp * p, Z, kp, sZ,
-                                               &one, W, ldw, sW, nb));
-      B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, C2, p, (int64_t)kp * p, jj * p, A + (int64_t)jj * pp,
-               (int64_t)k * pp, nb);
-      // Cholesky QR, twice: W = Q (L1 L2)^T
-      double* Ls[2] = {L1, L2};
-      for (int pass = 0; pass < 2; ++pass) {
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, p, (int)N, &one, W, ldw, sW, W, ldw, sW, &zero, Ls[pass],
-                                                 p, pp, nb));
-        hipLaunchKernelGGL(cholesky_kernel, dim3(nb), dim3(256), 0, st, Ls[pass], p, pp,
-                           pass == 0 ? (const double*)thr : (const double*)nullptr, kGramRelTol, flags);
+      return SFM_OK;
+    };
+
+    if (!finite) {
+      // polynomial space: block Lanczos on (A_+, F)
+      rc = lanczos(Z, N, k, thr, [&](int jj, double* W, int ldw, int64_t sW) -> sfm_status {
+        B_LAUNCH(stencil_kernel, (int64_t)nb * N * p, g, Sd, N, nb, Z + (int64_t)jj * p, kp, sZ, W, ldw, sW, 0.0);
+        return SFM_OK;
+      });
+      if (rc != SFM_OK) return rc;
+    } else {
+      // rational space: V = orthonormal basis of {F, (A_+ + sigma)^{-1} F, ...} from block Lanczos on
+      // ((A_+ + sigma I)^{-1}, F) with batched Jacobi-PCG solves (the tridiagonal blocks of this
+      // recurrence are not needed), then the reduced pair (V^T A_+ V, V^T F = E_1 B_1) is
+      // tridiagonalised by a second block Lanczos in the kp-dimensional space, Z = V Z~.
+      const CgVec cv{N, p, nchunk, nb};
+      const int64_t sN = N * p;
+      const dim3 cgrid(nchunk, nb);
+      const unsigned sgrid = (unsigned)((nb * p + 255) / 256);
+      B_LAUNCH(shifted_diag_kernel, (int64_t)nb * N, g, Sd, N, nb, shift.sigma, Dinv);
+      const double rtol2 = shift.rtol * shift.rtol;
+      rc = lanczos(Z, N, k - 1, nullptr, [&](int jj, double* X, int ldx, int64_t sx) -> sfm_status {
+        const double* Bv = Z + (int64_t)jj * p;
+        hipLaunchKernelGGL(cg_init_kernel, cgrid, dim3(256), 0, st, cv, Bv, kp, sZ, Dinv, X, ldx, sx, Rv, Pv, part);
         B_TRY_HIP(hipGetLastError());
-        B_TRY_BLAS(rocblas_dtrsm_strided_batched(h, rocblas_side_left, rocblas_fill_lower, NN, rocblas_diagonal_non_unit,
-                                                 p, (int)N, &one, Ls[pass], p, pp, W, ldw, sW, nb));
+        hipLaunchKernelGGL(cg_start_kernel, dim3(sgrid), dim3(256), 0, st, cv, part, cgs, active);
+        B_TRY_HIP(hipGetLastError());
+        int it = 0;
+        for (;;) {
+          for (int q = 0; q < kCgCheck; ++q, ++it) {
+            B_LAUNCH(stencil_kernel, (int64_t)nb * N * p, g, Sd, N, nb, Pv, p, sN, Qv, p, sN, shift.sigma);
+            hipLaunchKernelGGL(cg_dot_kernel, cgrid, dim3(256), 0, st, cv, Pv, Qv, part);
+            B_TRY_HIP(hipGetLastError());
+            hipLaunchKernelGGL(cg_alpha_kernel, dim3(sgrid), dim3(256), 0, st, cv, part, cgs, active);
+            B_TRY_HIP(hipGetLastError());
+            hipLaunchKernelGGL(cg_update_kernel, cgrid, dim3(256), 0, st, cv, cgs + 2 * nb * p, Dinv, Pv, Qv, X, ldx,
+                               sx, Rv, part);
+            B_TRY_HIP(hipGetLastError());
+            hipLaunchKernelGGL(cg_beta_kernel, dim3(sgrid), dim3(256), 0, st, cv, part, cgs, active, rtol2);
+            B_TRY_HIP(hipGetLastError());
+            B_LAUNCH(cg_dir_kernel, (int64_t)nb * N * p, cv, Dinv, Rv, cgs + 3 * nb * p, Pv);
+          }
+          hipLaunchKernelGGL(count_active_kernel, dim3(1), dim3(256), 0, st, active, nb * p, count);
+          B_TRY_HIP(hipGetLastError());
+          int na = 0;
+          B_TRY_HIP(hipMemcpyAsync(&na, count, sizeof(int), hipMemcpyDeviceToHost, st));
+          B_TRY_HIP(hipStreamSynchronize(st));
+          if (na == 0) break;
+          if (it >= shift.max_iter)
+            return c->fail(SFM_ENOCONV, "shifted solve of Lanczos block " + std::to_string(jj + 1) + " (subdomains " +
+                                            std::to_string(s0) + ".." + std::to_string(s0 + nb - 1) + "): " +
+                                            std::to_string(na) + " columns above rtol after " + std::to_string(it) +
+                                            " iterations");
+        }
+        cg_iters_max = std::max(cg_iters_max, it);
+        if (verbose) {
+          std::fprintf(stderr, "[sfm] shifted build: block %d of subdomains %d..%d, %d CG iterations\n", jj + 1, s0,
+                       s0 + nb - 1, it);
+          std::fflush(stderr);
+        }
+        return SFM_OK;
+      });
+      if (rc != SFM_OK) return rc;
+      // A~ = V^T A_+ V, one block row at a time (symmetric: rows jj*p.. of the column-major kp x kp)
+      for (int jj = 0; jj < k; ++jj) {
+        B_LAUNCH(stencil_kernel, (int64_t)nb * N * p, g, Sd, N, nb, Z + (int64_t)jj * p, kp, sZ, Wl, p, N * p, 0.0);
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, kp, (int)N, &one, Wl, p, N * p, Z, kp, sZ, &zero,
+                                                 At + (int64_t)jj * p, kp, kpkp, nb));
       }
-      // B_{j+1}^T = L1 L2
-      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, p, p, &one, L1, p, pp, L2, p, pp, &zero,
-                                               Bt + (int64_t)(jj + 1) * pp, p, (int64_t)k * pp, nb));
+      B_LAUNCH(symmetrize_kernel, (int64_t)nb * kpkp, At, kp, kpkp, nb);
+      // block Lanczos on (A~, E_1 B_1): Q~_1 = E_1, same B_1^T = diag(H^{1/2})
+      B_LAUNCH(eye_block_kernel, (int64_t)nb * kp * p, kp, p, nb, Zh, kpkp);
+      rc = lanczos(Zh, kp, k, thr, [&](int jj, double* W, int ldw, int64_t sW) -> sfm_status {
+        // W^T = Q~_j^T A~ (column-major p x kp)
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, kp, kp, &one, Zh + (int64_t)jj * p, kp, kpkp, At, kp,
+                                                 kpkp, &zero, W, ldw, sW, nb));
+        return SFM_OK;
+      });
+      if (rc != SFM_OK) return rc;
+      // Z = V Z~ in node chunks staged through Wl (column-major: Z^T = Z~^T V^T)
+      const int64_t nc = std::max<int64_t>(1, (N * p) / kp);
+      for (int64_t n0 = 0; n0 < N; n0 += nc) {
+        const int64_t nn = std::min(nc, N - n0);
+        B_LAUNCH(copy_blocks_kernel, (int64_t)nb * nn * kp, Z + n0 * kp, sZ, Wl, N * p, nn * kp, nb, 1.0);
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, kp, (int)nn, kp, &one, Zh, kp, kpkp, Wl, kp, N * p, &zero,
+                                                 Z + n0 * kp, kp, sZ, nb));
+      }
     }
     // a3: S-fraction
     const int64_t sk = (int64_t)k * pp;
@@ -662,7 +1006,6 @@ extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t ns
         status = c->fail(SFM_EBREAKDOWN, "subdomain " + std::to_string(s0 + b) +
                                              ": block Lanczos breakdown or non-SPD Gamma_j");
   }
-  cleanup();
   if (status != SFM_OK) {
     release_roms(c);
     return status;
@@ -682,6 +1025,38 @@ extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t ns
   }
   rc = finalize_roms(c, Hall, src_sub, sv, rec_sub, st);
   if (rc != SFM_OK) return rc;
+  if (cg_iters_out) *cg_iters_out = cg_iters_max;
   c->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return SFM_OK;
+}
+
+}  // namespace
+
+extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t nsrc, const int32_t* src_ijk,
+                                     int32_t nrec, const int32_t* rec_ijk, const float* u0_dev,
+                                     const float* v0_dev, void* stream) {
+  if (!c) return SFM_EINVAL;
+  const ShiftSpec spec{INFINITY, 0.0, 0};
+  const sfm_status rc = build_roms(c, spec, vel_dev, nsrc, src_ijk, nrec, rec_ijk, u0_dev, v0_dev, nullptr, stream);
+  if (rc != SFM_OK) release_roms(c);
+  return rc;
+}
+
+extern "C" sfm_status sfm_build_roms_shifted(sfm_ctx c, double sigma, double cg_rtol, int32_t cg_max_iter,
+                                             const float* vel_dev, int32_t nsrc, const int32_t* src_ijk, int32_t nrec,
+                                             const int32_t* rec_ijk, const float* u0_dev, const float* v0_dev,
+                                             int32_t* cg_iters, void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return c->fail(SFM_EINVAL, "sigma must be positive and finite");
+  if (!(cg_rtol > 0.0 && cg_rtol < 1.0)) return c->fail(SFM_EINVAL, "cg_rtol must lie in (0, 1)");
+  if (cg_max_iter < 1) return c->fail(SFM_EINVAL, "cg_max_iter must be at least 1");
+  if (c->cfg.precision != SFM_PREC_FP64)
+    return c->fail(SFM_EINVAL, "finite-shift ROMs need FP64 coefficient storage (SFM_PREC_FP64): their last "
+                               "S-fraction level is singular along the subdomain's constant mode and FP32 or "
+                               "BF16 rounding makes it indefinite");
+  const ShiftSpec spec{sigma, cg_rtol, cg_max_iter};
+  const sfm_status rc = build_roms(c, spec, vel_dev, nsrc, src_ijk, nrec, rec_ijk, u0_dev, v0_dev, cg_iters, stream);
+  if (rc != SFM_OK) release_roms(c);
+  return rc;
 }

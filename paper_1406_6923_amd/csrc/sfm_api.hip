@@ -141,13 +141,12 @@ sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vec
 
   // streamed tiles
   std::vector<int32_t> wrow, wcol;
-  const bool bf16 = c->cfg.precision == SFM_PREC_BF16_FP32ACC;
-  g.word_map(wrow, wcol, bf16);
+  c->tile_elem = tile_elem_bytes(c->cfg.precision);
+  g.word_map(wrow, wcol, (int)c->tile_elem);
   int32_t* wrow_d = alloc_copy(c, wrow, &e);
   if (e != hipSuccess) return c->fail(SFM_ENOMEM, "word map allocation failed");
   int32_t* wcol_d = alloc_copy(c, wcol, &e);
   if (e != hipSuccess) return c->fail(SFM_ENOMEM, "word map allocation failed");
-  c->tile_elem = bf16 ? 2 : 4;
   const size_t tile_bytes = (size_t)S * (2 * k - 1) * g.words_per_block * c->tile_elem;
   c->tiles_d = c->dalloc(tile_bytes, &e);
   if (!c->tiles_d) return c->fail(SFM_ENOMEM, "coefficient tiles: out of device memory");
@@ -284,6 +283,18 @@ sfm_status sfm_create(const sfm_config* cfg, sfm_ctx* out) {
     g_create_error = msg;
     return SFM_EINVAL;
   }
+  {
+    TileGeometry g;
+    g.init(topo.p, tile_elem_bytes(cfg->precision));
+    const size_t acc = cfg->precision == SFM_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const size_t lds = acc * ((size_t)2 * topo.k * g.P16 + (size_t)topo.k * g.nslots * kTile);
+    if (lds > kMaxLdsBytes) {
+      g_create_error = "k = " + std::to_string(topo.k) + " and p = " + std::to_string(topo.p) + " need " +
+                       std::to_string(lds) + " bytes of LDS per subdomain work-group, above the " +
+                       std::to_string(kMaxLdsBytes) + " of a CU";
+      return SFM_EINVAL;
+    }
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
     g_create_error = "no HIP device available";
@@ -296,7 +307,7 @@ sfm_status sfm_create(const sfm_config* cfg, sfm_ctx* out) {
   }
   c->cfg = *cfg;
   c->topo = topo;
-  c->geo.init(topo.p, cfg->precision == SFM_PREC_BF16_FP32ACC ? 2 : 4);
+  c->geo.init(topo.p, tile_elem_bytes(cfg->precision));
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     g_create_error = "hipGetDevice failed";
@@ -393,7 +404,7 @@ extern "C" sfm_status sfm_query(sfm_ctx c, sfm_info* out) {
   out->nrec = c->nrec;
   out->has_roms = c->has_roms ? 1 : 0;
   out->steps_done = c->n;
-  const int64_t elem = c->cfg.precision == SFM_PREC_FP32 ? 4 : 2;
+  const int64_t elem = tile_elem_bytes(c->cfg.precision);
   out->coef_bytes = (int64_t)t.S * (2 * t.k - 1) * c->geo.words_per_block * elem;
   out->coef_bytes_algorithmic = (int64_t)t.S * (2 * t.k - 1) * ((int64_t)t.p * (t.p + 1) / 2) * elem;
   out->state_bytes = (int64_t)t.S * t.k * t.p * 4;

@@ -6,10 +6,11 @@
 // P16 = 16 * nt rows and cut into 16 x 16 tiles.  Only tiles on or above the
 // diagonal are stored, each in "wrapped diagonal" order: for a tile at block
 // rows 16I.. and columns 16J.., lane i (0..15) holds W_t[i] = A(16I + i, 16J + (i + t) mod 16).
-//   * off-diagonal tile (I < J): t = 0..15, 256 words, stored [v][lane][4] with t = 4v + e
-//     (FP32) or [v][lane][8] (BF16), so each load instruction of a 16-lane row is contiguous;
-//   * diagonal tile (I = J): t = 0..7 in the tile, 128 words, stored [t 0..3][lane][4],
-//     [t 4..7][lane][4] (FP32) or [t 0..7][lane][8] (BF16); its t = 8 half-diagonal (16 lanes,
+//   * off-diagonal tile (I < J): t = 0..15, 256 words, stored [v][lane][e] with t = e v + i,
+//     e = 16 bytes / word size (4 FP32, 8 BF16, 2 FP64), so each load instruction of a
+//     16-lane row reads one contiguous 256-byte segment;
+//   * diagonal tile (I = J): t = 0..7 in the tile, 128 words in the same [v][lane][e]
+//     order; its t = 8 half-diagonal (16 lanes,
 //     each entry present twice) sits in the block's tail, [I][lane], after all tiles, padded
 //     to whole 128-byte lines.  Every tile then starts on a 128-byte line of HBM: a stream
 //     whose rows start 64 bytes into a line reads about 10% slower.
@@ -40,6 +41,13 @@ constexpr int kOffWords = 256;
 constexpr int kLineBytes = 128;
 constexpr int kStepThreads = 256;      // 16 rows of 16 lanes per subdomain work-group
 constexpr int kMaxNt = 16;             // p <= 256
+constexpr size_t kDefaultLdsBytes = 65536;     // dynamic LDS available without a kernel attribute
+constexpr size_t kMaxLdsBytes = 163840;        // LDS of one CU (gfx950), the work-group limit
+
+// Bytes of one stored coefficient word.
+inline int tile_elem_bytes(int precision) {
+  return precision == SFM_PREC_BF16_FP32ACC ? 2 : precision == SFM_PREC_FP64 ? 8 : 4;
+}
 
 // Geometry of the tile stream of one block.
 struct TileGeometry {
@@ -50,7 +58,7 @@ struct TileGeometry {
 
   void init(int p_, int elem_bytes);
   // (row, col) of every stored word of a block, in stream order (row, col may be >= p: padding).
-  void word_map(std::vector<int32_t>& rows, std::vector<int32_t>& cols, bool bf16) const;
+  void word_map(std::vector<int32_t>& rows, std::vector<int32_t>& cols, int elem_bytes) const;
 };
 
 // Decomposition of the global box into equal subdomains and their faces.
@@ -148,7 +156,7 @@ hipError_t launch_pack(const double* blocks, int64_t nblocks_total, int blocks_p
                        const int32_t* wcol, void* tiles, int precision, int S, hipStream_t st);
 hipError_t launch_pad_rows(const double* src, int64_t nrows, int p, int P16, float* dst,
                            hipStream_t st);
-size_t step_lds_bytes(const StepParams& prm);
+size_t step_lds_bytes(const StepParams& prm, int precision);
 hipError_t launch_gather_rows(const double* src, const int32_t* idx, int n, int64_t width, double* dst,
                               hipStream_t st);
 hipError_t launch_norm2(const float* x, int64_t n, double* out, hipStream_t st);

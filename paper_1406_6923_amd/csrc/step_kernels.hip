@@ -31,6 +31,15 @@ __device__ __forceinline__ float row_ror(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + R, 0xF, 0xF, true));
 }
 
+template <int R>
+__device__ __forceinline__ double row_ror(double v) {
+  static_assert(R >= 1 && R <= 15, "rotation amount");
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0x120 + R, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x120 + R, 0xF, 0xF, true);
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
 template <int B, int E, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
   if constexpr (B < E) {
@@ -98,27 +107,68 @@ struct TileIO<uint16_t> {
   }
 };
 
+template <>
+struct TileIO<double> {
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  static constexpr int kDiag = kDiagWords;
+  static constexpr int kOff = kOffWords;
+  __device__ __forceinline__ static void diag(const double* __restrict__ p, const double* __restrict__ h,
+                                              int lane, double (&w)[9]) {
+    const f64x2* q = reinterpret_cast<const f64x2*>(p);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      f64x2 a = __builtin_nontemporal_load(q + v * 16 + lane);
+      w[2 * v] = a.x;
+      w[2 * v + 1] = a.y;
+    }
+    w[8] = __builtin_nontemporal_load(h + lane);
+  }
+  __device__ __forceinline__ static void off(const double* __restrict__ p, int lane, double (&w)[16]) {
+    const f64x2* q = reinterpret_cast<const f64x2*>(p);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      f64x2 a = __builtin_nontemporal_load(q + v * 16 + lane);
+      w[2 * v] = a.x;
+      w[2 * v + 1] = a.y;
+    }
+  }
+};
+
+// Arithmetic type of the products and sums for a stored coefficient type.
+template <typename T>
+struct Acc {
+  typedef float type;
+};
+template <>
+struct Acc<double> {
+  typedef double type;
+};
+
+__device__ __forceinline__ float mad(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double mad(double a, double b, double c) { return fma(a, b, c); }
+
 // ------------------------------------------------------------------ tile products
 // Diagonal tile: y_I[i] += sum_c A(i, c) x_I[c] using W_0..W_8 (symmetric inside the tile).
-__device__ __forceinline__ void diag_tile(const float (&w)[9], float xI, const float (&xr)[16], float& yI) {
-  yI = fmaf(w[0], xI, yI);
+template <typename R>
+__device__ __forceinline__ void diag_tile(const R (&w)[9], R xI, const R (&xr)[16], R& yI) {
+  yI = mad(w[0], xI, yI);
   static_for<1, 8>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
-    yI = fmaf(w[t], row_ror<16 - t>(xI), yI);   // A(i, i+t) x[i+t]
-    yI = fmaf(row_ror<t>(w[t]), xr[t], yI);     // A(i-t, i) x[i-t]
+    yI = mad(w[t], row_ror<16 - t>(xI), yI);   // A(i, i+t) x[i+t]
+    yI = mad(row_ror<t>(w[t]), xr[t], yI);     // A(i-t, i) x[i-t]
   });
-  yI = fmaf(w[8], row_ror<8>(xI), yI);
+  yI = mad(w[8], row_ror<8>(xI), yI);
 }
 
 // Off-diagonal tile (I < J): y_I += A x_J and y_J += A^T x_I.
-__device__ __forceinline__ void off_tile(const float (&w)[16], float xJ, const float (&xr)[16],
-                                         float& yI, float& yJ) {
-  yI = fmaf(w[0], xJ, yI);
-  yJ = fmaf(w[0], xr[0], yJ);
+template <typename R>
+__device__ __forceinline__ void off_tile(const R (&w)[16], R xJ, const R (&xr)[16], R& yI, R& yJ) {
+  yI = mad(w[0], xJ, yI);
+  yJ = mad(w[0], xr[0], yJ);
   static_for<1, 16>([&](auto tc) {
     constexpr int t = decltype(tc)::value;
-    yI = fmaf(w[t], row_ror<16 - t>(xJ), yI);   // A(i, i+t) x_J[i+t]
-    yJ = fmaf(row_ror<t>(w[t]), xr[t], yJ);     // A(c-t, c) x_I[c-t]
+    yI = mad(w[t], row_ror<16 - t>(xJ), yI);   // A(i, i+t) x_J[i+t]
+    yJ = mad(row_ror<t>(w[t]), xr[t], yJ);     // A(c-t, c) x_I[c-t]
   });
 }
 
@@ -129,38 +179,38 @@ __device__ __forceinline__ int tri_index(int I, int J, int nt) {
 // One job: strips g and nt-1-g of one block.  x: block input vector (LDS); part: the
 // block's partial-sum slots (LDS): slot I = row sums of strip I, slot nt + tri(I,J) =
 // transposed contribution of tile (I, J) to segment J.
-template <typename T>
+template <typename T, typename R = typename Acc<T>::type>
 __device__ __forceinline__ void run_job(const T* __restrict__ blk, int job_off, int tail_off, int g, int nt,
-                                        const float* __restrict__ x, float* __restrict__ part, int lane) {
+                                        const R* __restrict__ x, R* __restrict__ part, int lane) {
   const int I0 = g, I1 = nt - 1 - g;
   const int nstrip = (I0 == I1) ? 1 : 2;
   const T* ptr = blk + job_off;
   for (int st = 0; st < nstrip; ++st) {
     const int I = st ? I1 : I0;
-    const float xI = x[kTile * I + lane];
-    float xr[16];
+    const R xI = x[kTile * I + lane];
+    R xr[16];
     xr[0] = xI;
     static_for<1, 16>([&](auto tc) {
       constexpr int t = decltype(tc)::value;
       xr[t] = row_ror<t>(xI);
     });
-    float yI = 0.f;
+    R yI = 0;
     {
-      float w[9];
+      R w[9];
       TileIO<T>::diag(ptr, blk + tail_off + kHalfDiagWords * I, lane, w);
       ptr += TileIO<T>::kDiag;
       diag_tile(w, xI, xr, yI);
     }
-    float wn[16];
+    R wn[16];
     if (I + 1 < nt) TileIO<T>::off(ptr, lane, wn);
     for (int J = I + 1; J < nt; ++J) {
-      float w[16];
+      R w[16];
 #pragma unroll
       for (int t = 0; t < 16; ++t) w[t] = wn[t];
       ptr += TileIO<T>::kOff;
       if (J + 1 < nt) TileIO<T>::off(ptr, lane, wn);   // prefetch the next tile
-      const float xJ = x[kTile * J + lane];
-      float yJ = 0.f;
+      const R xJ = x[kTile * J + lane];
+      R yJ = 0;
       off_tile(w, xJ, xr, yI, yJ);
       part[(nt + tri_index(I, J, nt)) * kTile + lane] = yJ;
     }
@@ -170,9 +220,9 @@ __device__ __forceinline__ void run_job(const T* __restrict__ blk, int job_off, 
 
 // All jobs of nb consecutive blocks.  The four rows of a wave take the same job shape g
 // on four different blocks so that their control flow is identical.
-template <typename T>
+template <typename T, typename R = typename Acc<T>::type>
 __device__ __forceinline__ void run_phase(const T* __restrict__ tiles, int nb, const StepParams& prm,
-                                          const float* xs, int vstride, float* part, int tid) {
+                                          const R* xs, int vstride, R* part, int tid) {
   const int lane = tid & 15;
   const int rw = (tid >> 4) & 3;
   const int wave = tid >> 6;
@@ -182,30 +232,33 @@ __device__ __forceinline__ void run_phase(const T* __restrict__ tiles, int nb, c
     const int g = grp / per_g;
     const int b = (grp - g * per_g) * 4 + rw;
     if (b < nb) {
-      run_job<T>(tiles + b * prm.words_per_block, prm.job_off[g], prm.tail_off, g, prm.nt, xs + b * vstride,
+      run_job<T, R>(tiles + b * prm.words_per_block, prm.job_off[g], prm.tail_off, g, prm.nt, xs + b * vstride,
                  part + b * prm.nslots * kTile, lane);
     }
   }
 }
 
-__device__ __forceinline__ float reduce_entry(const float* part, int b, int i, int nt, int nslots) {
+template <typename R>
+__device__ __forceinline__ R reduce_entry(const R* part, int b, int i, int nt, int nslots) {
   const int J = i >> 4, c = i & 15;
-  const float* pb = part + b * nslots * kTile;
-  float v = pb[J * kTile + c];
+  const R* pb = part + b * nslots * kTile;
+  R v = pb[J * kTile + c];
   for (int I = 0; I < J; ++I) v += pb[(nt + tri_index(I, J, nt)) * kTile + c];
   return v;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kStepThreads) void step_main_kernel(StepParams prm) {
-  extern __shared__ float smem[];
+  typedef typename Acc<T>::type R;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* smem = reinterpret_cast<R*>(smem_raw);
   const int s = blockIdx.x;
   const int tid = threadIdx.x;
   const int k = prm.k, P = prm.P16;
   const int vstride = P;
-  float* xs = smem;                       // [k][P]   block inputs
-  float* ph = xs + k * vstride;           // [k][P]   layer fluxes phi_j
-  float* part = ph + k * vstride;         // [k][nslots][16]
+  R* xs = smem;                           // [k][P]   block inputs
+  R* ph = xs + k * vstride;               // [k][P]   layer fluxes phi_j
+  R* part = ph + k * vstride;             // [k][nslots][16]
   const size_t sbase = (size_t)s * k * P;
   const float* Uin = prm.mode == 0 ? prm.U : prm.Uin;
   const T* tiles = reinterpret_cast<const T*>(prm.tiles) + (size_t)s * prm.words_per_sub;
@@ -213,42 +266,42 @@ __global__ __launch_bounds__(kStepThreads) void step_main_kernel(StepParams prm)
   // U_{j+1} - U_j with U_{k+1} = 0
   for (int e = tid; e < k * P; e += kStepThreads) {
     const int j = e / P;
-    const float u = Uin[sbase + e];
-    const float un = (j + 1 < k) ? Uin[sbase + e + P] : 0.f;
+    const R u = Uin[sbase + e];
+    const R un = (j + 1 < k) ? (R)Uin[sbase + e + P] : (R)0;
     xs[e] = un - u;
   }
   __syncthreads();
-  run_phase<T>(tiles, k, prm, xs, vstride, part, tid);          // phi_j = Gamma_j dU_j
+  run_phase<T, R>(tiles, k, prm, xs, vstride, part, tid);       // phi_j = Gamma_j dU_j
   __syncthreads();
   for (int e = tid; e < k * P; e += kStepThreads) {
     const int b = e / P, i = e - b * P;
     ph[e] = reduce_entry(part, b, i, prm.nt, prm.nslots);
   }
   __syncthreads();
-  for (int e = tid; e < P; e += kStepThreads) prm.exch[(size_t)s * P + e] = ph[e];   // step 2.1
+  for (int e = tid; e < P; e += kStepThreads) prm.exch[(size_t)s * P + e] = (float)ph[e];   // step 2.1
   for (int e = tid; e < (k - 1) * P; e += kStepThreads) xs[e] = ph[e + P] - ph[e];   // phi_j - phi_{j-1}
   __syncthreads();
-  run_phase<T>(tiles + (size_t)k * prm.words_per_block, k - 1, prm, xs, vstride, part, tid);
+  run_phase<T, R>(tiles + (size_t)k * prm.words_per_block, k - 1, prm, xs, vstride, part, tid);
   __syncthreads();
   const int slot = (prm.mode == 0 && prm.hist) ? prm.hist_slot[s] : -1;
   const int s0 = prm.src_off ? prm.src_off[s] : 0;
   const int s1 = prm.src_off ? prm.src_off[s + 1] : 0;
   for (int e = tid; e < (k - 1) * P; e += kStepThreads) {
     const int b = e / P, i = e - b * P;
-    float a = reduce_entry(part, b, i, prm.nt, prm.nslots);
+    R a = reduce_entry(part, b, i, prm.nt, prm.nslots);
     for (int q = s0; q < s1; ++q) {
       const int src = prm.src_ids[q];
-      a = fmaf(prm.wavelet[prm.step * prm.nsrc + src], prm.src_vec[((size_t)src * k + b + 1) * P + i], a);
+      a = mad((R)prm.wavelet[prm.step * prm.nsrc + src], (R)prm.src_vec[((size_t)src * k + b + 1) * P + i], a);
     }
     const size_t idx = sbase + (size_t)(b + 1) * P + i;
     if (prm.mode == 0) {
-      const float d = fmaf(prm.dt2, a, prm.D[idx]);
+      const float d = (float)mad((R)prm.dt2, a, (R)prm.D[idx]);
       const float un = prm.U[idx] + d;
       prm.D[idx] = d;
       prm.U[idx] = un;
       if (slot >= 0) prm.hist[prm.hist_off + ((size_t)slot * k + b + 1) * P + i] = un;
     } else {
-      prm.Aout[idx] = a;
+      prm.Aout[idx] = (float)a;
     }
   }
 }
@@ -302,7 +355,9 @@ __global__ void pack_kernel(const double* __restrict__ blocks, int k, int p, int
     const int r = wrow[w], c = wcol[w];
     double v = 0.0;
     if (r < p && c < p) v = blocks[((((size_t)s * 2 + which) * k + j) * p + r) * p + c];
-    if constexpr (std::is_same<T, float>::value) {
+    if constexpr (std::is_same<T, double>::value) {
+      out[idx] = v;
+    } else if constexpr (std::is_same<T, float>::value) {
       out[idx] = (float)v;
     } else {
       out[idx] = __bfloat16_as_ushort(__float2bfloat16((float)v));
@@ -354,18 +409,28 @@ __global__ void scale_kernel(const float* __restrict__ x, int64_t n, const doubl
 
 }  // namespace
 
-size_t step_lds_bytes(const StepParams& prm) {
-  return sizeof(float) * ((size_t)2 * prm.k * prm.P16 + (size_t)prm.k * prm.nslots * kTile);
+size_t step_lds_bytes(const StepParams& prm, int precision) {
+  const size_t acc = precision == SFM_PREC_FP64 ? sizeof(double) : sizeof(float);
+  return acc * ((size_t)2 * prm.k * prm.P16 + (size_t)prm.k * prm.nslots * kTile);
+}
+
+template <typename T>
+static hipError_t launch_main_t(const StepParams& prm, size_t lds, hipStream_t st) {
+  if (lds > kDefaultLdsBytes) {
+    // beyond the default dynamic-LDS limit (the work-group limit is kMaxLdsBytes, checked at create)
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&step_main_kernel<T>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(step_main_kernel<T>, dim3(prm.S), dim3(kStepThreads), lds, st, prm);
+  return hipGetLastError();
 }
 
 hipError_t launch_step_main(const StepParams& prm, int precision, hipStream_t st) {
-  const size_t lds = step_lds_bytes(prm);
-  if (precision == SFM_PREC_FP32) {
-    hipLaunchKernelGGL(step_main_kernel<float>, dim3(prm.S), dim3(kStepThreads), lds, st, prm);
-  } else {
-    hipLaunchKernelGGL(step_main_kernel<uint16_t>, dim3(prm.S), dim3(kStepThreads), lds, st, prm);
-  }
-  return hipGetLastError();
+  const size_t lds = step_lds_bytes(prm, precision);
+  if (precision == SFM_PREC_FP32) return launch_main_t<float>(prm, lds, st);
+  if (precision == SFM_PREC_FP64) return launch_main_t<double>(prm, lds, st);
+  return launch_main_t<uint16_t>(prm, lds, st);
 }
 
 hipError_t launch_step_face(const FaceParams& prm, hipStream_t st) {
@@ -384,6 +449,9 @@ hipError_t launch_pack(const double* blocks, int64_t /*nblocks_total*/, int /*bl
   if (precision == SFM_PREC_FP32) {
     hipLaunchKernelGGL(pack_kernel<float>, dim3(grid), dim3(threads), 0, st, blocks, k, p, geo.words_per_block,
                        wrow, wcol, reinterpret_cast<float*>(tiles), S);
+  } else if (precision == SFM_PREC_FP64) {
+    hipLaunchKernelGGL(pack_kernel<double>, dim3(grid), dim3(threads), 0, st, blocks, k, p, geo.words_per_block,
+                       wrow, wcol, reinterpret_cast<double*>(tiles), S);
   } else {
     hipLaunchKernelGGL(pack_kernel<uint16_t>, dim3(grid), dim3(threads), 0, st, blocks, k, p,
                        geo.words_per_block, wrow, wcol, reinterpret_cast<uint16_t*>(tiles), S);

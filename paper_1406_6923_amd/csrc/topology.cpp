@@ -32,27 +32,17 @@ void TileGeometry::init(int p_, int elem_bytes) {
   words_per_block = off + ((int64_t)kHalfDiagWords * nt + line - 1) / line * line;
 }
 
-// Lane and diagonal index (t) of word w of a diagonal / off-diagonal tile in the stored order.
-static void diag_word(int w, bool bf16, int& lane, int& t) {
-  if (bf16) { lane = w / 8; t = w % 8; return; }
-  const int v = w / 64, rem = w % 64;
-  lane = rem / 4;
-  t = 4 * v + rem % 4;
+// Lane and diagonal index (t) of word w of a tile in the stored order: every load
+// instruction of a 16-lane row reads 16 bytes per lane, i.e. e = 16 / elem_bytes
+// consecutive t of one lane; word w = (v * 16 + lane) * e + (t - v * e).
+static void tile_word(int w, int elem_bytes, int& lane, int& t) {
+  const int e = 16 / elem_bytes;
+  const int v = w / (16 * e), rem = w % (16 * e);
+  lane = rem / e;
+  t = e * v + rem % e;
 }
 
-static void off_word(int w, bool bf16, int& lane, int& t) {
-  if (bf16) {
-    const int v = w / 128, rem = w % 128;
-    lane = rem / 8;
-    t = 8 * v + rem % 8;
-    return;
-  }
-  const int v = w / 64, rem = w % 64;
-  lane = rem / 4;
-  t = 4 * v + rem % 4;
-}
-
-void TileGeometry::word_map(std::vector<int32_t>& rows, std::vector<int32_t>& cols, bool bf16) const {
+void TileGeometry::word_map(std::vector<int32_t>& rows, std::vector<int32_t>& cols, int elem_bytes) const {
   rows.clear();
   cols.clear();
   rows.reserve(words_per_block);
@@ -64,14 +54,14 @@ void TileGeometry::word_map(std::vector<int32_t>& rows, std::vector<int32_t>& co
       const int I = strips[si];
       for (int w = 0; w < kDiagWords; ++w) {
         int lane, t;
-        diag_word(w, bf16, lane, t);
+        tile_word(w, elem_bytes, lane, t);
         rows.push_back(kTile * I + lane);
         cols.push_back(kTile * I + (lane + t) % kTile);
       }
       for (int J = I + 1; J < nt; ++J) {
         for (int w = 0; w < kOffWords; ++w) {
           int lane, t;
-          off_word(w, bf16, lane, t);
+          tile_word(w, elem_bytes, lane, t);
           rows.push_back(kTile * I + lane);
           cols.push_back(kTile * J + (lane + t) % kTile);
         }
@@ -109,7 +99,8 @@ std::string Topology::init(const sfm_config& cfg) {
   if (!(cfg.h > 0.0)) return "h must be positive";
   if (cfg.m < 1) return "m must be at least 1";
   if (cfg.k < 2) return "k must be at least 2";
-  if (cfg.precision != SFM_PREC_FP32 && cfg.precision != SFM_PREC_BF16_FP32ACC) return "unknown precision";
+  if (cfg.precision != SFM_PREC_FP32 && cfg.precision != SFM_PREC_BF16_FP32ACC && cfg.precision != SFM_PREC_FP64)
+    return "unknown precision";
   if (cfg.build_batch < 0) return "build_batch must be >= 0";
   m = cfg.m;
   k = cfg.k;

@@ -24,10 +24,12 @@ SFM_ENOMEM = -3
 SFM_EBREAKDOWN = -4
 SFM_ESTATE = -5
 SFM_EUNSTABLE = -6
+SFM_ENOCONV = -7
 STATUS_NAMES = {0: "SFM_OK", -1: "SFM_EINVAL", -2: "SFM_EHIP", -3: "SFM_ENOMEM",
-                -4: "SFM_EBREAKDOWN", -5: "SFM_ESTATE", -6: "SFM_EUNSTABLE"}
+                -4: "SFM_EBREAKDOWN", -5: "SFM_ESTATE", -6: "SFM_EUNSTABLE", -7: "SFM_ENOCONV"}
 SFM_PREC_FP32 = 0
 SFM_PREC_BF16_FP32ACC = 1
+SFM_PREC_FP64 = 2
 
 
 class sfm_config(ctypes.Structure):
@@ -65,6 +67,8 @@ SIGNATURES = {
     "sfm_last_error": (ctypes.c_char_p, [_VP]),
     "sfm_query": (_I32, [_VP, ctypes.POINTER(sfm_info)]),
     "sfm_build_roms": (_I32, [_VP, _VP, _I32, _VP, _I32, _VP, _VP, _VP, _VP]),
+    "sfm_build_roms_shifted": (_I32, [_VP, _D, _D, _I32, _VP, _I32, _VP, _I32, _VP, _VP, _VP,
+                                      ctypes.POINTER(_I32), _VP]),
     "sfm_reset_state": (_I32, [_VP, _D, _VP]),
     "sfm_load_roms": (_I32, [_VP, _VP, _VP, _I32, _VP, _VP, _I32, _VP, _VP]),
     "sfm_export_roms": (_I32, [_VP, _VP, _VP]),
@@ -164,6 +168,18 @@ def sfm_build_roms(ctx: int, vel, src_ijk=None, rec_ijk=None, u0=None, v0=None, 
     rec = _host(np.zeros((0, 3)) if rec_ijk is None else rec_ijk, np.int32).reshape(-1, 3)
     _check(ctx, load_library().sfm_build_roms(ctx, _dev(vel), len(src), _ptr(src), len(rec), _ptr(rec),
                                               _dev(u0), _dev(v0), _stream(stream)))
+
+
+def sfm_build_roms_shifted(ctx: int, sigma: float, vel, src_ijk=None, rec_ijk=None, u0=None, v0=None,
+                           cg_rtol: float = 1e-12, cg_max_iter: int = 5000, stream=None) -> int:
+    """Finite-shift build; returns the largest inner CG iteration count."""
+    src = _host(np.zeros((0, 3)) if src_ijk is None else src_ijk, np.int32).reshape(-1, 3)
+    rec = _host(np.zeros((0, 3)) if rec_ijk is None else rec_ijk, np.int32).reshape(-1, 3)
+    iters = _I32(0)
+    _check(ctx, load_library().sfm_build_roms_shifted(ctx, float(sigma), float(cg_rtol), int(cg_max_iter), _dev(vel),
+                                                      len(src), _ptr(src), len(rec), _ptr(rec), _dev(u0), _dev(v0),
+                                                      ctypes.byref(iters), _stream(stream)))
+    return int(iters.value)
 
 
 def sfm_reset_state(ctx: int, dt: float, stream=None) -> None:

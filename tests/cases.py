@@ -10,9 +10,8 @@ import workloads as W
 from oracle import coupled, grid, lanczos, rom, sfraction, subdomains
 
 
-@functools.lru_cache(maxsize=4)
-def oracle_case(name: str = "small", sigma: float = np.inf):
-    """Build the oracle ROMs and coupled system of a named workload."""
+def case_config(name: str) -> W.Workload:
+    """Workload of a named parity case."""
     if name == "small":
         cfg = W.CFG_SMALL
     elif name == "ragged":
@@ -25,6 +24,13 @@ def oracle_case(name: str = "small", sigma: float = np.inf):
         cfg = W.scaled_large((2, 2, 1), nsteps=150)
     else:
         raise KeyError(name)
+    return cfg
+
+
+@functools.lru_cache(maxsize=4)
+def oracle_case(name: str = "small", sigma: float = np.inf):
+    """Build the oracle ROMs and coupled system of a named workload."""
+    cfg = case_config(name)
     if cfg.velocity == "layered_inclusions":
         c = W.layered_inclusions_velocity(cfg.nodes, seed=cfg.seed, n_spheres=6,
                                           radius_range=(2.0, 8.0))
@@ -62,7 +68,34 @@ def rel_l2(a, b) -> float:
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def perturbation_profile(sd, r, delta: float = 1e-15, seed: int = 1) -> np.ndarray:
+def _level_changes(sf, r) -> np.ndarray:
+    out = np.empty(r.k)
+    for j in range(r.k):
+        out[j] = max(np.abs(sf.gamma[j] - r.sf.gamma[j]).max() / np.abs(r.sf.gamma[j]).max(),
+                     np.abs(sf.gamma_hat[j] - r.sf.gamma_hat[j]).max() / np.abs(r.sf.gamma_hat[j]).max())
+    return out
+
+
+def solve_perturbation_profile(sd, r, sigma: float, rtol: float, seed: int = 2) -> np.ndarray:
+    """Per-level change of the finite-shift coefficients when every shifted solve is inexact.
+
+    An iterative solve stopped at |b - (A_+ + sigma) x| <= rtol |b| returns the exact solution
+    for a right-hand side moved by a residual of relative size rtol; the oracle is rebuilt with
+    each column of every right-hand side moved by a random vector of exactly that size.  The
+    result is the coefficient change a correct solver at that tolerance can produce."""
+    rng = np.random.default_rng(seed)
+
+    def noisy(solve, X):
+        X = np.asarray(X)
+        R = rng.standard_normal(X.shape)
+        R *= rtol * np.linalg.norm(X, axis=0) / np.linalg.norm(R, axis=0)
+        return solve(X + R)
+
+    sf = sfraction.sfraction(lanczos.lanczos_rational(sd.A_plus(), sd.F(), r.k, sigma, solve_hook=noisy))
+    return _level_changes(sf, r)
+
+
+def perturbation_profile(sd, r, delta: float = 1e-15, seed: int = 1, sigma: float = np.inf) -> np.ndarray:
     """Per-level reproducibility of the S-fraction coefficients in FP64.
 
     The subdomain operator's entries are perturbed by a symmetric relative noise of size delta
@@ -77,12 +110,11 @@ def perturbation_profile(sd, r, delta: float = 1e-15, seed: int = 1) -> np.ndarr
     noise[upper] = delta * rng.standard_normal(int(upper.sum()))
     Ap = sp.coo_matrix((A.data * (1 + noise), (A.row, A.col)), shape=A.shape).tocsr()
     Ap = (sp.triu(Ap) + sp.triu(Ap, 1).T).tocsr()
-    sf = sfraction.sfraction(lanczos.lanczos_infinite(Ap, sd.F(), r.k))
-    out = np.empty(r.k)
-    for j in range(r.k):
-        out[j] = max(np.abs(sf.gamma[j] - r.sf.gamma[j]).max() / np.abs(r.sf.gamma[j]).max(),
-                     np.abs(sf.gamma_hat[j] - r.sf.gamma_hat[j]).max() / np.abs(r.sf.gamma_hat[j]).max())
-    return out
+    if np.isinf(sigma):
+        tri = lanczos.lanczos_infinite(Ap, sd.F(), r.k)
+    else:
+        tri = lanczos.lanczos_rational(Ap, sd.F(), r.k, sigma)
+    return _level_changes(sfraction.sfraction(tri), r)
 
 
 def level_tolerance(profile: np.ndarray) -> np.ndarray:
@@ -97,3 +129,55 @@ def case_level_tolerance(name: str) -> np.ndarray:
     picks = sorted({0, len(subs) - 1})
     prof = np.max([perturbation_profile(subs[i], roms[i]) for i in picks], axis=0)
     return level_tolerance(prof)
+
+
+# Shift of the finite-sigma cases in units of (2 pi f_peak)^2, the squared peak angular frequency.
+# At k = 16, p = 96 the S-fraction of the rational space for (2 pi f_peak)^2 is not positive
+# definite even in FP64 (Gamma_15 has an eigenvalue ratio of 5e-17 and Gamma-hat_16 a negative
+# eigenvalue on the 33^3 case): the coefficients spread geometrically over the levels, faster
+# the closer the shift is to the bottom of the spectrum; 16 (2 pi f_peak)^2 keeps every level
+# positive definite with ratios above 1e-12 there.
+SIGMA_FACTOR = {"small": 1.0, "ragged": 1.0, "mid": 16.0}
+
+
+def case_sigma(name: str, factor: float = None) -> float:
+    """Shift of a finite-sigma case: SIGMA_FACTOR[name] (or factor) times (2 pi f_peak)^2."""
+    f = SIGMA_FACTOR[name] if factor is None else factor
+    return float(f * (2.0 * np.pi * case_config(name).f_peak) ** 2)
+
+
+@functools.lru_cache(maxsize=4)
+def shifted_level_tolerance(name: str, rtol: float) -> np.ndarray:
+    """Per-level tolerance of a finite-sigma build with inner solves at rtol: 30 times the larger of
+    the FP64 operator-perturbation response and the inexact-solve response, over two subdomains."""
+    sigma = case_sigma(name)
+    cfg, c, subs, roms, cs = oracle_case(name, sigma)
+    picks = sorted({0, len(subs) - 1})
+    prof = np.max([np.maximum(perturbation_profile(subs[i], roms[i], sigma=sigma),
+                              solve_perturbation_profile(subs[i], roms[i], sigma, rtol)) for i in picks], axis=0)
+    return level_tolerance(prof)
+
+
+def interpolation_error(sd, sf, sigma: float) -> float:
+    """Relative Frobenius error of a ROM's NtD map against the exact one at s^2 = sigma."""
+    s = float(np.sqrt(sigma))
+    exact = sfraction.ntd_resolvent(sd.A_plus(), sd.F(), s)
+    return float(np.linalg.norm(sfraction.ntd_continued_fraction(sf, s) - exact) / np.linalg.norm(exact))
+
+
+def shifted_interp_tolerance(sd, r, sigma: float, rtol: float, seed: int = 3) -> float:
+    """Bound on the interpolation error at s^2 = sigma of a finite-shift ROM built with inner solves
+    at rtol: 30 times the larger of the oracle ROM's error and that of an oracle ROM whose every
+    shifted solve carries a residual of relative size rtol (as in solve_perturbation_profile)."""
+    rng = np.random.default_rng(seed)
+
+    def noisy(solve, X):
+        X = np.asarray(X)
+        R = rng.standard_normal(X.shape)
+        R *= rtol * np.linalg.norm(X, axis=0) / np.linalg.norm(R, axis=0)
+        return solve(X + R)
+
+    sf_noisy = sfraction.sfraction(lanczos.lanczos_rational(sd.A_plus(), sd.F(), r.k, sigma, solve_hook=noisy))
+    e = max(interpolation_error(sd, r.sf, sigma), interpolation_error(sd, sf_noisy, sigma), 1e-15)
+    return 30.0 * e
+

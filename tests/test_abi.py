@@ -47,6 +47,8 @@ def test_struct_layouts_match_header():
     (dict(precision=7), "precision"),
     (dict(m=25, ncell=(8, 8, 8), sub_cells=(4, 4, 4)), "patch"),
     (dict(m=4, k=300), "exceeds"),
+    # FP64 blocks of p = 96 at k = 40 need 169 KB of LDS per work-group
+    (dict(m=16, k=40, precision=2), "LDS"),
 ])
 def test_create_rejects_bad_config_without_gpu(kwargs, fragment):
     args = dict(ncell=(32, 32, 32), sub_cells=(16, 16, 16), h=10.0, m=4, k=8, precision=0)
