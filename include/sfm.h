@@ -243,6 +243,35 @@ const char* sfm_fdtd_last_error(void);
  * (2k-1) p^2 words per subdomain), one thread per row, no receivers.  Advances the context state. */
 sfm_status sfm_step_plain(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet_dev, void* stream);
 
+/* ---- many shots through the same ROMs (Stage 2 with a 64-column right-hand side) ----
+ * The S-fraction blocks do not depend on the source, so up to 64 shots share one pass over
+ * the coefficient stream per step: the block products of eq. "intrtstep" become (6m x 6m) x
+ * (6m x 64) products on the FP32 matrix cores.  Shot n is driven by source shot_src[n] of the
+ * last sfm_build_roms / sfm_load_roms (its own wavelet column) and recorded at every receiver.
+ * Requires SFM_PREC_FP32 and 6m <= 112.  The single-shot state (sfm_step) is independent. */
+
+/* Allocate and zero the shot state (U^0 = U^{-1} = 0) for nshot shots (1..64).
+ *   shot_src  host, int32 [nshot]: source index driving each shot (-1: no source), or NULL
+ *             for shot n <- source n (then nshot <= nsrc).  A source drives at most one shot.
+ * Synchronizes.  Errors: SFM_ESTATE (no ROMs), SFM_EINVAL, SFM_ENOMEM. */
+sfm_status sfm_shots_init(sfm_ctx ctx, int32_t nshot, const int32_t* shot_src, void* stream);
+
+/* nsteps leapfrog steps of every shot (as sfm_step, per shot).
+ *   wavelet_dev  device, float [nsteps][nshot]: amplitude of each shot's source at t_n
+ *   traces_dev   device, float [nshot][nrec][ld] or NULL: receiver samples, column n = step n
+ * Errors: SFM_ESTATE (no shot state), SFM_EINVAL, SFM_EUNSTABLE (dt above sfm_cfl_dt's limit). */
+sfm_status sfm_shots_step(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet_dev, float* traces_dev,
+                          int64_t ld, void* stream);
+
+/* Copy the shot state U^n and D = U^n - U^{n-1} to / from host arrays float [S][k][p][nshot].
+ * Synchronize.  Errors: SFM_ESTATE, SFM_EINVAL. */
+sfm_status sfm_shots_get_state(sfm_ctx ctx, float* u_host, float* d_host);
+sfm_status sfm_shots_set_state(sfm_ctx ctx, const float* u_host, const float* d_host);
+
+/* Device times of the shot kernels summed over the steps run while sfm_set_timing was on:
+ * *timed_steps, ms3 = {main, face, record}; then resets the counters.  Never fails for a valid ctx. */
+sfm_status sfm_shots_timing(sfm_ctx ctx, int64_t* timed_steps, double* ms3);
+
 #ifdef __cplusplus
 }
 #endif

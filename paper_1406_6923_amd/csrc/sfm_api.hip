@@ -62,6 +62,9 @@ namespace sfm {
 
 // Drop every ROM-dependent buffer (before a new build or load).
 void release_roms(sfm_ctx c) {
+  release_shots(c);
+  c->dfree(c->wmap_d);
+  c->wmap_d = nullptr;
   void* bufs[] = {c->tiles_d, c->coef64_d, c->src_vec_d, c->src_vec64_d, c->src_off_d, c->src_ids_d,
                   c->sw_off_d, c->sw_q_d, c->sw_src_d, c->sw_w_d, c->rec_sub_d, c->rec_rows_d,
                   c->rec_rows64_d, c->U0_d, c->V0_d, c->rec_perm_d, c->rs_off_d, c->hist_slot_d,
@@ -147,6 +150,13 @@ sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vec
   if (e != hipSuccess) return c->fail(SFM_ENOMEM, "word map allocation failed");
   int32_t* wcol_d = alloc_copy(c, wcol, &e);
   if (e != hipSuccess) return c->fail(SFM_ENOMEM, "word map allocation failed");
+  {
+    std::vector<uint32_t> wmap(wrow.size());
+    for (size_t i = 0; i < wrow.size(); ++i) wmap[i] = ((uint32_t)wrow[i] << 16) | (uint32_t)wcol[i];
+    c->dfree(c->wmap_d);
+    c->wmap_d = alloc_copy(c, wmap, &e);
+    if (e != hipSuccess) return c->fail(SFM_ENOMEM, "word map allocation failed");
+  }
   const size_t tile_bytes = (size_t)S * (2 * k - 1) * g.words_per_block * c->tile_elem;
   c->tiles_d = c->dalloc(tile_bytes, &e);
   if (!c->tiles_d) return c->fail(SFM_ENOMEM, "coefficient tiles: out of device memory");

@@ -41,6 +41,7 @@ constexpr int kOffWords = 256;
 constexpr int kLineBytes = 128;
 constexpr int kStepThreads = 256;      // 16 rows of 16 lanes per subdomain work-group
 constexpr int kMaxNt = 16;             // p <= 256
+constexpr int kShotCols = 64;                  // shots per multi-shot state row (the MFMA N dimension)
 constexpr size_t kDefaultLdsBytes = 65536;     // dynamic LDS available without a kernel attribute
 constexpr size_t kMaxLdsBytes = 163840;        // LDS of one CU (gfx950), the work-group limit
 
@@ -169,6 +170,7 @@ sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vec
                          const std::vector<double>& src_vec_host, const std::vector<int32_t>& rec_sub,
                          hipStream_t st);
 void release_roms(sfm_ctx c);
+void release_shots(sfm_ctx c);
 void destroy_blas(sfm_ctx c);
 
 }  // namespace sfm
@@ -187,6 +189,7 @@ struct sfm_ctx_s {
   void* tiles_d = nullptr;
   double* coef64_d = nullptr;       // [S][2][k][p][p]: Gamma_j at [.][0], Gamma-hat_j at [.][1]
   size_t tile_elem = 4;             // bytes per streamed coefficient word
+  uint32_t* wmap_d = nullptr;       // [words_per_block]: (row << 16) | col of every stored word
   float* C_d = nullptr;             // [S][P16]
   float* U_d = nullptr;             // [S][k][P16]
   float* D_d = nullptr;
@@ -216,6 +219,15 @@ struct sfm_ctx_s {
   float* hist_d = nullptr;          // [kHistWindow][n_rs][k][P16]
   float* plain_blocks_d = nullptr;  // comparator only: full FP32 blocks [S][2k-1][p][p]
   double* rec_rows64_d = nullptr;   // [nrec][k][p]
+  // many shots (sfm_shots_*): state [S][k][P16][64], exchange [S][P16][64]
+  int nshot = 0;
+  float* Us_d = nullptr;
+  float* Ds_d = nullptr;
+  float* exch_s_d = nullptr;
+  int32_t* src_shot_d = nullptr;    // [nsrc] shot driven by each source, -1 if none
+  int64_t shots_n = 0;
+  int64_t shots_timed = 0;
+  double shots_ms[3] = {0, 0, 0};   // main, face, record
   // scratch
   double* red_d = nullptr;          // reduction scratch
   float* work_a_d = nullptr;        // [S][k][P16] operator scratch

@@ -70,6 +70,11 @@ SIGNATURES = {
     "sfm_build_roms_shifted": (_I32, [_VP, _D, _D, _I32, _VP, _I32, _VP, _I32, _VP, _VP, _VP,
                                       ctypes.POINTER(_I32), _VP]),
     "sfm_reset_state": (_I32, [_VP, _D, _VP]),
+    "sfm_shots_init": (_I32, [_VP, _I32, _VP, _VP]),
+    "sfm_shots_step": (_I32, [_VP, _I32, _D, _VP, _VP, _I64, _VP]),
+    "sfm_shots_get_state": (_I32, [_VP, _VP, _VP]),
+    "sfm_shots_set_state": (_I32, [_VP, _VP, _VP]),
+    "sfm_shots_timing": (_I32, [_VP, ctypes.POINTER(_I64), _VP]),
     "sfm_load_roms": (_I32, [_VP, _VP, _VP, _I32, _VP, _VP, _I32, _VP, _VP]),
     "sfm_export_roms": (_I32, [_VP, _VP, _VP]),
     "sfm_export_projections": (_I32, [_VP, _VP, _VP]),
@@ -227,6 +232,45 @@ def sfm_step(ctx: int, nsteps: int, dt: float, wavelet=None, traces=None, ld: Op
         ld = traces.shape[-1] if traces is not None else 0
     _check(ctx, load_library().sfm_step(ctx, int(nsteps), float(dt), _dev(wavelet), _dev(traces), int(ld),
                                         _stream(stream)))
+
+
+def sfm_shots_init(ctx: int, nshot: int, shot_src=None, stream=None) -> None:
+    arr = None if shot_src is None else _host(shot_src, np.int32).reshape(-1)
+    if arr is not None and len(arr) != nshot:
+        raise ValueError("shot_src needs one entry per shot")
+    _check(ctx, load_library().sfm_shots_init(ctx, int(nshot), _ptr(arr) if arr is not None else None,
+                                              _stream(stream)))
+
+
+def sfm_shots_step(ctx: int, nsteps: int, dt: float, wavelet=None, traces=None, ld: Optional[int] = None,
+                   stream=None) -> None:
+    """wavelet: device float [nsteps][nshot]; traces: device float [nshot][nrec][ld] or None."""
+    if ld is None:
+        ld = traces.shape[-1] if traces is not None else 0
+    _check(ctx, load_library().sfm_shots_step(ctx, int(nsteps), float(dt), _dev(wavelet), _dev(traces), int(ld),
+                                              _stream(stream)))
+
+
+def sfm_shots_get_state(ctx: int, nshot: int):
+    info = sfm_query(ctx)
+    u = np.empty((info["n_subdomains"], info["k"], info["p"], nshot), np.float32)
+    d = np.empty_like(u)
+    _check(ctx, load_library().sfm_shots_get_state(ctx, _ptr(u), _ptr(d)))
+    return u, d
+
+
+def sfm_shots_set_state(ctx: int, u, d) -> None:
+    u = _host(u, np.float32)
+    d = _host(d, np.float32)
+    _check(ctx, load_library().sfm_shots_set_state(ctx, _ptr(u), _ptr(d)))
+
+
+def sfm_shots_timing(ctx: int):
+    """(timed_steps, [main_ms, face_ms, record_ms]) summed since the last call."""
+    n = _I64(0)
+    ms = np.zeros(3, np.float64)
+    _check(ctx, load_library().sfm_shots_timing(ctx, ctypes.byref(n), _ptr(ms)))
+    return int(n.value), ms
 
 
 def sfm_record_receivers(ctx: int, out, stream=None) -> None:

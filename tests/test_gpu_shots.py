@@ -1,0 +1,139 @@
+"""GPU parity of the many-shot step (64-column MFMA block products) against the FP64 oracle.
+
+Every shot is an independent run of Algorithm 1, Stage 2 through the same ROMs, so the oracle
+for shot n is the oracle's coupled system driven by shot n's source alone.  The operator is
+checked on all 64 shots at once: with D = 0 and dt = 1 one step leaves D = a(U) exactly (FP32
+fma with a zero addend), compared entry by entry with the oracle's accelerations of each shot's
+random state, at the same relative bars as the single-shot FP32 operator (1e-5 at p <= 24, 5e-5
+at p = 96, where FP32 rounding of the stored coefficients dominates).  Traces of 8 shots with 8
+distinct sources and wavelets are held to 1e-5 against 8 separate oracle runs.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import coupled
+from tests.cases import oracle_case, random_consistent_state, rel_l2, rom_arrays
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NSHOT = 64
+
+
+def _load(cfg, cs, src_ijk=None, src_vec=None):
+    from paper_1406_6923_amd import sfm
+    gam, hat, src, rec = rom_arrays(cs)
+    if src_ijk is None:
+        src_ijk, src_vec = cfg.sources(), src
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
+    sfm.sfm_load_roms(h.ctx, gam, hat, src_ijk, src_vec, cfg.receivers(), rec)
+    return h
+
+
+@pytest.mark.parametrize("name, tol", [("small", 1e-5), ("ragged", 1e-5), ("mid", 5e-5)])
+def test_shots_operator_matches_oracle(name, tol):
+    from paper_1406_6923_amd import sfm
+    cfg, c, subs, roms, cs = oracle_case(name)
+    print(f"[case] shots operator {name}, {NSHOT} shots", flush=True)
+    h = _load(cfg, cs)
+    sfm.sfm_shots_init(h.ctx, NSHOT, np.full(NSHOT, -1))
+    U = np.stack([random_consistent_state(cs, seed=100 + n) for n in range(NSHOT)], axis=-1).astype(np.float32)
+    sfm.sfm_shots_set_state(h.ctx, U, np.zeros_like(U))
+    wav = torch.zeros((1, NSHOT), dtype=torch.float32, device="cuda")
+    sfm.sfm_shots_step(h.ctx, 1, 1.0, wav, None)
+    _, a = sfm.sfm_shots_get_state(h.ctx, NSHOT)
+    worst = 0.0
+    for n in range(NSHOT):
+        ref = np.stack(cs.accel(list(U[..., n].astype(np.float64))))
+        err = rel_l2(a[..., n], ref)
+        worst = max(worst, err)
+        assert rel_l2(a[:, 0, :, n], ref[:, 0]) < tol, (n, "boundary layer")
+        assert rel_l2(a[:, 1:, :, n], ref[:, 1:]) < tol, (n, "interior layers")
+    print(f"{name}: shots operator worst rel-L2 over {NSHOT} shots {worst:.2e}")
+    assert worst < tol
+    h.close()
+
+
+def _shot_sources(cfg, n):
+    """n surface-near source nodes strictly inside subdomains (off every interface plane)."""
+    rng = np.random.default_rng(7)
+    out = []
+    while len(out) < n:
+        i, j = (int(x) for x in rng.integers(1, min(cfg.ncell[:2]), size=2))
+        l = 2
+        if i % cfg.sub_cells[0] == 0 or j % cfg.sub_cells[1] == 0 or (i, j, l) in out:
+            continue
+        out.append((i, j, l))
+    return out
+
+
+@pytest.mark.parametrize("name, nsteps", [("small", 500), ("ragged", 300)])
+def test_shots_traces_match_oracle(name, nsteps):
+    from paper_1406_6923_amd import sfm
+    cfg, c, subs, roms, cs = oracle_case(name)
+    nrun = 8
+    srcs = _shot_sources(cfg, nrun)
+    cs_all = coupled.CoupledSystem(subs, roms, srcs, cfg.receivers())
+    _, _, src_vec, _ = rom_arrays(cs_all)
+    h = _load(cfg, cs, np.asarray(srcs), src_vec)
+    # shots 0..7 driven by sources 7..0 (a non-identity map), the other 56 shots silent
+    shot_src = np.full(NSHOT, -1)
+    shot_src[:nrun] = np.arange(nrun)[::-1]
+    sfm.sfm_shots_init(h.ctx, NSHOT, shot_src)
+    dt = 0.9 * cs.cfl_dt()
+    wav = np.zeros((nsteps, NSHOT))
+    for n in range(nrun):
+        wav[:, n] = W.ricker(cfg.f_peak * (0.8 + 0.05 * n), dt, nsteps)
+    tr = torch.zeros((NSHOT, len(cs.receivers), nsteps), dtype=torch.float32, device="cuda")
+    print(f"[case] shots traces {name}, {nrun} driven shots, {nsteps} steps", flush=True)
+    sfm.sfm_shots_step(h.ctx, nsteps, dt, torch.tensor(wav, dtype=torch.float32, device="cuda"), tr)
+    torch.cuda.synchronize()
+    got = tr.cpu().numpy()
+    worst = 0.0
+    for n in range(nrun):
+        cs_n = coupled.CoupledSystem(subs, roms, [srcs[shot_src[n]]], cfg.receivers())
+        ref = cs_n.run(dt, wav[:, n:n + 1])
+        err = rel_l2(got[n], ref)
+        worst = max(worst, err)
+        assert err < 1e-5, (n, err)
+    assert not got[nrun:].any()
+    print(f"{name}: {nrun} shots, worst traces rel-L2 {worst:.2e}")
+    h.close()
+
+
+def test_shots_errors():
+    from paper_1406_6923_amd import sfm
+    cfg, c, subs, roms, cs = oracle_case("small")
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_shots_init(h.ctx, 4)
+    assert ei.value.status == sfm.SFM_ESTATE
+    h.close()
+    h = _load(cfg, cs)
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_shots_step(h.ctx, 1, 1e-3, None, None)
+    assert ei.value.status == sfm.SFM_ESTATE
+    for bad in (0, 65):
+        with pytest.raises(sfm.SfmError) as ei:
+            sfm.sfm_shots_init(h.ctx, bad, np.full(max(bad, 1), -1)[:bad] if bad else None)
+        assert ei.value.status == sfm.SFM_EINVAL
+    with pytest.raises(sfm.SfmError) as ei:     # source index out of range
+        sfm.sfm_shots_init(h.ctx, 2, np.array([0, 5]))
+    assert ei.value.status == sfm.SFM_EINVAL
+    with pytest.raises(sfm.SfmError) as ei:     # one source driving two shots
+        sfm.sfm_shots_init(h.ctx, 2, np.array([0, 0]))
+    assert ei.value.status == sfm.SFM_EINVAL
+    sfm.sfm_shots_init(h.ctx, 1)
+    dt_max = sfm.sfm_cfl_dt(h.ctx, 100)
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_shots_step(h.ctx, 1, 1.5 * dt_max, torch.zeros((1, 1), device="cuda"), None)
+    assert ei.value.status == sfm.SFM_EUNSTABLE
+    h.close()
+    gam, hat, src, rec = rom_arrays(cs)
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k, precision=sfm.SFM_PREC_BF16_FP32ACC)
+    sfm.sfm_load_roms(h.ctx, gam, hat, cfg.sources(), src, cfg.receivers(), rec)
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_shots_init(h.ctx, 1)
+    assert ei.value.status == sfm.SFM_EINVAL
+    h.close()
