@@ -144,6 +144,70 @@ def finite_shift_probe(torch, sfm, dev, stream, n: int = 4, steps: int = 200, si
     return out
 
 
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def shot_sources(cfg: W.Workload, n: int, seed: int = 2024):
+    """n shot positions uniformly random on the surface (depth 2 nodes), off every interface plane."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        i = int(rng.integers(1, cfg.ncell[0]))
+        j = int(rng.integers(1, cfg.ncell[1]))
+        if i % cfg.sub_cells[0] == 0 or j % cfg.sub_cells[1] == 0 or (i, j, 2) in out:
+            continue
+        out.append((i, j, 2))
+    return out
+
+
+def shots_probe(torch, sfm, h, cfg, dev, stream, dt, ratio, nshot, first_src, warmup, steps, nrec, single_ms):
+    """nshot shots (sources first_src..) stepped together through the same ROMs, all receivers recorded."""
+    sfm.sfm_shots_init(h.ctx, nshot, np.arange(first_src, first_src + nshot), stream=stream)
+    chosen, variants = sfm.sfm_shots_tuning(h.ctx)
+    log(f"[bench] shot kernel autotuner: {variants} (waves per SIMD, ms per step) -> {chosen}")
+    total = warmup + steps
+    w = W.ricker(cfg.f_peak, dt, total)
+    wav = torch.tensor(np.repeat(w[:, None], nshot, axis=1), dtype=torch.float32, device=dev)
+    tr = torch.zeros((nshot, max(nrec, 1), steps), dtype=torch.float32, device=dev) if nrec else None
+    if warmup:
+        sfm.sfm_shots_step(h.ctx, warmup, dt, wav[:warmup].contiguous(), None, stream=stream)
+    torch.cuda.synchronize()
+    sfm.sfm_shots_timing(h.ctx)
+    sfm.sfm_set_timing(h.ctx, True)
+    t0 = time.perf_counter()
+    sfm.sfm_shots_step(h.ctx, steps, dt, wav[warmup:].contiguous(), tr, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sfm.sfm_set_timing(h.ctx, False)
+    nt, ms = sfm.sfm_shots_timing(h.ctx)
+    info = h.info()
+    S, k, p = info["n_subdomains"], info["k"], info["p"]
+    main_ms = ms[0] / max(nt, 1)
+    flops = S * 2.0 * (2 * k - 1) * p * p * nshot
+    hbm = S * ((2 * k - 1) * p * (p + 1) // 2 * 4 + 4 * k * p * nshot * 4)
+    achieved = flops / (main_ms * 1e-3) / 1e12
+    out = {
+        "nshot": nshot, "steps": steps, "warmup": warmup, "receivers": nrec,
+        "ms_per_step": wall / steps * 1e3,
+        "value": cfg.n_cells * nshot * steps * ratio / wall / 1e9,
+        "unit": "Gcell-updates/s (all shots)",
+        "speedup_vs_single_shot_runs": nshot * single_ms / (wall / steps * 1e3),
+        "main_kernel_ms": main_ms, "face_kernel_ms": ms[1] / max(nt, 1), "record_kernel_ms": ms[2] / max(nt, 1),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "kernel": "shots_main_kernel",
+                     "flops_per_launch": flops, "algorithmic_bytes_per_launch": hbm,
+                     "hbm_gbs": hbm / (main_ms * 1e-3) / 1e9},
+        "traces_finite": bool(torch.isfinite(tr).all().item()) if tr is not None else True,
+        "autotune": {"chosen_waves_per_simd": chosen,
+                     "variants": [{"waves_per_simd": w, "ms": m} for w, m in variants]},
+    }
+    log(f"[bench] {nshot} shots: {out['ms_per_step']:.3f} ms/step, {out['value']:.1f} Gcell-updates/s, main kernel "
+        f"{main_ms:.3f} ms = {achieved:.1f} TFLOP/s FP32 MFMA ({100 * achieved / FP32_MFMA_PEAK_TFLOPS:.1f}%), "
+        f"{out['roofline']['hbm_gbs']:.0f} GB/s")
+    del tr
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +222,9 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=2048,
                     help="size of the device copy timed as the practical HBM bandwidth reference")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--shots", type=int, default=64,
+                    help="shots stepped together through the same ROMs after the single-shot run (0: skip)")
+    ap.add_argument("--shot-steps", type=int, default=100)
     ap.add_argument("--no-finite-shift", action="store_true",
                     help="skip the finite-shift ROM probe (4^3-subdomain sample of the same ROM shape)")
     args = ap.parse_args()
@@ -183,6 +250,11 @@ def main():
     log(f"[bench] velocity ready ({time.perf_counter() - t0:.1f} s), c in [{c.min():.0f}, {c_max:.0f}]")
     src = cfg.sources()
     rec = cfg.receivers()
+    n_main_src = len(src)
+    nshot = args.shots if prec == sfm.SFM_PREC_FP32 else 0
+    if nshot:
+        # the shot sources ride along in the build; they stay silent in the single-shot run
+        src = np.concatenate([np.asarray(src).reshape(-1, 3), np.asarray(shot_sources(cfg, nshot))])
 
     h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k, precision=prec, build_batch=args.build_batch)
     info = h.info()
@@ -203,7 +275,9 @@ def main():
 
     nrec = 0 if args.no_receivers else len(rec)
     total = args.warmup + args.steps
-    wav = torch.tensor(W.ricker(cfg.f_peak, dt, total)[:, None], dtype=torch.float32, device=dev)
+    wav_np = np.zeros((total, len(src)))
+    wav_np[:, :n_main_src] = W.ricker(cfg.f_peak, dt, total)[:, None]
+    wav = torch.tensor(wav_np, dtype=torch.float32, device=dev)
     traces = torch.zeros((max(nrec, 1), max(args.steps, 1)), dtype=torch.float32, device=dev) if nrec else None
     warm_tr = torch.zeros((max(nrec, 1), max(args.warmup, 1)), dtype=torch.float32, device=dev) if nrec else None
 
@@ -258,7 +332,7 @@ def main():
         # fine-grid FDTD on the same grid at its own stability limit
         nf = min(args.steps, 200)
         wf = torch.tensor(W.ricker(cfg.f_peak, dt_fine, nf)[:, None], dtype=torch.float32, device=dev)
-        secs = sfm.sfm_fdtd_run(cfg.ncell, cfg.h, vel, dt_fine, nf, src, wf, None, None, stream=stream)
+        secs = sfm.sfm_fdtd_run(cfg.ncell, cfg.h, vel, dt_fine, nf, cfg.sources(), wf, None, None, stream=stream)
         fdtd_rate = cfg.n_cells * nf / secs / 1e9
         log(f"[bench] fine-grid FDTD: {secs / nf * 1e3:.4f} ms/step, {fdtd_rate:.1f} Gcell-updates/s")
         # plain per-subdomain ROM stepping (same math, one launch per subdomain per step)
@@ -293,7 +367,8 @@ def main():
         "config": {
             "workload": cfg.name,
             "ncell": list(cfg.ncell), "sub_cells": list(cfg.sub_cells), "subdomains": S,
-            "m": cfg.m, "k": cfg.k, "p": p, "h": cfg.h, "receivers": nrec, "sources": len(src),
+            "m": cfg.m, "k": cfg.k, "p": p, "h": cfg.h, "receivers": nrec, "sources": n_main_src,
+            "silent_shot_sources_in_build": nshot,
             "velocity": "seeded 20-layer model (1500-4500 m/s) + 50 spheres (+-30%)",
         },
         "roofline": {
@@ -324,6 +399,9 @@ def main():
         comparators["speedup_vs_fine_fdtd"] = value / comparators["fine_fdtd_gcell_per_s"]
         comparators["speedup_vs_plain_rom"] = value / comparators["plain_rom_gcell_per_s"]
         out["comparators"] = comparators
+    if nshot:
+        out["shots"] = shots_probe(torch, sfm, h, cfg, dev, stream, dt, ratio, nshot, n_main_src, 10,
+                                   args.shot_steps, nrec, ms_per_step)
     if not args.no_finite_shift:
         out["finite_shift"] = finite_shift_probe(torch, sfm, dev, stream)
     if not args.no_cpu_baseline:

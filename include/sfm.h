@@ -250,7 +250,9 @@ sfm_status sfm_step_plain(sfm_ctx ctx, int32_t nsteps, double dt, const float* w
  * last sfm_build_roms / sfm_load_roms (its own wavelet column) and recorded at every receiver.
  * Requires SFM_PREC_FP32 and 6m <= 112.  The single-shot state (sfm_step) is independent. */
 
-/* Allocate and zero the shot state (U^0 = U^{-1} = 0) for nshot shots (1..64).
+/* Allocate and zero the shot state (U^0 = U^{-1} = 0) for nshot shots (1..64), then time every
+ * compiled variant of the shot kernel on it (no sources, dt = 0: the state stays zero) and keep
+ * the fastest (see sfm_shots_tuning).
  *   shot_src  host, int32 [nshot]: source index driving each shot (-1: no source), or NULL
  *             for shot n <- source n (then nshot <= nsrc).  A source drives at most one shot.
  * Synchronizes.  Errors: SFM_ESTATE (no ROMs), SFM_EINVAL, SFM_ENOMEM. */
@@ -267,6 +269,11 @@ sfm_status sfm_shots_step(sfm_ctx ctx, int32_t nsteps, double dt, const float* w
  * Synchronize.  Errors: SFM_ESTATE, SFM_EINVAL. */
 sfm_status sfm_shots_get_state(sfm_ctx ctx, float* u_host, float* d_host);
 sfm_status sfm_shots_set_state(sfm_ctx ctx, const float* u_host, const float* d_host);
+
+/* Autotuner result of the last sfm_shots_init: *chosen_waves = the register budget (minimum
+ * waves per SIMD) of the chosen variant; ms (host, double [2 cap]) = {waves, ms per step} of
+ * each variant (up to cap); *count = number of variants.  Errors: SFM_ESTATE. */
+sfm_status sfm_shots_tuning(sfm_ctx ctx, int32_t* chosen_waves, double* ms, int32_t cap, int32_t* count);
 
 /* Device times of the shot kernels summed over the steps run while sfm_set_timing was on:
  * *timed_steps, ms3 = {main, face, record}; then resets the counters.  Never fails for a valid ctx. */

@@ -225,9 +225,12 @@ struct sfm_ctx_s {
   float* Ds_d = nullptr;
   float* exch_s_d = nullptr;
   int32_t* src_shot_d = nullptr;    // [nsrc] shot driven by each source, -1 if none
+  float* rec_stage_d = nullptr;     // receiver samples of the current window [32][nrec][64]
   int64_t shots_n = 0;
   int64_t shots_timed = 0;
   double shots_ms[3] = {0, 0, 0};   // main, face, record
+  int shots_variant = 0;            // main-kernel variant chosen by the autotuner
+  double shots_tune_ms[4] = {0, 0, 0, 0};
   // scratch
   double* red_d = nullptr;          // reduction scratch
   float* work_a_d = nullptr;        // [S][k][P16] operator scratch

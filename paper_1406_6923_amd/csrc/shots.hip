@@ -7,12 +7,16 @@
 //
 // State layout: U, D [S][k][P16][64] (shot fastest); exch [S][P16][64].
 //
-// shots_main_kernel: one work-group per subdomain, one wave per 16-row tile of the block (P16/16
-// waves).  Per level j the block is read from the packed tile stream once (prefetched into
+// shots_main_kernel: one work-group per subdomain, two waves per 16-row tile of the block (each
+// wave 32 of the 64 shots; 2 P16/16 waves, which spreads the matrix-core work evenly over the
+// four SIMDs of a CU for every even P16/16).  Per level j the block is read from the packed tile stream once (prefetched into
 // registers while the previous block computes), expanded to a dense symmetric P16 x P16 copy in
 // LDS through the stored word map, and multiplied by the level input held transposed in LDS
-// ([shot][row], rows padded to PP = P16 + 4 floats).  phi_{j-1} stays in LDS, so one sweep over
-// the levels does both halves of the step without an HBM round trip for phi.  Within each
+// ([shot][row], rows padded to PP = P16 + 4 floats).  phi_{j-1} stays in registers, so one sweep
+// over the levels does both halves of the step without an HBM round trip for phi; U_j, U_{j+1},
+// U_{j+2} and D_j are held in registers in a layout where every thread owns one shot of 8 rows
+// (coalesced 256-byte rows), the loads of the next level issued before the matrix-core work.
+// LDS is the dense block and one [64][PP] array (64 KB at 6m = 96): two work-groups per CU.  Within each
 // 16-wide reduction chunk the MFMA number c takes k = kk + 4 g + c in lane group g, so a lane
 // reads its four k values of A and of B with one 16-byte LDS load each.
 #include <algorithm>
@@ -28,8 +32,10 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMaxShotP16 = 112;        // LDS: dense block + three [64][P16 + 4] arrays <= 160 KB
-constexpr int kPrefetchQuads = 5;       // 16-byte words of the next block held per thread
+constexpr int kMaxShotP16 = 112;        // work-group size (2 P16 / 16 waves) and prefetch capacity
+constexpr int kPrefetchQuads = 2;       // 16-byte words of the next block held per thread
+constexpr int kShotRowsPerThread = 8;   // P16 rows x 64 shots over 2 P16 / 16 waves
+constexpr int kShotWindow = 32;         // receiver samples staged per shot before the flush
 
 struct ShotParams {
   const float* tiles;          // packed FP32 tile stream [S][2k-1][words_per_block]
@@ -86,104 +92,123 @@ __device__ __forceinline__ void expand_block(float* __restrict__ G, int PP, int 
   }
 }
 
-// acc[s4] (16 x 16, shots 16 s4..) = G[16 I .. 16 I + 15][:] * X[:][16 s4 ..] with X held as Xt[shot][row].
+// acc[h] (16 x 16, shots 16 (sh + h)..) = G[16 I .. 16 I + 15][:] * X[:][16 (sh + h) ..] for the
+// wave's two shot tiles, X held as Xt[shot][row].
 __device__ __forceinline__ void block_product(const float* __restrict__ G, const float* __restrict__ Xt, int PP,
-                                              int P, int I, int g, int li, f4 (&acc)[4]) {
+                                              int P, int I, int sh, int g, int li, f4 (&acc)[2]) {
 #pragma unroll
-  for (int s4 = 0; s4 < 4; ++s4) acc[s4] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int h = 0; h < 2; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
   const float* arow = G + (16 * I + li) * PP + 4 * g;
-  const float* brow = Xt + li * PP + 4 * g;
+  const float* brow = Xt + (16 * sh + li) * PP + 4 * g;
   for (int kk = 0; kk < P; kk += 16) {
     const f4 a = *reinterpret_cast<const f4*>(arow + kk);
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const f4 b = *reinterpret_cast<const f4*>(brow + 16 * s4 * PP + kk);
-      acc[s4] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[s4], 0, 0, 0);
-      acc[s4] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[s4], 0, 0, 0);
-      acc[s4] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[s4], 0, 0, 0);
-      acc[s4] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[s4], 0, 0, 0);
+    for (int h = 0; h < 2; ++h) {
+      const f4 b = *reinterpret_cast<const f4*>(brow + 16 * h * PP + kk);
+      acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[h], 0, 0, 0);
+      acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[h], 0, 0, 0);
+      acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[h], 0, 0, 0);
+      acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[h], 0, 0, 0);
     }
   }
 }
 
-__global__ __launch_bounds__(64 * (kMaxShotP16 / kTile)) void shots_main_kernel(ShotParams prm) {
+// kMinWaves: waves per SIMD the register allocation must allow (2: one work-group per CU, no
+// spills; 3: two work-groups per CU at 6m = 96, some registers spilled).  sfm_shots_init times
+// every instantiation and keeps the fastest.
+template <int kMinWaves>
+__global__ __launch_bounds__(128 * (kMaxShotP16 / kTile), kMinWaves) void shots_main_kernel(ShotParams prm) {
   extern __shared__ __align__(16) float lds[];
   const int P = prm.P, PP = prm.PP, k = prm.k;
   float* G = lds;                        // [P][PP]   dense block
-  float* Xt = G + P * PP;                // [64][PP]  block input, transposed
-  float* Ut = Xt + kShotCols * PP;       // [64][PP]  U_{j+1} of the previous level = U_j
-  float* Ft = Ut + kShotCols * PP;       // [64][PP]  phi_{j-1}
+  float* Xt = G + P * PP;                // [64][PP]  block input, then a_j, transposed
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int I = tid >> 6, lane = tid & 63, g = lane >> 4, li = lane & 15;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index: uniform
+  const int nw = nthr >> 6;              // = 2 P / 16: two waves per 16-row tile
+  const int I = w >> 1, sh = 2 * (w & 1);   // row tile, first of the wave's two shot tiles
+  const int lane = tid & 63, g = lane >> 4, li = lane & 15;
   const int s = blockIdx.x;
   const int nq = (int)(prm.words_per_block / 4);
   const size_t sbase = (size_t)s * k * P * kShotCols;
   const int ns0 = prm.src_off ? prm.src_off[s] : 0;
   const int ns1 = prm.src_off ? prm.src_off[s + 1] : 0;
-
-  for (int e = tid; e < P * kShotCols; e += nthr) {
-    const int r = e / kShotCols, n = e - r * kShotCols;
-    Ut[n * PP + r] = prm.U[sbase + e];
-  }
+  // X layout: this thread owns shot `lane` of rows w + i nw (i < 8) of every level; its global
+  // accesses are 256-byte rows of 64 shots at a wave-uniform row offset.
+  float* const Uw = prm.U + sbase + (size_t)w * kShotCols;
+  float* const Dw = prm.D + sbase + (size_t)w * kShotCols;
+  auto xrow = [&](int j, int i) { return ((j * P + i * nw) * kShotCols); };
+  constexpr int R = kShotRowsPerThread;
+  float Ua[R], Ub[R], Un[R], Dr[R];      // U_j, U_{j+1}, U_{j+2}, D_j
+  f4 phip[2];                            // phi_{j-1} in the MFMA output layout
+  f4 acc[2];
   f4 buf[kPrefetchQuads];
   prefetch_block(prm.tiles + block_word(prm, s, 0), nq, tid, nthr, buf);
-  f4 acc[4];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    Ua[i] = Uw[xrow(0, i) + lane];
+    Ub[i] = k > 1 ? Uw[xrow(1, i) + lane] : 0.f;
+  }
+  const int row0 = 16 * I + 4 * g;
   for (int j = 0; j < k; ++j) {
     __syncthreads();                                       // G, Xt free
     expand_block(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma_j
-    // X = U_{j+1} - U_j (U_{k+1} = 0); Ut <- U_{j+1}
-    for (int e = tid; e < P * kShotCols; e += nthr) {
-      const int r = e / kShotCols, n = e - r * kShotCols;
-      const float un = (j + 1 < k) ? prm.U[sbase + (size_t)(j + 1) * P * kShotCols + e] : 0.f;
-      Xt[n * PP + r] = un - Ut[n * PP + r];
-      Ut[n * PP + r] = un;
-    }
-    __syncthreads();
-    if (j >= 1) prefetch_block(prm.tiles + block_word(prm, s, k + j - 1), nq, tid, nthr, buf);   // Gamma-hat_j
-    else if (k > 1) prefetch_block(prm.tiles + block_word(prm, s, 1), nq, tid, nthr, buf);       // Gamma_2
-    block_product(G, Xt, PP, P, I, g, li, acc);            // phi_j
-    __syncthreads();                                       // every wave done with G, Xt
-    const int row0 = 16 * I + 4 * g;
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int n = 16 * s4 + li;
-      float* fp = Ft + n * PP + row0;
+    for (int i = 0; i < R; ++i) Xt[lane * PP + w + i * nw] = Ub[i] - Ua[i];   // U_{j+1} - U_j
+    __syncthreads();
+    if (j >= 1) {
+      prefetch_block(prm.tiles + block_word(prm, s, k + j - 1), nq, tid, nthr, buf);   // Gamma-hat_j
+#pragma unroll
+      for (int i = 0; i < R; ++i) Dr[i] = Dw[xrow(j, i) + lane];
+    } else {
+      prefetch_block(prm.tiles + block_word(prm, s, 1), nq, tid, nthr, buf);           // Gamma_2
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) Un[i] = (j + 2 < k) ? Uw[xrow(j + 2, i) + lane] : 0.f;
+    block_product(G, Xt, PP, P, I, sh, g, li, acc);        // phi_j
+    __syncthreads();                                       // every wave done with G, Xt
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int n = 16 * (sh + h) + li;
       if (j == 0) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) prm.exch[((size_t)s * P + row0 + v) * kShotCols + n] = acc[s4][v];   // step 2.1
+        for (int v = 0; v < 4; ++v) prm.exch[((size_t)s * P + row0 + v) * kShotCols + n] = acc[h][v];   // step 2.1
       } else {
-        const f4 prev = *reinterpret_cast<const f4*>(fp);
-        *reinterpret_cast<f4*>(Xt + n * PP + row0) = acc[s4] - prev;   // phi_j - phi_{j-1}
+        *reinterpret_cast<f4*>(Xt + n * PP + row0) = acc[h] - phip[h];   // phi_j - phi_{j-1}
       }
-      *reinterpret_cast<f4*>(fp) = acc[s4];
+      phip[h] = acc[h];
     }
-    if (j == 0) continue;                                  // the boundary layer is the face kernel's
-    expand_block(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma-hat_j
-    __syncthreads();
-    if (j + 1 < k) prefetch_block(prm.tiles + block_word(prm, s, j + 1), nq, tid, nthr, buf);   // Gamma_{j+1}
-    block_product(G, Xt, PP, P, I, g, li, acc);            // a_j
-    // sources of this subdomain: a_j += f_n(t) s_j for the shot n each source drives
-    for (int q = ns0; q < ns1; ++q) {
-      const int src = prm.src_ids[q];
-      const int n = prm.src_shot[src];
-      if (n < 0 || (n & 15) != li) continue;
-      const float w = prm.wavelet[prm.step * prm.nshot + n];
-      const float* sv = prm.src_vec + ((size_t)src * k + j) * P + row0;
-      const int s4 = n >> 4;
+    if (j >= 1) {
+      expand_block(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma-hat_j
+      __syncthreads();
+      if (j + 1 < k) prefetch_block(prm.tiles + block_word(prm, s, j + 1), nq, tid, nthr, buf);   // Gamma_{j+1}
+      block_product(G, Xt, PP, P, I, sh, g, li, acc);        // a_j
+      // sources of this subdomain: a_j += f_n(t) s_j for the shot n each source drives
+      for (int q = ns0; q < ns1; ++q) {
+        const int src = prm.src_ids[q];
+        const int n = prm.src_shot[src];
+        if (n < 0 || (n & 15) != li || (n >> 4) < sh || (n >> 4) > sh + 1) continue;
+        const float wv = prm.wavelet[prm.step * prm.nshot + n];
+        const float* sv = prm.src_vec + ((size_t)src * k + j) * P + row0;
+        const int h = (n >> 4) - sh;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[s4][v] = fmaf(w, sv[v], acc[s4][v]);
-    }
-    // leapfrog in increment form: D_j += dt^2 a_j, U_j += D_j
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int n = 16 * s4 + li;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const size_t idx = sbase + ((size_t)j * P + row0 + v) * kShotCols + n;
-        const float d = fmaf(prm.dt2, acc[s4][v], prm.D[idx]);
-        prm.D[idx] = d;
-        prm.U[idx] = prm.U[idx] + d;
+        for (int v = 0; v < 4; ++v) acc[h][v] = fmaf(wv, sv[v], acc[h][v]);
       }
+      __syncthreads();                                     // every wave done reading Xt
+#pragma unroll
+      for (int h = 0; h < 2; ++h) *reinterpret_cast<f4*>(Xt + (16 * (sh + h) + li) * PP + row0) = acc[h];
+      __syncthreads();
+      // leapfrog in increment form: D_j += dt^2 a_j, U_j += D_j
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const float d = fmaf(prm.dt2, Xt[lane * PP + w + i * nw], Dr[i]);
+        Dw[xrow(j, i) + lane] = d;
+        Uw[xrow(j, i) + lane] = Ua[i] + d;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      Ua[i] = Ub[i];
+      Ub[i] = Un[i];
     }
   }
 }
@@ -206,28 +231,36 @@ struct ShotFaceParams {
   float* D;
 };
 
-// a_f = C_f (phi_1^alpha + phi_1^beta) + f_n(t) w_f per shot n (eq. "bdrytstep").
+// a_f = C_f (phi_1^alpha + phi_1^beta) + f_n(t) w_f per shot n (eq. "bdrytstep"); four shots per
+// thread (16-byte accesses).
 __global__ void shots_face_kernel(ShotFaceParams prm) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)prm.S * prm.p * kShotCols) return;
-  const int n = (int)(idx % kShotCols);
-  const int64_t sq = idx / kShotCols;
+  constexpr int kQ = kShotCols / 4;
+  if (idx >= (int64_t)prm.S * prm.p * kQ) return;
+  const int n0 = 4 * (int)(idx % kQ);
+  const int64_t sq = idx / kQ;
   const int s = (int)(sq / prm.p);
   const int q = (int)(sq - (int64_t)s * prm.p);
   const int f = q / prm.m, pat = q - f * prm.m;
   const int nb = prm.nbr[s * 6 + f];
-  float flux = prm.exch[((size_t)s * prm.P + q) * kShotCols + n];
-  if (nb >= 0) flux += prm.exch[((size_t)nb * prm.P + (f ^ 1) * prm.m + pat) * kShotCols + n];
-  float a = prm.C[(size_t)s * prm.P + q] * flux;
+  f4 flux = *reinterpret_cast<const f4*>(prm.exch + ((size_t)s * prm.P + q) * kShotCols + n0);
+  if (nb >= 0) flux += *reinterpret_cast<const f4*>(prm.exch + ((size_t)nb * prm.P + (f ^ 1) * prm.m + pat) * kShotCols + n0);
+  f4 a = prm.C[(size_t)s * prm.P + q] * flux;
   if (prm.sw_off) {
-    for (int e = prm.sw_off[s]; e < prm.sw_off[s + 1]; ++e)
-      if (prm.sw_q[e] == q && prm.src_shot[prm.sw_src[e]] == n)
-        a = fmaf(prm.sw_w[e], prm.wavelet[prm.step * prm.nshot + n], a);
+    for (int e = prm.sw_off[s]; e < prm.sw_off[s + 1]; ++e) {
+      if (prm.sw_q[e] != q) continue;
+      const int n = prm.src_shot[prm.sw_src[e]];
+      if (n < n0 || n >= n0 + 4) continue;
+      a[n - n0] = fmaf(prm.sw_w[e], prm.wavelet[prm.step * prm.nshot + n], a[n - n0]);
+    }
   }
-  const size_t u = ((size_t)s * prm.k * prm.P + q) * kShotCols + n;
-  const float d = fmaf(prm.dt2, a, prm.D[u]);
-  prm.D[u] = d;
-  prm.U[u] = prm.U[u] + d;
+  const size_t u = ((size_t)s * prm.k * prm.P + q) * kShotCols + n0;
+  f4 d = *reinterpret_cast<const f4*>(prm.D + u);
+  const f4 uu = *reinterpret_cast<const f4*>(prm.U + u);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) d[c] = fmaf(prm.dt2, a[c], d[c]);
+  *reinterpret_cast<f4*>(prm.D + u) = d;
+  *reinterpret_cast<f4*>(prm.U + u) = uu + d;
 }
 
 struct ShotRecParams {
@@ -236,72 +269,117 @@ struct ShotRecParams {
   const int32_t* rec_sub;      // sorted receivers: subdomain
   const int32_t* perm;         // sorted receivers: caller index
   const float* U;              // [S][k][P][64]
+  float* stage;                // [kShotWindow][nrec][64] samples of the current window (sorted order)
   float* out;                  // [nshot][nrec][ld]
   int k, P, nrec, nshot;
-  int64_t ld, col;
+  int64_t ld;
+  int slot;                    // time slot of this step in the window
+  int64_t col0;                // flush: trace column of slot 0
+  int w;                       // flush: filled slots
 };
 
-// out[n][r][col] = rows[r] . U[s(r)][:][:][n]: per receiver subdomain a (receivers x kP) (kP x 64)
-// product, 64 x 64 outputs per work-group staged through LDS in chunks of 32.
+// stage[slot][r][n] = rows[r] . U[s(r)][:][:][n]: per receiver subdomain a (receivers x kP) (kP x 64)
+// product on the matrix cores, 64 receivers x 64 shots per work-group (one wave per 16 receivers).
+// The reduction runs in chunks of 64 staged through LDS (rows as [r][e], U as [e][n]); the next
+// chunk is loaded into registers (16-byte loads) while the current one is multiplied.  The 64
+// shots of a receiver are one 256-byte row of the window.
 __global__ __launch_bounds__(256) void shots_record_kernel(ShotRecParams prm) {
-  constexpr int kR = 64, kK = 32;
-  __shared__ float Rs[kK][kR + 4];
-  __shared__ float Us[kK][kShotCols + 4];
+  constexpr int kR = 64, kK = 64, kKP = kK + 4, kNP = kShotCols + 4;
+  __shared__ __align__(16) float Rs[kR][kKP];
+  __shared__ __align__(16) float Us[kK][kNP];
   const int slot = blockIdx.y;
   const int r0 = prm.rs_off[slot] + blockIdx.x * kR;
   const int r1 = prm.rs_off[slot + 1];
   if (r0 >= r1) return;
-  const int K = prm.k * prm.P;
+  const int K = prm.k * prm.P;            // a multiple of 16 (P = P16)
   const float* Ub = prm.U + (size_t)prm.rec_sub[r0] * K * kShotCols;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  float acc[4][4] = {};
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, g = lane >> 4, li = lane & 15;
+  // loader layout: 4 passes of 16 rows x 16 quads
+  const int lr = tid >> 4, lq = tid & 15;
+  f4 rbuf[4], ubuf[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+      const int rr = lr + 16 * pass;
+      const int r = r0 + rr, e = k0 + 4 * lq;
+      rbuf[pass] = (r < r1 && e < K) ? *reinterpret_cast<const f4*>(prm.rows + (size_t)r * K + e) : f4{0.f, 0.f, 0.f, 0.f};
+      const int e2 = k0 + rr;
+      ubuf[pass] = e2 < K ? *reinterpret_cast<const f4*>(Ub + (size_t)e2 * kShotCols + 4 * lq) : f4{0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  f4 acc[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
+  load(0);
   for (int k0 = 0; k0 < K; k0 += kK) {
-    for (int q = tid; q < kR * kK; q += 256) {
-      const int rr = q / kK, kk = q - rr * kK;
-      const int r = r0 + rr, e = k0 + kk;
-      Rs[kk][rr] = (r < r1 && e < K) ? prm.rows[(size_t)r * K + e] : 0.f;
-      const int kk2 = q / kShotCols, n = q - kk2 * kShotCols;
-      const int e2 = k0 + kk2;
-      Us[kk2][n] = e2 < K ? Ub[(size_t)e2 * kShotCols + n] : 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+      *reinterpret_cast<f4*>(&Rs[lr + 16 * pass][4 * lq]) = rbuf[pass];
+      *reinterpret_cast<f4*>(&Us[lr + 16 * pass][4 * lq]) = ubuf[pass];
     }
     __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < kK; ++kk) {
-      float a[4], b[4];
+    if (k0 + kK < K) load(k0 + kK);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = Rs[kk][ty * 4 + i];
+    for (int kk = 0; kk < kK; kk += 16) {
+      const f4 a = *reinterpret_cast<const f4*>(&Rs[16 * wv + li][kk + 4 * g]);
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) b[jj] = Us[kk][tx * 4 + jj];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) acc[i][jj] = fmaf(a[i], b[jj], acc[i][jj]);
+      for (int h = 0; h < 4; ++h) {
+        const int n = 16 * h + li;
+        const float* ub = &Us[kk + 4 * g][n];
+        acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, ub[0], acc[h], 0, 0, 0);
+        acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, ub[kNP], acc[h], 0, 0, 0);
+        acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, ub[2 * kNP], acc[h], 0, 0, 0);
+        acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, ub[3 * kNP], acc[h], 0, 0, 0);
+      }
     }
-    __syncthreads();
   }
+  // acc[h][v]: receiver r0 + 16 wv + 4 g + v, shot 16 h + li
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = r0 + ty * 4 + i;
+  for (int v = 0; v < 4; ++v) {
+    const int r = r0 + 16 * wv + 4 * g + v;
     if (r >= r1) continue;
+    float* row = prm.stage + ((size_t)prm.slot * prm.nrec + r) * kShotCols;
 #pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      const int n = tx * 4 + jj;
-      if (n < prm.nshot) prm.out[((size_t)n * prm.nrec + prm.perm[r]) * prm.ld + prm.col] = acc[i][jj];
-    }
+    for (int h = 0; h < 4; ++h) row[16 * h + li] = acc[h][v];
   }
 }
 
+// out[n][perm[r]][col0 + t] = stage[t][r][n] for t < w: one work-group per receiver, transposed
+// through LDS so that both the window rows (64 shots) and the trace runs (w samples) are contiguous.
+__global__ __launch_bounds__(256) void shots_flush_kernel(ShotRecParams prm) {
+  __shared__ float tile[kShotWindow][kShotCols + 1];
+  const int r = blockIdx.x;
+  for (int e = threadIdx.x; e < prm.w * kShotCols; e += 256) {
+    const int t = e / kShotCols, n = e - t * kShotCols;
+    tile[t][n] = prm.stage[((size_t)t * prm.nrec + r) * kShotCols + n];
+  }
+  __syncthreads();
+  const size_t orow = (size_t)prm.perm[r];
+  for (int e = threadIdx.x; e < prm.w * prm.nshot; e += 256) {
+    const int n = e / prm.w, t = e - n * prm.w;
+    prm.out[((size_t)n * prm.nrec + orow) * prm.ld + prm.col0 + t] = tile[t][n];
+  }
+}
+
+typedef void (*ShotKernel)(ShotParams);
+// 4 waves per SIMD: one 12-wave work-group per CU at 6m = 96 with no spills; 6: two work-groups
+// per CU with some registers spilled.
+constexpr ShotKernel kShotVariants[] = {shots_main_kernel<4>, shots_main_kernel<6>};
+constexpr int kShotVariantWaves[] = {4, 6};
+constexpr int kNumShotVariants = 2;
+
 size_t shots_lds_bytes(int P) {
   const int PP = P + 4;
-  return sizeof(float) * ((size_t)P * PP + (size_t)3 * kShotCols * PP);
+  return sizeof(float) * ((size_t)P * PP + (size_t)kShotCols * PP);
 }
 
 }  // namespace
 
 void release_shots(sfm_ctx c) {
-  void* bufs[] = {c->Us_d, c->Ds_d, c->exch_s_d, c->src_shot_d};
+  void* bufs[] = {c->Us_d, c->Ds_d, c->exch_s_d, c->src_shot_d, c->rec_stage_d};
   for (void* b : bufs) c->dfree(b);
-  c->Us_d = c->Ds_d = c->exch_s_d = nullptr;
+  c->Us_d = c->Ds_d = c->exch_s_d = c->rec_stage_d = nullptr;
   c->src_shot_d = nullptr;
   c->nshot = 0;
   c->shots_n = 0;
@@ -310,6 +388,10 @@ void release_shots(sfm_ctx c) {
 }  // namespace sfm
 
 using namespace sfm;
+
+namespace {
+sfm_status autotune_shots(sfm_ctx c, hipStream_t st);
+}
 
 #define SH_TRY_HIP(call)                                                                      \
   do {                                                                                        \
@@ -326,7 +408,7 @@ sfm_status sfm_shots_init(sfm_ctx c, int32_t nshot, const int32_t* shot_src, voi
   if (c->cfg.precision != SFM_PREC_FP32) return c->fail(SFM_EINVAL, "shots need FP32 coefficient storage");
   if (c->geo.P16 > kMaxShotP16)
     return c->fail(SFM_EINVAL, "shots support 6m <= " + std::to_string(kMaxShotP16) + " (LDS of one CU)");
-  if (c->geo.words_per_block > (int64_t)kPrefetchQuads * 4 * 64 * c->geo.nt)
+  if (c->geo.words_per_block > (int64_t)kPrefetchQuads * 4 * 128 * c->geo.nt)
     return c->fail(SFM_EINVAL, "coefficient block larger than the shot kernel's prefetch");
   if (nshot < 1 || nshot > kShotCols) return c->fail(SFM_EINVAL, "nshot must lie in 1..64");
   std::vector<int32_t> src_shot(std::max(c->nsrc, 1), -1);
@@ -349,6 +431,8 @@ sfm_status sfm_shots_init(sfm_ctx c, int32_t nshot, const int32_t* shot_src, voi
   c->Ds_d = static_cast<float*>(c->dalloc(nstate * sizeof(float), &e));
   c->exch_s_d = static_cast<float*>(c->dalloc((size_t)t.S * c->geo.P16 * kShotCols * sizeof(float), &e));
   c->src_shot_d = static_cast<int32_t*>(c->dalloc(src_shot.size() * sizeof(int32_t), &e));
+  if (c->nrec > 0)
+    c->rec_stage_d = static_cast<float*>(c->dalloc((size_t)kShotWindow * c->nrec * kShotCols * sizeof(float), &e));
   if (e != hipSuccess) {
     release_shots(c);
     return c->fail(SFM_ENOMEM, "shot state: out of device memory");
@@ -360,22 +444,16 @@ sfm_status sfm_shots_init(sfm_ctx c, int32_t nshot, const int32_t* shot_src, voi
   SH_TRY_HIP(hipStreamSynchronize(st));
   c->nshot = nshot;
   c->shots_n = 0;
-  return SFM_OK;
+  const sfm_status rc = autotune_shots(c, st);
+  if (rc != SFM_OK) release_shots(c);
+  return rc;
 }
 
-sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wavelet_dev, float* traces_dev,
-                          int64_t ld, void* stream) {
-  if (!c) return SFM_EINVAL;
-  c->err.clear();
-  if (c->nshot == 0) return c->fail(SFM_ESTATE, "call sfm_shots_init first");
-  if (nsteps < 0) return c->fail(SFM_EINVAL, "nsteps must be >= 0");
-  if (!(dt > 0.0)) return c->fail(SFM_EINVAL, "dt must be positive");
-  if (c->dt_max > 0.0 && dt > c->dt_max)
-    return c->fail(SFM_EUNSTABLE, "dt above the stability limit from sfm_cfl_dt");
-  if (c->nsrc > 0 && !wavelet_dev) return c->fail(SFM_EINVAL, "wavelet_dev is NULL but sources exist");
-  if (traces_dev && c->nrec > 0 && ld < nsteps) return c->fail(SFM_EINVAL, "ld must be >= nsteps");
-  SH_TRY_HIP(hipSetDevice(c->device));
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+}  // extern "C"
+
+namespace {
+
+ShotParams main_params(sfm_ctx c, const float* wavelet_dev, double dt) {
   const Topology& t = c->topo;
   const TileGeometry& g = c->geo;
   ShotParams prm{};
@@ -397,6 +475,68 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
   prm.wavelet = wavelet_dev;
   prm.nshot = c->nshot;
   prm.dt2 = (float)(dt * dt);
+  return prm;
+}
+
+hipError_t launch_shots_main(int variant, const ShotParams& prm, int nt, hipStream_t st) {
+  const size_t lds = shots_lds_bytes(prm.P);
+  const ShotKernel kern = kShotVariants[variant];
+  if (lds > kDefaultLdsBytes) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(prm.S), dim3(128 * nt), lds, st, prm);
+  return hipGetLastError();
+}
+
+// Times every kernel variant on the (zero) shot state with no sources and dt = 0, which leaves
+// the state unchanged, and keeps the fastest.
+sfm_status autotune_shots(sfm_ctx c, hipStream_t st) {
+  ShotParams prm = main_params(c, nullptr, 0.0);
+  prm.src_off = nullptr;
+  hipEvent_t a, b;
+  SH_TRY_HIP(hipEventCreate(&a));
+  SH_TRY_HIP(hipEventCreate(&b));
+  int best = 0;
+  for (int v = 0; v < kNumShotVariants; ++v) {
+    for (int r = 0; r < 2; ++r) SH_TRY_HIP(launch_shots_main(v, prm, c->geo.nt, st));
+    SH_TRY_HIP(hipEventRecord(a, st));
+    constexpr int kReps = 5;
+    for (int r = 0; r < kReps; ++r) SH_TRY_HIP(launch_shots_main(v, prm, c->geo.nt, st));
+    SH_TRY_HIP(hipEventRecord(b, st));
+    SH_TRY_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    SH_TRY_HIP(hipEventElapsedTime(&ms, a, b));
+    c->shots_tune_ms[v] = ms / kReps;
+    if (c->shots_tune_ms[v] < c->shots_tune_ms[best]) best = v;
+  }
+  SH_TRY_HIP(hipEventDestroy(a));
+  SH_TRY_HIP(hipEventDestroy(b));
+  c->shots_variant = best;
+  return SFM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wavelet_dev, float* traces_dev,
+                          int64_t ld, void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (c->nshot == 0) return c->fail(SFM_ESTATE, "call sfm_shots_init first");
+  if (nsteps < 0) return c->fail(SFM_EINVAL, "nsteps must be >= 0");
+  if (!(dt > 0.0)) return c->fail(SFM_EINVAL, "dt must be positive");
+  if (c->dt_max > 0.0 && dt > c->dt_max)
+    return c->fail(SFM_EUNSTABLE, "dt above the stability limit from sfm_cfl_dt");
+  if (c->nsrc > 0 && !wavelet_dev) return c->fail(SFM_EINVAL, "wavelet_dev is NULL but sources exist");
+  if (traces_dev && c->nrec > 0 && ld < nsteps) return c->fail(SFM_EINVAL, "ld must be >= nsteps");
+  SH_TRY_HIP(hipSetDevice(c->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const Topology& t = c->topo;
+  const TileGeometry& g = c->geo;
+  ShotParams prm = main_params(c, wavelet_dev, dt);
   ShotFaceParams fp{};
   fp.S = t.S;
   fp.k = t.k;
@@ -422,17 +562,14 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
   rp.rec_sub = c->rec_sub_d;
   rp.perm = c->rec_perm_d;
   rp.U = c->Us_d;
+  rp.stage = c->rec_stage_d;
   rp.out = traces_dev;
   rp.k = t.k;
   rp.P = g.P16;
   rp.nrec = c->nrec;
   rp.nshot = c->nshot;
   rp.ld = ld;
-  const size_t lds = shots_lds_bytes(g.P16);
-  if (lds > kDefaultLdsBytes)
-    SH_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&shots_main_kernel),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  const int64_t nface = (int64_t)t.S * t.p * kShotCols;
+  const int64_t nface = (int64_t)t.S * t.p * (kShotCols / 4);
   const bool record = traces_dev && c->nrec > 0;
   const dim3 rgrid((c->rs_max + 63) / 64, c->n_rs);
   hipEvent_t ev[4] = {};
@@ -444,16 +581,21 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
       for (auto& x : ev) SH_TRY_HIP(hipEventCreate(&x));
       SH_TRY_HIP(hipEventRecord(ev[0], st));
     }
-    hipLaunchKernelGGL(shots_main_kernel, dim3(t.S), dim3(64 * g.nt), lds, st, prm);
-    SH_TRY_HIP(hipGetLastError());
+    SH_TRY_HIP(launch_shots_main(c->shots_variant, prm, g.nt, st));
     if (timing) SH_TRY_HIP(hipEventRecord(ev[1], st));
     hipLaunchKernelGGL(shots_face_kernel, dim3((unsigned)((nface + 255) / 256)), dim3(256), 0, st, fp);
     SH_TRY_HIP(hipGetLastError());
     if (timing) SH_TRY_HIP(hipEventRecord(ev[2], st));
     if (record) {
-      rp.col = n;
+      rp.slot = n % kShotWindow;
       hipLaunchKernelGGL(shots_record_kernel, rgrid, dim3(256), 0, st, rp);
       SH_TRY_HIP(hipGetLastError());
+      if (rp.slot == kShotWindow - 1 || n + 1 == nsteps) {
+        rp.w = rp.slot + 1;
+        rp.col0 = n - rp.slot;
+        hipLaunchKernelGGL(shots_flush_kernel, dim3(c->nrec), dim3(256), 0, st, rp);
+        SH_TRY_HIP(hipGetLastError());
+      }
     }
     if (timing) {
       SH_TRY_HIP(hipEventRecord(ev[3], st));
@@ -511,6 +653,19 @@ sfm_status sfm_shots_set_state(sfm_ctx c, const float* u_host, const float* d_ho
         std::memcpy(buf.data() + (sj * P + q) * kShotCols, ins[a] + (sj * t.p + q) * c->nshot,
                     c->nshot * sizeof(float));
     SH_TRY_HIP(hipMemcpy(dsts[a], buf.data(), buf.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  return SFM_OK;
+}
+
+sfm_status sfm_shots_tuning(sfm_ctx c, int32_t* chosen_waves, double* ms, int32_t cap, int32_t* count) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (c->nshot == 0) return c->fail(SFM_ESTATE, "call sfm_shots_init first");
+  if (chosen_waves) *chosen_waves = kShotVariantWaves[c->shots_variant];
+  if (count) *count = kNumShotVariants;
+  for (int v = 0; v < std::min<int>(cap, kNumShotVariants); ++v) {
+    if (ms) ms[2 * v] = kShotVariantWaves[v];
+    if (ms) ms[2 * v + 1] = c->shots_tune_ms[v];
   }
   return SFM_OK;
 }

@@ -75,6 +75,7 @@ SIGNATURES = {
     "sfm_shots_get_state": (_I32, [_VP, _VP, _VP]),
     "sfm_shots_set_state": (_I32, [_VP, _VP, _VP]),
     "sfm_shots_timing": (_I32, [_VP, ctypes.POINTER(_I64), _VP]),
+    "sfm_shots_tuning": (_I32, [_VP, ctypes.POINTER(_I32), _VP, _I32, ctypes.POINTER(_I32)]),
     "sfm_load_roms": (_I32, [_VP, _VP, _VP, _I32, _VP, _VP, _I32, _VP, _VP]),
     "sfm_export_roms": (_I32, [_VP, _VP, _VP]),
     "sfm_export_projections": (_I32, [_VP, _VP, _VP]),
@@ -263,6 +264,14 @@ def sfm_shots_set_state(ctx: int, u, d) -> None:
     u = _host(u, np.float32)
     d = _host(d, np.float32)
     _check(ctx, load_library().sfm_shots_set_state(ctx, _ptr(u), _ptr(d)))
+
+
+def sfm_shots_tuning(ctx: int):
+    """(chosen waves per SIMD, [(waves, ms per step) of each variant]) from the last sfm_shots_init."""
+    chosen, count = _I32(0), _I32(0)
+    ms = np.zeros(16, np.float64)
+    _check(ctx, load_library().sfm_shots_tuning(ctx, ctypes.byref(chosen), _ptr(ms), 8, ctypes.byref(count)))
+    return int(chosen.value), [(int(ms[2 * v]), float(ms[2 * v + 1])) for v in range(count.value)]
 
 
 def sfm_shots_timing(ctx: int):

@@ -38,6 +38,10 @@ def test_shots_operator_matches_oracle(name, tol):
     print(f"[case] shots operator {name}, {NSHOT} shots", flush=True)
     h = _load(cfg, cs)
     sfm.sfm_shots_init(h.ctx, NSHOT, np.full(NSHOT, -1))
+    chosen, variants = sfm.sfm_shots_tuning(h.ctx)
+    print(f"{name}: autotuner {variants} -> {chosen} waves per SIMD")
+    assert chosen in [w for w, _ in variants] and all(ms > 0 for _, ms in variants)
+    assert min(variants, key=lambda v: v[1])[0] == chosen
     U = np.stack([random_consistent_state(cs, seed=100 + n) for n in range(NSHOT)], axis=-1).astype(np.float32)
     sfm.sfm_shots_set_state(h.ctx, U, np.zeros_like(U))
     wav = torch.zeros((1, NSHOT), dtype=torch.float32, device="cuda")
