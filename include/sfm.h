@@ -243,6 +243,25 @@ const char* sfm_fdtd_last_error(void);
  * (2k-1) p^2 words per subdomain), one thread per row, no receivers.  Advances the context state. */
 sfm_status sfm_step_plain(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet_dev, void* stream);
 
+/* ---- misfit gradients (discrete adjoint of the leapfrog step) ----
+ * For traces t^n = R X^{n+1} of nsteps leapfrog steps from rest (as sfm_step after
+ * sfm_reset_state without initial conditions) and a misfit J with trace gradient
+ * r^n = dJ/dt^n, returns dJ/dGamma_j and dJ/dGamma-hat_j of every subdomain (the symmetric
+ * parts; Gamma-hat_1, the face masses, and the source / receiver projections held fixed, so
+ * grad_gamma_hat[.][0] = 0).  The adjoint runs backward with A^T = -K M^{-1} (the step with its
+ * two block products swapped) and the residuals injected through the receiver rows; forward
+ * states come from checkpoints every checkpoint_every steps and a recomputation of each segment.
+ *   wavelet_dev      device, float [nsteps][nsrc] (as sfm_step)
+ *   grad_traces_dev  device, float [nrec][ld]: r^n in column n (caller's receiver order)
+ *   grad_gamma, grad_gamma_hat  host, double [S][k][p][p]
+ * Device memory: checkpoints 2 ceil(nsteps / L) states, a segment of 2 L + 2 states, 64 window
+ * states and S (2k-1) p^2 doubles (state = S k P16 floats).  Requires SFM_PREC_FP32 and
+ * receivers.  Synchronizes; the single-shot state is left at rest (n = 0).
+ * Errors: SFM_ESTATE, SFM_EINVAL, SFM_EUNSTABLE, SFM_ENOMEM. */
+sfm_status sfm_adjoint_gradient(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet_dev,
+                                const float* grad_traces_dev, int64_t ld, int32_t checkpoint_every,
+                                double* grad_gamma, double* grad_gamma_hat, void* stream);
+
 /* ---- many shots through the same ROMs (Stage 2 with a 64-column right-hand side) ----
  * The S-fraction blocks do not depend on the source, so up to 64 shots share one pass over
  * the coefficient stream per step: the block products of eq. "intrtstep" become (6m x 6m) x

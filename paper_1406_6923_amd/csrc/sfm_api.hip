@@ -559,6 +559,35 @@ static hipError_t apply_operator(sfm_ctx c, const float* u, float* a, hipStream_
   return launch_step_face(f, st);
 }
 
+// One leapfrog step of the single-shot state (no receivers): wavelet_row = this step's source
+// amplitudes [nsrc]; kx_out (optional) receives the interior flux differences of the step.
+sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, hipStream_t st) {
+  StepParams prm = make_step_params(c);
+  FaceParams f = make_face_params(c);
+  prm.mode = 0;
+  f.mode = 0;
+  prm.dt2 = (float)(dt * dt);
+  f.dt2 = prm.dt2;
+  prm.nsrc = f.nsrc = c->nsrc;
+  prm.wavelet = f.wavelet = wavelet_row;
+  prm.step = f.step = 0;
+  if (c->nsrc > 0) {
+    prm.src_off = c->src_off_d;
+    prm.src_ids = c->src_ids_d;
+    prm.src_vec = c->src_vec_d;
+    f.sw_off = c->sw_off_d;
+    f.sw_q = c->sw_q_d;
+    f.sw_src = c->sw_src_d;
+    f.sw_w = c->sw_w_d;
+  }
+  prm.kx_out = kx_out;
+  SFM_TRY_HIP(c, launch_step_main(prm, c->cfg.precision, st));
+  SFM_TRY_HIP(c, launch_step_face(f, st));
+  return SFM_OK;
+}
+
+StepParams step_params(sfm_ctx c) { return make_step_params(c); }
+
 }  // namespace sfm
 
 extern "C" {

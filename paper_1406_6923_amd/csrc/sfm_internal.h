@@ -97,6 +97,8 @@ struct StepParams {
   int64_t step;
   float dt2;
   int mode;                   // 0 = leapfrog step, 1 = apply operator
+  float* kx_out;              // optional [S][k][P16]: the interior flux differences phi_j - phi_{j-1}
+                              // (j >= 2) of this step, for the adjoint's recomputed segments
   float* hist;                // receiver-subdomain state history [Tw][n_rs][k][P16] (or null)
   const int32_t* hist_slot;   // [S] history slot of each subdomain, -1 if it holds no receiver
   int64_t hist_off;           // offset of this step's time slot in hist
@@ -171,6 +173,8 @@ sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vec
                          hipStream_t st);
 void release_roms(sfm_ctx c);
 void release_shots(sfm_ctx c);
+sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, hipStream_t st);
+StepParams step_params(sfm_ctx c);
 void destroy_blas(sfm_ctx c);
 
 }  // namespace sfm

@@ -70,6 +70,7 @@ SIGNATURES = {
     "sfm_build_roms_shifted": (_I32, [_VP, _D, _D, _I32, _VP, _I32, _VP, _I32, _VP, _VP, _VP,
                                       ctypes.POINTER(_I32), _VP]),
     "sfm_reset_state": (_I32, [_VP, _D, _VP]),
+    "sfm_adjoint_gradient": (_I32, [_VP, _I32, _D, _VP, _VP, _I64, _I32, _VP, _VP, _VP]),
     "sfm_shots_init": (_I32, [_VP, _I32, _VP, _VP]),
     "sfm_shots_step": (_I32, [_VP, _I32, _D, _VP, _VP, _I64, _VP]),
     "sfm_shots_get_state": (_I32, [_VP, _VP, _VP]),
@@ -233,6 +234,21 @@ def sfm_step(ctx: int, nsteps: int, dt: float, wavelet=None, traces=None, ld: Op
         ld = traces.shape[-1] if traces is not None else 0
     _check(ctx, load_library().sfm_step(ctx, int(nsteps), float(dt), _dev(wavelet), _dev(traces), int(ld),
                                         _stream(stream)))
+
+
+def sfm_adjoint_gradient(ctx: int, nsteps: int, dt: float, wavelet, grad_traces, checkpoint_every: int = 100,
+                         ld: Optional[int] = None, stream=None):
+    """dJ/dGamma, dJ/dGamma-hat (FP64 [S][k][p][p] each) for trace gradient grad_traces [nrec][ld] (device)."""
+    info = sfm_query(ctx)
+    shape = (info["n_subdomains"], info["k"], info["p"], info["p"])
+    g_gam = np.zeros(shape)
+    g_hat = np.zeros(shape)
+    if ld is None:
+        ld = grad_traces.shape[-1]
+    _check(ctx, load_library().sfm_adjoint_gradient(ctx, int(nsteps), float(dt), _dev(wavelet), _dev(grad_traces),
+                                                    int(ld), int(checkpoint_every), _ptr(g_gam), _ptr(g_hat),
+                                                    _stream(stream)))
+    return g_gam, g_hat
 
 
 def sfm_shots_init(ctx: int, nshot: int, shot_src=None, stream=None) -> None:
