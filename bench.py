@@ -208,6 +208,53 @@ def shots_probe(torch, sfm, h, cfg, dev, stream, dt, ratio, nshot, first_src, wa
     return out
 
 
+def adjoint_probe(torch, sfm, dev, stream, nsteps: int, checkpoint_every: int = 100):
+    """Misfit gradient on the gradient workload: observed traces from the medium with the Gaussian
+    anomaly, ROMs of the background medium, J = 1/2 ||traces - observed||^2, dJ/d(Gamma, Gamma-hat)
+    by the discrete adjoint with checkpoints; timed forward and gradient."""
+    cfg = W.CFG_ADJOINT
+    c_bg = cfg.velocity_model()
+    c_true = W.gaussian_anomaly(c_bg, **W.ADJOINT_ANOMALY)
+    src, rec = cfg.sources(), cfg.receivers()
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
+    out = {"workload": cfg.name, "subdomains": cfg.n_subdomains, "m": cfg.m, "k": cfg.k, "p": cfg.p,
+           "steps": nsteps, "receivers": len(rec), "checkpoint_every": checkpoint_every,
+           "anomaly": "+5% Gaussian, radius 30 cells, domain centre"}
+    tr_obs = torch.zeros((len(rec), nsteps), dtype=torch.float32, device=dev)
+    tr = torch.zeros_like(tr_obs)
+    h_obs = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
+    sfm.sfm_build_roms(h_obs.ctx, torch.from_numpy(c_true.astype(np.float32)).to(dev), src, rec, stream=stream)
+    dt_true = sfm.sfm_cfl_dt(h_obs.ctx, 100, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sfm.sfm_build_roms(h.ctx, torch.from_numpy(c_bg.astype(np.float32)).to(dev), src, rec, stream=stream)
+    torch.cuda.synchronize()
+    out["build_seconds"] = time.perf_counter() - t0
+    dt = 0.9 * min(dt_true, sfm.sfm_cfl_dt(h.ctx, 100, stream=stream))
+    wav = torch.tensor(W.ricker(cfg.f_peak, dt, nsteps)[:, None], dtype=torch.float32, device=dev)
+    sfm.sfm_step(h_obs.ctx, nsteps, dt, wav, tr_obs, stream=stream)      # observed data
+    h_obs.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sfm.sfm_step(h.ctx, nsteps, dt, wav, tr, stream=stream)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    resid = (tr - tr_obs).contiguous()
+    J = 0.5 * float((resid.double() ** 2).sum().item())
+    t0 = time.perf_counter()
+    g_gam, g_hat = sfm.sfm_adjoint_gradient(h.ctx, nsteps, dt, wav, resid, checkpoint_every, stream=stream)
+    t_grad = time.perf_counter() - t0
+    h.close()
+    out.update(dt=dt, misfit=J, forward_seconds=t_fwd, forward_ms_per_step=t_fwd / nsteps * 1e3,
+               gradient_seconds=t_grad, gradient_over_forward=t_grad / t_fwd,
+               grad_gamma_norm=float(np.linalg.norm(g_gam)), grad_gamma_hat_norm=float(np.linalg.norm(g_hat)),
+               gradient_finite=bool(np.isfinite(g_gam).all() and np.isfinite(g_hat).all()),
+               fine_equiv_gcell_per_s_gradient=cfg.n_cells * nsteps / t_grad / 1e9)
+    log(f"[bench] adjoint ({cfg.name}, {nsteps} steps): forward {t_fwd:.3f} s, gradient {t_grad:.3f} s "
+        f"({t_grad / t_fwd:.2f}x the forward), misfit {J:.4e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +272,8 @@ def main():
     ap.add_argument("--shots", type=int, default=64,
                     help="shots stepped together through the same ROMs after the single-shot run (0: skip)")
     ap.add_argument("--shot-steps", type=int, default=100)
+    ap.add_argument("--adjoint-steps", type=int, default=4000,
+                    help="steps of the misfit-gradient probe on the 256^3 gradient workload (0: skip)")
     ap.add_argument("--no-finite-shift", action="store_true",
                     help="skip the finite-shift ROM probe (4^3-subdomain sample of the same ROM shape)")
     args = ap.parse_args()
@@ -404,6 +453,8 @@ def main():
                                    args.shot_steps, nrec, ms_per_step)
     if not args.no_finite_shift:
         out["finite_shift"] = finite_shift_probe(torch, sfm, dev, stream)
+    if args.adjoint_steps:
+        out["adjoint"] = adjoint_probe(torch, sfm, dev, stream, args.adjoint_steps)
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline: oracle on a one-subdomain sample")
         out["cpu_baseline"] = cpu_baseline(cfg, c, ratio)

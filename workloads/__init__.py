@@ -178,3 +178,21 @@ def scaled_large(nsub: Tuple[int, int, int], seed: int = 1406, nsteps: int = 200
         nsteps=nsteps, src=(src,), rec_grid=(rx, ry), velocity="layered_inclusions",
         seed=seed)
 
+
+
+def gaussian_anomaly(c: np.ndarray, center, radius: float, amplitude: float) -> np.ndarray:
+    """c (1 + amplitude exp(-r^2 / radius^2)), r the distance in nodes from center = (i, j, l)."""
+    nz, ny, nx = c.shape
+    l, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r2 = (i - center[0]) ** 2 + (j - center[1]) ** 2 + (l - center[2]) ** 2
+    return c * (1.0 + amplitude * np.exp(-r2 / (radius * radius)))
+
+
+# Gradient workload: 256^3 cells in 32^3-cell subdomains, m = 12 (p = 72), k = 16, 4000 steps,
+# 128 x 128 surface receivers; observed data from the same medium with a +5% Gaussian anomaly
+# of radius 30 cells at the centre.
+CFG_ADJOINT = Workload(
+    name="layered_256c_8x8x8_m12_k16_adjoint", ncell=(256, 256, 256), sub_cells=(32, 32, 32), h=10.0,
+    m=12, k=16, f_peak=12.0, nsteps=4000, src=((127, 127, 2),), rec_grid=(128, 128),
+    velocity="layered_inclusions", seed=1406)
+ADJOINT_ANOMALY = dict(center=(128, 128, 128), radius=30.0, amplitude=0.05)
