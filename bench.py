@@ -85,6 +85,24 @@ def cpu_baseline(cfg: W.Workload, c_full: np.ndarray, dt_ratio: float, nsub=(1, 
     cs.run(dt, np.zeros((nsteps, 0)), U0=U, U_prev=U)
     t_step = time.perf_counter() - t0
     cells = nsub[0] * sx * nsub[1] * sy * nsub[2] * sz
+    one_thread = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            cs.run(dt, np.zeros((nsteps, 0)), U0=U, U_prev=U)
+            one_thread = cells * nsteps * dt_ratio / (time.perf_counter() - t0) / 1e9
+    except Exception:  # pragma: no cover
+        pass
+    # the oracle's fine-grid FDTD on the same box, at its own stability limit
+    from oracle import grid
+    fg = grid.FineGrid(box, cfg.h)
+    nf = 200
+    dtf = 0.9 * fg.cfl_dt()
+    src = np.array([[box.shape[2] // 2, box.shape[1] // 2, box.shape[0] // 2]])
+    t0 = time.perf_counter()
+    fg.fdtd(dtf, W.ricker(cfg.f_peak, dtf, nf)[:, None], src, np.array([[1, 1, 0]]))
+    fdtd_rate = cells * nf / (time.perf_counter() - t0) / 1e9
     return {
         "value": cells * nsteps * dt_ratio / t_step / 1e9,
         "unit": "Gcell-updates/s (fine-grid-equivalent)",
@@ -96,6 +114,8 @@ def cpu_baseline(cfg: W.Workload, c_full: np.ndarray, dt_ratio: float, nsub=(1, 
                    f"of the coupled ROMs timed; dt ratio taken from the GPU run"),
         "builds_per_s": len(subs) / t_build,
         "step_seconds": t_step,
+        "value_one_thread": one_thread,
+        "oracle_fine_fdtd_gcell_per_s": fdtd_rate,
     }
 
 
