@@ -112,14 +112,15 @@ def layer_differences(U: List[np.ndarray]) -> List[np.ndarray]:
 
 def gradient(cs: CoupledSystem, dt: float, wavelets: np.ndarray, observed: np.ndarray):
     """Misfit J and its gradient: (J, grad_gamma [S][k][p][p], grad_gamma_hat [S][k][p][p]);
-    grad_gamma_hat[:, 0] is zero (face masses held fixed)."""
+    grad_gamma_hat[:, 0] is zero (face masses held fixed).  With subdomain ROMs of different
+    sizes k is the largest; the blocks past a subdomain's own k are zero."""
     traces, X = forward(cs, dt, wavelets)
     J = misfit(traces, observed)
     resid = traces - np.asarray(observed)
     N = resid.shape[1]
     adj = Adjoint(cs)
     S = len(cs.roms)
-    k, p = cs.roms[0].k, cs.roms[0].p
+    k, p = max(r.k for r in cs.roms), cs.roms[0].p
     g_gam = np.zeros((S, k, p, p))
     g_hat = np.zeros((S, k, p, p))
     psi1 = np.zeros(adj.n)          # psi^{m+1}
@@ -135,7 +136,7 @@ def gradient(cs: CoupledSystem, dt: float, wavelets: np.ndarray, observed: np.nd
             DX = layer_differences(X[n])
             KX = interior_flux_difference(cs, X[n])
             for a in range(S):
-                for j in range(k):
+                for j in range(cs.roms[a].k):
                     g_gam[a, j] -= dt * dt * np.outer(Dz[a][j], DX[a][j])
                     if j >= 1:
                         g_hat[a, j] += dt * dt * np.outer(pz[a][j], KX[a][j])

@@ -46,6 +46,33 @@ def oracle_case(name: str = "small", sigma: float = np.inf):
     return cfg, c, subs, roms, cs
 
 
+def level_table(S: int, k: int, seed: int) -> np.ndarray:
+    """Seeded ROM size per subdomain in [2, k]; the first subdomain keeps k, the last takes 2."""
+    rng = np.random.default_rng(seed)
+    ks = rng.integers(2, k + 1, size=S)
+    ks[0], ks[-1] = k, 2
+    return ks.astype(np.int32)
+
+
+@functools.lru_cache(maxsize=4)
+def mixed_level_case(name: str = "small", seed: int = 21):
+    """The named case with every subdomain's ROM built by the oracle at its own size k_s
+    (Algorithm 1, Stage 1 per subdomain): (cfg, subs, roms_ks, cs_ks, ks)."""
+    cfg, c, subs, roms, cs = oracle_case(name)
+    ks = level_table(len(subs), cfg.k, seed)
+    roms_ks = [rom.build_rom(sd, int(kk)) for sd, kk in zip(subs, ks)]
+    cs_ks = coupled.CoupledSystem(subs, roms_ks, cfg.sources(), cfg.receivers())
+    return cfg, subs, roms_ks, cs_ks, ks
+
+
+def pad_levels(U, k: int) -> np.ndarray:
+    """Per-subdomain [k_s][...] arrays stacked into [S][k][...] with zero levels past k_s."""
+    out = np.zeros((len(U), k) + np.asarray(U[0]).shape[1:])
+    for a, Ua in enumerate(U):
+        out[a, :len(Ua)] = Ua
+    return out
+
+
 def rom_arrays(cs: coupled.CoupledSystem):
     """FP64 arrays in the C-ABI layout: gamma/gamma_hat [S][k][p][p], src [nsrc][k][p], rec [nrec][k][p]."""
     gam = np.stack([r.gamma for r in cs.roms])

@@ -3,7 +3,8 @@
 * A^T from the assembled stiffness (-K M^{-1}) against the per-subdomain steps 2.1-2.3 of
   ``CoupledSystem.accel`` through a dot-product test <psi, A x> = <A^T psi, x>;
 * the gradient against central finite differences of the oracle's own forward misfit on 20
-  random symmetric directions over every Gamma_j and Gamma-hat_j (j >= 2) block;
+  random symmetric directions over every Gamma_j and Gamma-hat_j (j >= 2) block, with one ROM
+  size for all subdomains and with a seeded size per subdomain;
 * zero residual gives a zero gradient.
 """
 import numpy as np
@@ -11,7 +12,7 @@ import pytest
 
 import workloads as W
 from oracle import adjoint, coupled
-from tests.cases import oracle_case
+from tests.cases import mixed_level_case, oracle_case
 
 
 @pytest.fixture(scope="module")
@@ -42,8 +43,11 @@ def _case(cs, cfg, nsteps=120):
     return dt, wav, observed
 
 
-def test_adjoint_gradient_matches_central_differences(small):
+@pytest.mark.parametrize("levels", ["uniform", "mixed"])
+def test_adjoint_gradient_matches_central_differences(small, levels):
     cfg, c, subs, roms, cs = small
+    if levels == "mixed":                    # every subdomain's ROM at its own size
+        cfg, subs, roms, cs, _ = mixed_level_case("small")
     dt, wav, observed = _case(cs, cfg)
     J, g_gam, g_hat = adjoint.gradient(cs, dt, wav, observed)
     assert J > 0 and np.abs(g_gam).max() > 0 and np.abs(g_hat[:, 1:]).max() > 0
@@ -58,7 +62,7 @@ def test_adjoint_gradient_matches_central_differences(small):
             dgam.append([np.abs(g).max() * (x + x.T) / 2 for g, x in zip(rom.sf.gamma, dg)])
             dhat.append([np.abs(g).max() * (x + x.T) / 2 for g, x in zip(rom.sf.gamma_hat, dh)])
         pred = sum(np.sum(g_gam[a, j] * dgam[a][j]) + (np.sum(g_hat[a, j] * dhat[a][j]) if j else 0.0)
-                   for a in range(len(roms)) for j in range(roms[0].k))
+                   for a in range(len(roms)) for j in range(roms[a].k))
         eps = 1e-6
         Jp = adjoint.misfit(adjoint.forward(adjoint.perturbed_system(cs, dgam, dhat, eps), dt, wav)[0], observed)
         Jm = adjoint.misfit(adjoint.forward(adjoint.perturbed_system(cs, dgam, dhat, -eps), dt, wav)[0], observed)

@@ -513,3 +513,59 @@ def test_e1_rom_size_arithmetic():
     per_dim = dof ** (1.0 / 3.0) * g["lambda_min"]
     assert round(per_dim) == g["rom_dof_per_wavelength_per_dimension"]
     assert round(g["subdomain_nodes_per_unit_length"] * g["lambda_min"]) == g["fine_points_per_wavelength"]
+
+
+# ----------------------------------------------------------------------------- per-subdomain ROM size
+@pytest.mark.parametrize("k2", [2, 5])
+def test_rom_of_fewer_levels_is_the_leading_part(small_case, k2):
+    """Stage 1 with k2 < k steps on a subdomain gives the first k2 blocks of the k-step result:
+    block Lanczos and the S-fraction recursion (G_1 = B_1^T, Gamma_j from A_j, G_j and Gamma_{j-1})
+    run forward in j, so Gamma_j, Gamma-hat_j, G_j and the source / receiver maps of levels j <= k2
+    do not depend on the later steps.  Checked against an independent k2-step build."""
+    cfg, c, subs, roms = small_case
+    for a in (0, 5):
+        sd, big = subs[a], roms[a]
+        small = rom.build_rom(sd, k2)
+        assert small.k == k2
+        for name in ("gamma", "gamma_hat", "G"):
+            x = np.stack(getattr(small.sf, name))
+            y = np.stack(getattr(big.sf, name))[:k2]
+            assert np.abs(x - y).max() <= 1e-12 * np.abs(y).max(), name
+        for node in (0, sd.N // 3, sd.N - 1):
+            np.testing.assert_allclose(small.source_vector(sd, node), big.source_vector(sd, node)[:k2],
+                                       rtol=0, atol=1e-12 * np.abs(big.source_vector(sd, node)).max())
+            np.testing.assert_allclose(small.receiver_row(sd, node), big.receiver_row(sd, node)[:k2],
+                                       rtol=0, atol=1e-10 * np.abs(big.receiver_row(sd, node)).max())
+
+
+def _mixed_system(small_case, seed=21):
+    cfg, c, subs, roms = small_case
+    rng = np.random.default_rng(seed)
+    ks = rng.integers(2, cfg.k + 1, size=len(subs))
+    ks[0], ks[-1] = cfg.k, 2
+    return coupled.CoupledSystem(subs, [rom.build_rom(sd, int(kk)) for sd, kk in zip(subs, ks)])
+
+
+def test_mixed_sizes_exchange_form_and_energy(small_case):
+    """Subdomain ROMs of different sizes couple through the boundary layer alone (steps 2.1-2.3):
+    the exchange form equals -M^{-1} K X of the assembled scheme, and leapfrog energy is constant."""
+    cs = _mixed_system(small_case)
+    assert len({r.k for r in cs.roms}) > 2
+    M, K, _ = cs.assemble()
+    import scipy.sparse.linalg as spla
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal(cs._dof_layout()[1])
+    ref = -spla.spsolve(M.tocsc(), K @ X)
+    assert np.linalg.norm(cs.gather(cs.accel(cs.scatter(X))) - ref) / np.linalg.norm(ref) < 1e-9
+    dt = 0.9 * cs.cfl_dt()
+    U = cs.scatter(rng.standard_normal(cs._dof_layout()[1]))
+    Up = [u.copy() for u in U]
+    e = []
+    for n in range(200):
+        acc = cs.accel(U)
+        Un = [2 * u - up + dt * dt * aa for u, up, aa in zip(U, Up, acc)]
+        Up, U = U, Un
+        e.append(cs.energy(M, K, cs.gather(U), cs.gather(Up), dt))
+    e = np.array(e)
+    assert np.abs(e - e[0]).max() / abs(e[0]) < 1e-10
+    assert cs.max_eig() <= coupled.subdomain_bound(cs.roms) * (1 + 1e-12)
