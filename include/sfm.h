@@ -214,8 +214,26 @@ sfm_status sfm_set_timing(sfm_ctx ctx, int32_t enable);
  * what get_state returned resumes bit-identically.  Synchronizes. */
 sfm_status sfm_get_state(sfm_ctx ctx, float* u_now, float* u_incr, int64_t* n);
 
-/* Restore a checkpoint written by sfm_get_state (NULL arrays mean zero).  Synchronizes. */
+/* Restore a checkpoint written by sfm_get_state (NULL arrays mean zero; levels a subdomain's
+ * ROM does not use, see sfm_set_levels, are set to zero).  Synchronizes. */
 sfm_status sfm_set_state(sfm_ctx ctx, const float* u_now, const float* u_incr, int64_t n);
+
+/* Per-subdomain ROM size (Algorithm 1, Stage 1 run with its own k on each subdomain).  Block
+ * Lanczos and the S-fraction recursions run forward in j, so the first k_s levels of a k-level
+ * ROM (Gamma_j, Gamma-hat_j, source projections and receiver rows for j <= k_s) are exactly the
+ * k_s-level ROM of the same subdomain: after a build or load with the largest k, this selects
+ * k_s levels for subdomain s in every later sfm_step, sfm_apply_operator, sfm_cfl_dt,
+ * sfm_shots_step and sfm_adjoint_gradient (levels j > k_s of the states are held at zero, their
+ * gradients are zero).
+ *   k_per_sub  host, int32 [S], 2 <= k_s <= k; NULL restores k levels everywhere.
+ * Restarts both states from the initial condition (n = 0) and forgets the last sfm_cfl_dt
+ * result (call it again: the limit grows as levels are dropped).  A new build or load clears
+ * the table.  Synchronizes.  Errors: SFM_ESTATE (no ROMs), SFM_EINVAL (k_s out of range; the
+ * previous table stays). */
+sfm_status sfm_set_levels(sfm_ctx ctx, const int32_t* k_per_sub);
+
+/* The levels in use per subdomain, host int32 [S] (k everywhere without a table). */
+sfm_status sfm_get_levels(sfm_ctx ctx, int32_t* k_per_sub);
 
 /* ------------------------------------------------------------------------------------------
  * Comparators on the same GPU (baselines, not the method's hot path)

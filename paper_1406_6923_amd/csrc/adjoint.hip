@@ -54,40 +54,41 @@ __global__ __launch_bounds__(kStepThreads) void adj_main_kernel(AdjParams prm) {
   const size_t sbase = (size_t)s * k * P;
   const float* tiles = reinterpret_cast<const float*>(gp.tiles) + (size_t)s * gp.words_per_sub;
   const int slot = prm.slot_of ? prm.slot_of[s] : -1;
+  const int ks = gp.k_of ? gp.k_of[s] : k;      // this ROM's levels; the others stay zero
 
-  // z_j = Gamma-hat_j psi_j, j = 2..k (blocks k .. 2k-2 of the stream)
-  for (int e = tid; e < (k - 1) * P; e += kStepThreads) {
+  // z_j = Gamma-hat_j psi_j, j = 2..ks (blocks k .. k + ks - 2 of the stream)
+  for (int e = tid; e < (ks - 1) * P; e += kStepThreads) {
     const float v = prm.Psi[sbase + P + e];
     xs[e] = v;
     if (prm.win_psi) prm.win_psi[sbase + P + e] = v;
   }
   __syncthreads();
-  run_phase<float>(tiles + (size_t)k * gp.words_per_block, k - 1, gp, xs, P, part, tid);
+  run_phase<float>(tiles + (size_t)k * gp.words_per_block, ks - 1, gp, xs, P, part, tid);
   __syncthreads();
-  for (int e = tid; e < (k - 1) * P; e += kStepThreads) {
+  for (int e = tid; e < (ks - 1) * P; e += kStepThreads) {
     const int b = e / P, i = e - b * P;
     zs[P + e] = reduce_entry(part, b, i, gp.nt, gp.nslots);
   }
   for (int e = tid; e < P; e += kStepThreads) zs[e] = prm.C[(size_t)s * P + e] * prm.Psi[sbase + e];   // z_1
   __syncthreads();
   // (D z)_j = z_{j+1} - z_j
-  for (int e = tid; e < k * P; e += kStepThreads) {
+  for (int e = tid; e < ks * P; e += kStepThreads) {
     const int j = e / P;
-    const float v = (j + 1 < k ? zs[e + P] : 0.f) - zs[e];
+    const float v = (j + 1 < ks ? zs[e + P] : 0.f) - zs[e];
     xs[e] = v;
     if (prm.win_dz) prm.win_dz[sbase + e] = v;
   }
   __syncthreads();
-  run_phase<float>(tiles, k, gp, xs, P, part, tid);                      // phi_j = Gamma_j (D z)_j
+  run_phase<float>(tiles, ks, gp, xs, P, part, tid);                     // phi_j = Gamma_j (D z)_j
   __syncthreads();
-  for (int e = tid; e < k * P; e += kStepThreads) {
+  for (int e = tid; e < ks * P; e += kStepThreads) {
     const int b = e / P, i = e - b * P;
     zs[e] = reduce_entry(part, b, i, gp.nt, gp.nslots);
   }
   __syncthreads();
   for (int e = tid; e < P; e += kStepThreads) prm.exch[(size_t)s * P + e] = zs[e];
   // interior layers: (A^T psi)_j = phi_j - phi_{j-1}
-  for (int e = tid; e < (k - 1) * P; e += kStepThreads) {
+  for (int e = tid; e < (ks - 1) * P; e += kStepThreads) {
     const size_t idx = sbase + P + e;
     float f = fmaf(prm.dt2, zs[e + P] - zs[e], prm.F[idx]);
     if (slot >= 0 && prm.gslot) f += prm.gslot[((size_t)slot * k) * P + P + e];
@@ -141,6 +142,7 @@ struct GradParams {
   const float* win_psi;        // [T][S][k][P16]
   const float* useg;           // [L + 1][S][k][P16] forward states of the segment
   const float* kxseg;          // [L][S][k][P16] forward (-K X) of the segment
+  const int32_t* k_of;         // [S] levels of each subdomain's ROM (null: all k)
   int first;                   // segment slot of window entry 0 (entry t is slot first - t)
   int w;                       // filled window entries
   int S, k, P, p;
@@ -157,6 +159,7 @@ __global__ __launch_bounds__(256) void grad_accum_kernel(GradParams prm) {
   const int k = prm.k, P = prm.P, p = prm.p;
   const bool hat = b >= k;
   const int j = hat ? b - k + 1 : b;           // layer index (0-based)
+  if (j >= (prm.k_of ? prm.k_of[s] : k)) return;   // a level this ROM does not have: gradient zero
   for (int e = threadIdx.x; e < prm.w * P; e += 256) {
     const int t = e / P, i = e - t * P;
     const size_t lay = ((size_t)s * k + j) * P + i;
@@ -283,6 +286,7 @@ extern "C" sfm_status sfm_adjoint_gradient(sfm_ctx c, int32_t nsteps, double dt,
   gp.win_psi = wpsi;
   gp.useg = useg;
   gp.kxseg = kxseg;
+  gp.k_of = c->k_of_d;
   gp.S = S;
   gp.k = k;
   gp.P = P;

@@ -33,7 +33,23 @@ __global__ void reset_state_kernel(float* U, float* D, const float* U0, const fl
   }
 }
 
+// Levels j >= k_of[s] of a [S][k][row] state are outside subdomain s's ROM: hold them at zero.
+__global__ void zero_levels_kernel(float* X, const int32_t* k_of, int k, int64_t row, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sj = i / row;
+    if ((int)(sj % k) >= k_of[sj / k]) X[i] = 0.f;
+  }
+}
+
 }  // namespace
+
+hipError_t sfm::clear_extra_levels(sfm_ctx c, float* X, int cols, hipStream_t st) {
+  if (!c->k_of_d || !X) return hipSuccess;
+  const sfm::Topology& t = c->topo;
+  const int64_t row = (int64_t)c->geo.P16 * cols;
+  hipLaunchKernelGGL(zero_levels_kernel, dim3(1024), dim3(256), 0, st, X, c->k_of_d, t.k, row, (int64_t)t.S * t.k * row);
+  return hipGetLastError();
+}
 
 // ----------------------------------------------------------------------------- context helpers
 void* sfm_ctx_s::dalloc(size_t bytes, hipError_t* e) {
@@ -75,6 +91,9 @@ void release_roms(sfm_ctx c) {
   c->sw_src_d = nullptr; c->sw_w_d = nullptr; c->rec_sub_d = nullptr; c->rec_rows_d = nullptr;
   c->rec_rows64_d = nullptr; c->U0_d = nullptr; c->V0_d = nullptr; c->rec_perm_d = nullptr;
   c->rs_off_d = nullptr; c->hist_slot_d = nullptr; c->hist_d = nullptr; c->plain_blocks_d = nullptr;
+  c->dfree(c->k_of_d);
+  c->k_of_d = nullptr;
+  c->k_of.clear();
   c->n_rs = 0;
   c->rs_max = 0;
   c->has_roms = false;
@@ -520,6 +539,7 @@ static StepParams make_step_params(sfm_ctx c) {
   prm.tail_off = g.tail_off;
   prm.S = c->topo.S;
   prm.k = c->topo.k;
+  prm.k_of = c->k_of_d;
   prm.P16 = g.P16;
   prm.nt = g.nt;
   prm.npairs = g.npairs;
@@ -794,7 +814,60 @@ sfm_status sfm_set_state(sfm_ctx c, const float* u_now, const float* u_incr, int
   if (u_incr)
     SFM_TRY_HIP(c, hipMemcpy2D(c->D_d, P16 * sizeof(float), u_incr, t.p * sizeof(float), t.p * sizeof(float),
                                (size_t)t.S * t.k, hipMemcpyHostToDevice));
+  SFM_TRY_HIP(c, sfm::clear_extra_levels(c, c->U_d, 1, nullptr));
+  SFM_TRY_HIP(c, sfm::clear_extra_levels(c, c->D_d, 1, nullptr));
+  SFM_TRY_HIP(c, hipDeviceSynchronize());
   c->n = n;
+  return SFM_OK;
+}
+
+sfm_status sfm_set_levels(sfm_ctx c, const int32_t* k_per_sub) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs: call sfm_build_roms or sfm_load_roms first");
+  const Topology& t = c->topo;
+  std::vector<int32_t> ks;
+  if (k_per_sub) {
+    ks.assign(k_per_sub, k_per_sub + t.S);
+    for (int s = 0; s < t.S; ++s)
+      if (ks[s] < 2 || ks[s] > t.k)
+        return c->fail(SFM_EINVAL, "subdomain " + std::to_string(s) + ": levels " + std::to_string(ks[s]) +
+                                       " outside [2, " + std::to_string(t.k) + "]");
+    if (std::all_of(ks.begin(), ks.end(), [&](int32_t v) { return v == t.k; })) ks.clear();
+  }
+  SFM_TRY_HIP(c, hipSetDevice(c->device));
+  SFM_TRY_HIP(c, hipDeviceSynchronize());
+  c->dfree(c->k_of_d);
+  c->k_of_d = nullptr;
+  c->k_of = ks;
+  if (!ks.empty()) {
+    hipError_t e = hipSuccess;
+    c->k_of_d = alloc_copy(c, ks, &e);
+    if (!c->k_of_d) {
+      c->k_of.clear();
+      return c->fail(SFM_ENOMEM, "level table: out of device memory");
+    }
+    SFM_TRY_HIP(c, e);
+  }
+  // the stepped system changed: states restart from the initial condition, the limit is unknown
+  hipLaunchKernelGGL(reset_state_kernel, dim3(1024), dim3(256), 0, nullptr, c->U_d, c->D_d, c->U0_d, nullptr, 0.f,
+                     (int64_t)t.S * t.k * c->geo.P16);
+  SFM_TRY_HIP(c, hipGetLastError());
+  SFM_TRY_HIP(c, sfm::clear_extra_levels(c, c->U_d, 1, nullptr));
+  SFM_TRY_HIP(c, sfm::clear_extra_levels(c, c->D_d, 1, nullptr));
+  SFM_TRY_HIP(c, sfm::clear_extra_levels(c, c->Us_d, kShotCols, nullptr));
+  SFM_TRY_HIP(c, sfm::clear_extra_levels(c, c->Ds_d, kShotCols, nullptr));
+  SFM_TRY_HIP(c, hipDeviceSynchronize());
+  c->n = 0;
+  c->dt_max = -1.0;
+  return SFM_OK;
+}
+
+sfm_status sfm_get_levels(sfm_ctx c, int32_t* k_per_sub) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!k_per_sub) return c->fail(SFM_EINVAL, "k_per_sub is NULL");
+  for (int s = 0; s < c->topo.S; ++s) k_per_sub[s] = c->k_of.empty() ? c->topo.k : c->k_of[s];
   return SFM_OK;
 }
 
@@ -808,6 +881,8 @@ sfm_status sfm_reset_state(sfm_ctx c, double dt, void* stream) {
   hipLaunchKernelGGL(reset_state_kernel, dim3(1024), dim3(256), 0, as_stream(stream), c->U_d, c->D_d, c->U0_d,
                      c->V0_d, (float)dt, n);
   SFM_TRY_HIP(c, hipGetLastError());
+  SFM_TRY_HIP(c, sfm::clear_extra_levels(c, c->U_d, 1, as_stream(stream)));
+  SFM_TRY_HIP(c, sfm::clear_extra_levels(c, c->D_d, 1, as_stream(stream)));
   c->n = 0;
   return SFM_OK;
 }

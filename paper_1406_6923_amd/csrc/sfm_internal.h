@@ -97,6 +97,7 @@ struct StepParams {
   int64_t step;
   float dt2;
   int mode;                   // 0 = leapfrog step, 1 = apply operator
+  const int32_t* k_of;        // optional [S]: levels of each subdomain's ROM (<= k; null: all k)
   float* kx_out;              // optional [S][k][P16]: the interior flux differences phi_j - phi_{j-1}
                               // (j >= 2) of this step, for the adjoint's recomputed segments
   float* hist;                // receiver-subdomain state history [Tw][n_rs][k][P16] (or null)
@@ -173,6 +174,8 @@ sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vec
                          hipStream_t st);
 void release_roms(sfm_ctx c);
 void release_shots(sfm_ctx c);
+// Zero the levels j >= k_of[s] of a [S][k][P16][cols] state (no-op without a level table).
+hipError_t clear_extra_levels(sfm_ctx c, float* X, int cols, hipStream_t st);
 sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, hipStream_t st);
 StepParams step_params(sfm_ctx c);
 void destroy_blas(sfm_ctx c);
@@ -239,6 +242,9 @@ struct sfm_ctx_s {
   double* red_d = nullptr;          // reduction scratch
   float* work_a_d = nullptr;        // [S][k][P16] operator scratch
   float* work_b_d = nullptr;
+
+  int32_t* k_of_d = nullptr;        // [S] per-subdomain levels (null: every subdomain uses k)
+  std::vector<int32_t> k_of;        // host copy
 
   bool has_roms = false;
   int64_t n = 0;

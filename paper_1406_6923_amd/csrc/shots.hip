@@ -45,6 +45,7 @@ struct ShotParams {
   float* U;                    // [S][k][P][64]
   float* D;
   float* exch;                 // [S][P][64]
+  const int32_t* k_of;         // [S] levels of each subdomain's ROM (null: all k)
   const int32_t* src_off;      // [S+1] interior sources of each subdomain
   const int32_t* src_ids;
   const int32_t* src_shot;     // [nsrc] shot driven by each source (-1: none)
@@ -132,6 +133,7 @@ __global__ __launch_bounds__(128 * (kMaxShotP16 / kTile), kMinWaves) void shots_
   const size_t sbase = (size_t)s * k * P * kShotCols;
   const int ns0 = prm.src_off ? prm.src_off[s] : 0;
   const int ns1 = prm.src_off ? prm.src_off[s + 1] : 0;
+  const int ks = prm.k_of ? prm.k_of[s] : k;   // this ROM's levels (>= 2); the others stay zero
   // X layout: this thread owns shot `lane` of rows w + i nw (i < 8) of every level; its global
   // accesses are 256-byte rows of 64 shots at a wave-uniform row offset.
   float* const Uw = prm.U + sbase + (size_t)w * kShotCols;
@@ -146,10 +148,10 @@ __global__ __launch_bounds__(128 * (kMaxShotP16 / kTile), kMinWaves) void shots_
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     Ua[i] = Uw[xrow(0, i) + lane];
-    Ub[i] = k > 1 ? Uw[xrow(1, i) + lane] : 0.f;
+    Ub[i] = Uw[xrow(1, i) + lane];
   }
   const int row0 = 16 * I + 4 * g;
-  for (int j = 0; j < k; ++j) {
+  for (int j = 0; j < ks; ++j) {
     __syncthreads();                                       // G, Xt free
     expand_block(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma_j
 #pragma unroll
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(128 * (kMaxShotP16 / kTile), kMinWaves) void shots_
       prefetch_block(prm.tiles + block_word(prm, s, 1), nq, tid, nthr, buf);           // Gamma_2
     }
 #pragma unroll
-    for (int i = 0; i < R; ++i) Un[i] = (j + 2 < k) ? Uw[xrow(j + 2, i) + lane] : 0.f;
+    for (int i = 0; i < R; ++i) Un[i] = (j + 2 < ks) ? Uw[xrow(j + 2, i) + lane] : 0.f;
     block_product(G, Xt, PP, P, I, sh, g, li, acc);        // phi_j
     __syncthreads();                                       // every wave done with G, Xt
 #pragma unroll
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(128 * (kMaxShotP16 / kTile), kMinWaves) void shots_
     if (j >= 1) {
       expand_block(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma-hat_j
       __syncthreads();
-      if (j + 1 < k) prefetch_block(prm.tiles + block_word(prm, s, j + 1), nq, tid, nthr, buf);   // Gamma_{j+1}
+      if (j + 1 < ks) prefetch_block(prm.tiles + block_word(prm, s, j + 1), nq, tid, nthr, buf);  // Gamma_{j+1}
       block_product(G, Xt, PP, P, I, sh, g, li, acc);        // a_j
       // sources of this subdomain: a_j += f_n(t) s_j for the shot n each source drives
       for (int q = ns0; q < ns1; ++q) {
@@ -463,6 +465,7 @@ ShotParams main_params(sfm_ctx c, const float* wavelet_dev, double dt) {
   prm.wmap = c->wmap_d;
   prm.S = t.S;
   prm.k = t.k;
+  prm.k_of = c->k_of_d;
   prm.P = g.P16;
   prm.PP = g.P16 + 4;
   prm.U = c->Us_d;
@@ -653,7 +656,9 @@ sfm_status sfm_shots_set_state(sfm_ctx c, const float* u_host, const float* d_ho
         std::memcpy(buf.data() + (sj * P + q) * kShotCols, ins[a] + (sj * t.p + q) * c->nshot,
                     c->nshot * sizeof(float));
     SH_TRY_HIP(hipMemcpy(dsts[a], buf.data(), buf.size() * sizeof(float), hipMemcpyHostToDevice));
+    SH_TRY_HIP(clear_extra_levels(c, dsts[a], kShotCols, nullptr));
   }
+  SH_TRY_HIP(hipDeviceSynchronize());
   return SFM_OK;
 }
 

@@ -41,34 +41,38 @@ __global__ __launch_bounds__(kStepThreads) void step_main_kernel(StepParams prm)
   const size_t sbase = (size_t)s * k * P;
   const float* Uin = prm.mode == 0 ? prm.U : prm.Uin;
   const T* tiles = reinterpret_cast<const T*>(prm.tiles) + (size_t)s * prm.words_per_sub;
+  // levels of this subdomain's ROM (the leading ks of the stored k; the others stay zero)
+  const int ks = prm.k_of ? prm.k_of[s] : k;
 
-  // U_{j+1} - U_j with U_{k+1} = 0
-  for (int e = tid; e < k * P; e += kStepThreads) {
+  // U_{j+1} - U_j with U_{ks+1} = 0
+  for (int e = tid; e < ks * P; e += kStepThreads) {
     const int j = e / P;
     const R u = Uin[sbase + e];
-    const R un = (j + 1 < k) ? (R)Uin[sbase + e + P] : (R)0;
+    const R un = (j + 1 < ks) ? (R)Uin[sbase + e + P] : (R)0;
     xs[e] = un - u;
   }
   __syncthreads();
-  run_phase<T, R>(tiles, k, prm, xs, vstride, part, tid);       // phi_j = Gamma_j dU_j
+  run_phase<T, R>(tiles, ks, prm, xs, vstride, part, tid);      // phi_j = Gamma_j dU_j
   __syncthreads();
-  for (int e = tid; e < k * P; e += kStepThreads) {
+  for (int e = tid; e < ks * P; e += kStepThreads) {
     const int b = e / P, i = e - b * P;
     ph[e] = reduce_entry(part, b, i, prm.nt, prm.nslots);
   }
   __syncthreads();
   for (int e = tid; e < P; e += kStepThreads) prm.exch[(size_t)s * P + e] = (float)ph[e];   // step 2.1
-  for (int e = tid; e < (k - 1) * P; e += kStepThreads) {
+  for (int e = tid; e < (ks - 1) * P; e += kStepThreads) {
     xs[e] = ph[e + P] - ph[e];                                          // phi_j - phi_{j-1}
     if (prm.kx_out) prm.kx_out[sbase + P + e] = (float)xs[e];           // (-K U)_j, j >= 2
   }
   __syncthreads();
-  run_phase<T, R>(tiles + (size_t)k * prm.words_per_block, k - 1, prm, xs, vstride, part, tid);
+  run_phase<T, R>(tiles + (size_t)k * prm.words_per_block, ks - 1, prm, xs, vstride, part, tid);
   __syncthreads();
   const int slot = (prm.mode == 0 && prm.hist) ? prm.hist_slot[s] : -1;
   const int s0 = prm.src_off ? prm.src_off[s] : 0;
   const int s1 = prm.src_off ? prm.src_off[s + 1] : 0;
-  for (int e = tid; e < (k - 1) * P; e += kStepThreads) {
+  if (prm.mode != 0)
+    for (int e = (ks - 1) * P + tid; e < (k - 1) * P; e += kStepThreads) prm.Aout[sbase + P + e] = 0.f;
+  for (int e = tid; e < (ks - 1) * P; e += kStepThreads) {
     const int b = e / P, i = e - b * P;
     R a = reduce_entry(part, b, i, prm.nt, prm.nslots);
     for (int q = s0; q < s1; ++q) {

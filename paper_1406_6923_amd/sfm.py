@@ -87,6 +87,8 @@ SIGNATURES = {
     "sfm_set_timing": (_I32, [_VP, _I32]),
     "sfm_get_state": (_I32, [_VP, _VP, _VP, ctypes.POINTER(_I64)]),
     "sfm_set_state": (_I32, [_VP, _VP, _VP, _I64]),
+    "sfm_set_levels": (_I32, [_VP, _VP]),
+    "sfm_get_levels": (_I32, [_VP, _VP]),
     "sfm_fdtd_run": (_I32, [_VP, _D, _VP, _D, _I32, _I32, _VP, _VP, _I32, _VP, _VP, _I64, ctypes.POINTER(_D), _VP]),
     "sfm_fdtd_last_error": (ctypes.c_char_p, []),
     "sfm_step_plain": (_I32, [_VP, _I32, _D, _VP, _VP]),
@@ -324,6 +326,18 @@ def sfm_set_state(ctx: int, u_now=None, u_incr=None, n: int = 0) -> None:
     u = _host(u_now, np.float32)
     d = _host(u_incr, np.float32)
     _check(ctx, load_library().sfm_set_state(ctx, _ptr(u), _ptr(d), int(n)))
+
+
+def sfm_set_levels(ctx: int, k_per_sub=None) -> None:
+    """Per-subdomain ROM levels (int per subdomain, 2..k); None restores k everywhere."""
+    ks = None if k_per_sub is None else _host(np.asarray(k_per_sub), np.int32)
+    _check(ctx, load_library().sfm_set_levels(ctx, _ptr(ks)))
+
+
+def sfm_get_levels(ctx: int) -> np.ndarray:
+    out = np.empty(sfm_query(ctx)["n_subdomains"], dtype=np.int32)
+    _check(ctx, load_library().sfm_get_levels(ctx, _ptr(out)))
+    return out
 
 
 def sfm_fdtd_run(ncell, h: float, vel, dt: float, nsteps: int, src_ijk=None, wavelet=None, rec_ijk=None,
