@@ -112,8 +112,22 @@ def _boundary_faces(loc, cells):
     return np.stack([i == 0, i == sx, j == 0, j == sy, l == 0, l == sz], axis=1)
 
 
+def box_cuts(ncells: int, sub) -> List[int]:
+    """Plane positions 0 = x_0 < x_1 < ... = ncells along one axis: ``sub`` is the cell count of
+    every box (an int dividing ncells) or the list of the boxes' cell counts in order."""
+    if np.ndim(sub) == 0:
+        if ncells % int(sub):
+            raise ValueError("cells per axis must be a multiple of sub_cells")
+        sub = [int(sub)] * (ncells // int(sub))
+    cuts = np.concatenate([[0], np.cumsum(np.asarray(sub, dtype=np.int64))]).tolist()
+    if cuts[-1] != ncells or min(np.diff(cuts)) < 1:
+        raise ValueError("box sizes along an axis must be positive and add up to its cells")
+    return [int(x) for x in cuts]
+
+
 def decompose(c: np.ndarray, h: float, sub_cells, m: int, mode: str = "patches") -> List[Subdomain]:
-    """Split the node grid ``c`` ([nz][ny][nx]) into boxes of ``sub_cells`` cells.
+    """Split the node grid ``c`` ([nz][ny][nx]) into a tensor product of boxes: per axis,
+    ``sub_cells`` gives one cell count for all boxes or the list of box cell counts.
 
     ``mode = "patches"``: the m-patch basis on all six faces (p = 6m).
     ``mode = "interface_nodes"``: one function per node owned by an interface
@@ -121,17 +135,16 @@ def decompose(c: np.ndarray, h: float, sub_cells, m: int, mode: str = "patches")
     """
     c = np.asarray(c, dtype=np.float64)
     nz, ny, nx = c.shape
-    sx, sy, sz = sub_cells
-    if (nx - 1) % sx or (ny - 1) % sy or (nz - 1) % sz:
-        raise ValueError("cells per axis must be a multiple of sub_cells")
-    Bx, By, Bz = (nx - 1) // sx, (ny - 1) // sy, (nz - 1) // sz
+    cx, cy, cz = (box_cuts(n - 1, s) for n, s in zip((nx, ny, nz), sub_cells))
+    Bx, By, Bz = len(cx) - 1, len(cy) - 1, len(cz) - 1
     m1, m2 = factor_patches(m) if mode == "patches" else (0, 0)
     subs = []
     for bz in range(Bz):
         for by in range(By):
             for bx in range(Bx):
                 idx = (bz * By + by) * Bx + bx
-                i0, j0, l0 = bx * sx, by * sy, bz * sz
+                i0, j0, l0 = cx[bx], cy[by], cz[bz]
+                sx, sy, sz = cx[bx + 1] - i0, cy[by + 1] - j0, cz[bz + 1] - l0
                 cl = c[l0:l0 + sz + 1, j0:j0 + sy + 1, i0:i0 + sx + 1].copy()
                 box = (bx, by, bz)
                 nb = []

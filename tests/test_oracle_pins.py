@@ -51,12 +51,14 @@ def test_fine_operator_is_mirror_neumann_7point():
     np.testing.assert_allclose(got, (c ** 2 * lap).ravel(), rtol=1e-12, atol=1e-12 * np.abs(got).max())
 
 
-def test_subdomain_operators_sum_to_global():
-    """Shared interface nodes get complementary halves: sum_alpha M^alpha = M, sum K^alpha = K."""
-    c = tiny_box((6, 4, 6), seed=5)
+@pytest.mark.parametrize("cells, split", [((6, 4, 6), (3, 2, 2)), ((7, 4, 6), ((3, 4), (2, 2), (4, 2)))])
+def test_subdomain_operators_sum_to_global(cells, split):
+    """Shared interface nodes get complementary halves: sum_alpha M^alpha = M, sum K^alpha = K
+    (equal boxes, and a tensor product of boxes of uneven size)."""
+    c = tiny_box(cells, seed=5)
     h = 3.0
     g = grid.FineGrid(c, h)
-    subs = subdomains.decompose(c, h, (3, 2, 2), m=1)
+    subs = subdomains.decompose(c, h, split, m=1)
     Msum = np.zeros(g.M.size)
     Ksum = sp.csr_matrix(g.K.shape)
     nz, ny, nx = c.shape
@@ -393,6 +395,26 @@ def test_two_subdomains_nodal_interface_equals_fdtd():
     roms = rom.build_all(subs, 3)
     src = [(1, 1, 1)]
     rec = [(0, 0, 4), (1, 1, 3), (2, 0, 2), (1, 2, 0)]
+    g = grid.FineGrid(c, h)
+    dt = 0.9 * g.cfl_dt()
+    wav = W.ricker(1.0 / (40 * dt), dt, 400)[:, None]
+    cs = coupled.CoupledSystem(subs, roms, src, rec)
+    tr = cs.run(dt, wav)
+    ref = g.fdtd(dt, wav, src, rec)
+    assert np.linalg.norm(tr - ref) / np.linalg.norm(ref) < 1e-8
+
+
+def test_uneven_boxes_own_sizes_nodal_interface_equals_fdtd():
+    """Boxes of 3 x 3 x 3 and 3 x 3 x 4 nodes, one boundary function per interface node and each
+    ROM at its own k with k p = N (k = 3 and 4): the coupled scheme reproduces the global FDTD
+    (P7 with uneven subdomains and ROM sizes)."""
+    c = tiny_box((2, 2, 5), seed=33)          # 3 x 3 x 6 nodes
+    h = 10.0
+    subs = subdomains.decompose(c, h, (2, 2, (2, 3)), m=0, mode="interface_nodes")
+    assert [sd.p for sd in subs] == [9, 9] and [sd.N for sd in subs] == [27, 36]
+    roms = [rom.build_rom(subs[0], 3), rom.build_rom(subs[1], 4)]
+    src = [(1, 1, 1)]
+    rec = [(0, 0, 5), (1, 1, 4), (2, 0, 2), (1, 2, 0)]
     g = grid.FineGrid(c, h)
     dt = 0.9 * g.cfl_dt()
     wav = W.ricker(1.0 / (40 * dt), dt, 400)[:, None]

@@ -24,7 +24,7 @@ class Workload:
 
     name: str
     ncell: Tuple[int, int, int]          # cells along x, y, z
-    sub_cells: Tuple[int, int, int]      # cells per subdomain edge (x, y, z)
+    sub_cells: tuple                     # per axis (x, y, z): cells of every box, or the box sizes in order
     h: float                             # grid step in metres
     m: int                               # boundary basis functions per face
     k: int                               # S-fraction levels (number of blocks)
@@ -41,7 +41,20 @@ class Workload:
 
     @property
     def nsub(self) -> Tuple[int, int, int]:
-        return tuple(c // s for c, s in zip(self.ncell, self.sub_cells))
+        return tuple(len(s) if np.ndim(s) else c // s for c, s in zip(self.ncell, self.sub_cells))
+
+    def box_cells(self, axis: int) -> List[int]:
+        """Cell counts of the boxes along one axis."""
+        s = self.sub_cells[axis]
+        return [int(x) for x in s] if np.ndim(s) else [int(s)] * (self.ncell[axis] // int(s))
+
+    def on_box_plane(self, ijk) -> bool:
+        """True when a node lies on a subdomain plane along any axis."""
+        for d in range(3):
+            cuts = np.concatenate([[0], np.cumsum(self.box_cells(d))])
+            if int(ijk[d]) in cuts:
+                return True
+        return False
 
     @property
     def n_subdomains(self) -> int:
