@@ -95,6 +95,17 @@ typedef struct {
  *         SFM_EHIP (no usable device).  *out is NULL on failure. */
 sfm_status sfm_create(const sfm_config* cfg, sfm_ctx* out);
 
+/* As sfm_create with boxes of uneven size (the decomposition of the Introduction needs no equal
+ * subdomains): the grid is the tensor product of nbox[0] x nbox[1] x nbox[2] boxes, and along
+ * axis d box b has box_cells[nbox[0] + .. + nbox[d-1] + b] cells (each >= 2, adding up to
+ * ncell[d]); cfg->sub_cells is ignored.  Neighbours across a face share the whole face, so its
+ * m patches match on both sides; p = 6m on every subdomain, and 6mk must not exceed the nodes of
+ * the smallest box.  The ROM build groups subdomains of one shape into its batches.
+ *   nbox       host, int32 [3]
+ *   box_cells  host, int32 [nbox[0] + nbox[1] + nbox[2]]; both NULL selects equal boxes.
+ * Errors as sfm_create. */
+sfm_status sfm_create_boxes(const sfm_config* cfg, const int32_t* nbox, const int32_t* box_cells, sfm_ctx* out);
+
 /* Release every device buffer owned by ctx (NULL is ignored). */
 void sfm_destroy(sfm_ctx ctx);
 

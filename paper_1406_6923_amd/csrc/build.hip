@@ -500,6 +500,17 @@ __global__ void copy_blocks_kernel(const double* __restrict__ src, int64_t ss, d
   }
 }
 
+// dst[ids[b] * sd + e] = src[b * ss + e], e < n: batch results to their subdomains' slots.
+__global__ void scatter_blocks_kernel(const double* __restrict__ src, int64_t ss, double* __restrict__ dst, int64_t sd,
+                                      int64_t n, int nb, const int32_t* __restrict__ ids) {
+  const int64_t total = (int64_t)nb * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / n);
+    const int64_t e = idx - (int64_t)b * n;
+    dst[(int64_t)ids[b] * sd + e] = src[b * ss + e];
+  }
+}
+
 // Source vectors s_j = G_j z_j and receiver rows r_j = z_j^T G_j^{-1} with z = M^{-1/2} Z^T e_node.
 __global__ void project_points_kernel(const double* __restrict__ Z, const double* __restrict__ S, int64_t N, int k, int p,
                                       const double* __restrict__ G, const double* __restrict__ Gi, int64_t sg,
@@ -547,7 +558,7 @@ __global__ void project_field_kernel(BoxGeo g, const double* __restrict__ Z, con
 
 // U_j = G_j y_j into the FP32 state layout [S][k][P16].
 __global__ void apply_g_kernel(const double* __restrict__ y, const double* __restrict__ G, int64_t sg, int k, int p,
-                               int P16, int nb, int s0, float* __restrict__ U) {
+                               int P16, int nb, const int32_t* __restrict__ ids, float* __restrict__ U) {
   const int64_t total = (int64_t)nb * k * p;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     const int e = (int)(idx % p);
@@ -558,7 +569,7 @@ __global__ void apply_g_kernel(const double* __restrict__ y, const double* __res
     const double* yj = y + (int64_t)b * k * p + (int64_t)j * p;
     double acc = 0.0;
     for (int c = 0; c < p; ++c) acc += M[e + (int64_t)c * p] * yj[c];
-    U[(((int64_t)(s0 + b)) * k + j) * P16 + e] = (float)acc;
+    U[(((int64_t)ids[b]) * k + j) * P16 + e] = (float)acc;
   }
 }
 
@@ -648,7 +659,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const Topology& t = c->topo;
   const int S = t.S, k = t.k, p = t.p, kp = k * p, P16 = c->geo.P16;
-  const int64_t N = t.N_local;
+  const int64_t Nmax = t.N_max;
   const int64_t pp = (int64_t)p * p;
   const int64_t kpkp = (int64_t)kp * kp;
   std::vector<int32_t> src_sub, src_local, rec_sub, rec_local;
@@ -681,8 +692,8 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
 
   // batch size from the free device memory
   int64_t per_sub = (int64_t)sizeof(double) *
-                    (N * kp + N * p + N + 2 * (int64_t)kp * p + 7 * (int64_t)k * pp + 6 * pp + kp + 8);
-  if (finite) per_sub += (int64_t)sizeof(double) * (3 * N * p + N + 2 * kpkp + 16 * (int64_t)p) +
+                    (Nmax * kp + Nmax * p + Nmax + 2 * (int64_t)kp * p + 7 * (int64_t)k * pp + 6 * pp + kp + 8);
+  if (finite) per_sub += (int64_t)sizeof(double) * (3 * Nmax * p + Nmax + 2 * kpkp + 16 * (int64_t)p) +
                          (int64_t)sizeof(double) * 2 * 1024 * p;
   int nbmax = c->cfg.build_batch;
   if (nbmax <= 0) {
@@ -692,11 +703,14 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
   }
   nbmax = std::min(nbmax, S);
   // CG chunks: enough work-groups per column sum to fill the device, at most 1024
-  const int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(1024, std::min<int64_t>(N, (2048 + nbmax - 1) / nbmax)));
+  auto chunks_for = [&](int64_t n) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(1024, std::min<int64_t>(n, (2048 + nbmax - 1) / nbmax)));
+  };
+  const int nchunk_max = chunks_for(Nmax);
   Scratch sc(c);
-  double* Z = sc.get((size_t)nbmax * N * kp);
-  double* Wl = sc.get((size_t)nbmax * N * p);
-  double* Sd = sc.get((size_t)nbmax * N);
+  double* Z = sc.get((size_t)nbmax * Nmax * kp);
+  double* Wl = sc.get((size_t)nbmax * Nmax * p);
+  double* Sd = sc.get((size_t)nbmax * Nmax);
   double* C1 = sc.get((size_t)nbmax * kp * p);
   double* C2 = sc.get((size_t)nbmax * kp * p);
   double* A = sc.get((size_t)nbmax * k * pp);
@@ -712,18 +726,18 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
   double* thr = sc.get((size_t)nbmax);
   double* ybuf = sc.get((size_t)nbmax * kp);
   int32_t* flags = sc.get<int32_t>((size_t)nbmax + 1);
-  int32_t* meta = sc.get<int32_t>((size_t)nbmax * 4);
+  int32_t* meta = sc.get<int32_t>((size_t)nbmax * 5);
   int32_t* pts = sc.get<int32_t>((size_t)(std::max(nsrc, nrec) + 1) * 3);
   // finite shift: PCG vectors, reduced operator and reduced-space basis
   double *Dinv = nullptr, *Rv = nullptr, *Pv = nullptr, *Qv = nullptr, *part = nullptr, *cgs = nullptr;
   double *At = nullptr, *Zh = nullptr;
   int32_t *active = nullptr, *count = nullptr;
   if (finite) {
-    Dinv = sc.get((size_t)nbmax * N);
-    Rv = sc.get((size_t)nbmax * N * p);
-    Pv = sc.get((size_t)nbmax * N * p);
-    Qv = sc.get((size_t)nbmax * N * p);
-    part = sc.get((size_t)2 * nbmax * nchunk * p);
+    Dinv = sc.get((size_t)nbmax * Nmax);
+    Rv = sc.get((size_t)nbmax * Nmax * p);
+    Pv = sc.get((size_t)nbmax * Nmax * p);
+    Qv = sc.get((size_t)nbmax * Nmax * p);
+    part = sc.get((size_t)2 * nbmax * nchunk_max * p);
     cgs = sc.get((size_t)4 * nbmax * p);
     At = sc.get((size_t)nbmax * kpkp);
     Zh = sc.get((size_t)nbmax * kpkp);
@@ -731,48 +745,76 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
     count = sc.get<int32_t>(1);
   }
   if (sc.e != hipSuccess) return c->fail(SFM_ENOMEM, "ROM build scratch: out of device memory (lower build_batch)");
-  const BoxGeo g{{t.sub[0], t.sub[1], t.sub[2]}, {t.nodes_local[0], t.nodes_local[1], t.nodes_local[2]},
-                 t.m, t.m1, t.m2, p, c->cfg.h};
   std::vector<double> Hall((size_t)S * p);
   const double one = 1.0, zero = 0.0, mone = -1.0;
   const rocblas_operation NN = rocblas_operation_none, TT = rocblas_operation_transpose;
-  const int64_t sZ = N * kp;
 
   const char* vb = std::getenv("SFM_VERBOSE");
   const bool verbose = vb && vb[0] && vb[0] != '0';
   int cg_iters_max = 0;
   sfm_status status = SFM_OK;
-  for (int s0 = 0; s0 < S && status == SFM_OK; s0 += nbmax) {
-    const int nb = std::min(nbmax, S - s0);
-    // batch metadata: origins and neighbour masks
+  // Batches: up to nbmax subdomains of one box shape (all of them for equal boxes), in
+  // subdomain order within a shape.  ids[b] is the subdomain of batch member b.
+  std::vector<int32_t> order(S);
+  for (int s = 0; s < S; ++s) order[s] = s;
+  auto shape_key = [&](int s) {
+    int w[3];
+    t.cells(s, w);
+    return ((int64_t)w[2] * (t.ncell[1] + 1) + w[1]) * (t.ncell[0] + 1) + w[0];
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return shape_key(a) < shape_key(b); });
+  std::vector<int32_t> batch_of(S), pos_of(S);
+  int nbatch_done = 0;
+  for (size_t i0 = 0; i0 < order.size() && status == SFM_OK;) {
+    size_t i1 = i0 + 1;
+    while (i1 < order.size() && (int)(i1 - i0) < nbmax && shape_key(order[i1]) == shape_key(order[i0])) ++i1;
+    const int nb = (int)(i1 - i0);
+    const std::vector<int32_t> ids(order.begin() + i0, order.begin() + i1);
+    i0 = i1;
+    for (int b = 0; b < nb; ++b) {
+      batch_of[ids[b]] = nbatch_done;
+      pos_of[ids[b]] = b;
+    }
+    const int bidx = nbatch_done++;
+    int w[3];
+    t.cells(ids[0], w);
+    const BoxGeo g{{w[0], w[1], w[2]}, {w[0] + 1, w[1] + 1, w[2] + 1}, t.m, t.m1, t.m2, p, c->cfg.h};
+    const int64_t N = (int64_t)(w[0] + 1) * (w[1] + 1) * (w[2] + 1);
+    const int64_t sZ = N * kp;
+    const int nchunk = chunks_for(N);
+    // batch metadata: origins, neighbour masks, subdomain ids
     std::vector<int32_t> org(3 * nb), mask(nb);
     for (int b = 0; b < nb; ++b) {
       int o[3];
-      t.origin(s0 + b, o);
+      t.origin(ids[b], o);
       org[3 * b] = o[0]; org[3 * b + 1] = o[1]; org[3 * b + 2] = o[2];
       int mk = 0;
       for (int f = 0; f < 6; ++f)
-        if (t.nbr[(size_t)(s0 + b) * 6 + f] >= 0) mk |= 1 << f;
+        if (t.nbr[(size_t)ids[b] * 6 + f] >= 0) mk |= 1 << f;
       mask[b] = mk;
     }
     int32_t* org_d = meta;
     int32_t* mask_d = meta + 3 * nbmax;
+    int32_t* ids_d = meta + 4 * nbmax;
     B_TRY_HIP(hipMemcpyAsync(org_d, org.data(), org.size() * 4, hipMemcpyHostToDevice, st));
     B_TRY_HIP(hipMemcpyAsync(mask_d, mask.data(), mask.size() * 4, hipMemcpyHostToDevice, st));
+    B_TRY_HIP(hipMemcpyAsync(ids_d, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, st));
     B_TRY_HIP(hipMemsetAsync(flags, 0, (size_t)(nbmax + 1) * sizeof(int32_t), st));
 
     // a1: scaling, face masses, Q_1
     B_LAUNCH(node_scale_kernel, (int64_t)nb * N, g, vel_dev, t.ncell[0], t.ncell[1], org_d, N, nb, Sd, flags + nbmax);
     B_LAUNCH(face_mass_kernel, (int64_t)nb * p, g, Sd, mask_d, N, nb, Hb);
-    B_TRY_HIP(hipMemcpyAsync(Hall.data() + (size_t)s0 * p, Hb, (size_t)nb * p * sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> Hbat((size_t)nb * p);
+    B_TRY_HIP(hipMemcpyAsync(Hbat.data(), Hb, Hbat.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     B_TRY_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < nb; ++b) std::copy(Hbat.begin() + (size_t)b * p, Hbat.begin() + (size_t)(b + 1) * p, Hall.begin() + (size_t)ids[b] * p);
     std::vector<double> thr_h(nb);
     for (int b = 0; b < nb; ++b) {
       double hm = 0.0;
       for (int q = 0; q < p; ++q) {
-        const double hv = Hall[(size_t)(s0 + b) * p + q];
+        const double hv = Hall[(size_t)ids[b] * p + q];
         if (!(hv > 0.0))
-          return c->fail(SFM_EBREAKDOWN, "subdomain " + std::to_string(s0 + b) + ": empty boundary patch " +
+          return c->fail(SFM_EBREAKDOWN, "subdomain " + std::to_string(ids[b]) + ": empty boundary patch " +
                                              std::to_string(q) + " (rank-deficient start block)");
         hm = std::max(hm, hv);
       }
@@ -876,15 +918,15 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
           B_TRY_HIP(hipStreamSynchronize(st));
           if (na == 0) break;
           if (it >= shift.max_iter)
-            return c->fail(SFM_ENOCONV, "shifted solve of Lanczos block " + std::to_string(jj + 1) + " (subdomains " +
-                                            std::to_string(s0) + ".." + std::to_string(s0 + nb - 1) + "): " +
+            return c->fail(SFM_ENOCONV, "shifted solve of Lanczos block " + std::to_string(jj + 1) + " (build batch " +
+                                            std::to_string(bidx) + ", subdomains " + std::to_string(ids.front()) +
+                                            ".." + std::to_string(ids.back()) + "): " +
                                             std::to_string(na) + " columns above rtol after " + std::to_string(it) +
                                             " iterations");
         }
         cg_iters_max = std::max(cg_iters_max, it);
         if (verbose) {
-          std::fprintf(stderr, "[sfm] shifted build: block %d of subdomains %d..%d, %d CG iterations\n", jj + 1, s0,
-                       s0 + nb - 1, it);
+          std::fprintf(stderr, "[sfm] shifted build: block %d of batch %d, %d CG iterations\n", jj + 1, bidx, it);
           std::fflush(stderr);
         }
         return SFM_OK;
@@ -955,8 +997,8 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
                                                p, p, &mone, Btn, p, sk, Gin, p, sk, nb));
     }
     // coefficients to the FP64 store [S][2][k][p][p] (symmetric: column-major = row-major)
-    B_LAUNCH(copy_blocks_kernel, (int64_t)nb * sk, Gam, sk, c->coef64_d + (int64_t)s0 * 2 * sk, 2 * sk, sk, nb, 1.0);
-    B_LAUNCH(copy_blocks_kernel, (int64_t)nb * sk, Gh, sk, c->coef64_d + (int64_t)s0 * 2 * sk + sk, 2 * sk, sk, nb, 1.0);
+    B_LAUNCH(scatter_blocks_kernel, (int64_t)nb * sk, Gam, sk, c->coef64_d, 2 * sk, sk, nb, ids_d);
+    B_LAUNCH(scatter_blocks_kernel, (int64_t)nb * sk, Gh, sk, c->coef64_d + sk, 2 * sk, sk, nb, ids_d);
 
     // a4: projections of the points of this batch
     for (int mode = 0; mode < 2; ++mode) {
@@ -964,8 +1006,8 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
       const std::vector<int32_t>& loc = mode == 0 ? src_local : rec_local;
       std::vector<int32_t> pb, pn, pid;
       for (size_t i = 0; i < sub.size(); ++i)
-        if (sub[i] >= s0 && sub[i] < s0 + nb) {
-          pb.push_back(sub[i] - s0);
+        if (batch_of[sub[i]] == bidx) {
+          pb.push_back(pos_of[sub[i]]);
           pn.push_back(loc[i]);
           pid.push_back((int32_t)i);
         }
@@ -988,7 +1030,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
         hipLaunchKernelGGL(project_field_kernel, dim3((nb * kp + 255) / 256), dim3(256), 0, st, g, Z, Sd, N, kp, nb,
                            fields[fi], t.ncell[0], t.ncell[1], org_d, ybuf);
         B_TRY_HIP(hipGetLastError());
-        B_LAUNCH(apply_g_kernel, (int64_t)nb * kp, ybuf, G, sk, k, p, P16, nb, s0, outs[fi]);
+        B_LAUNCH(apply_g_kernel, (int64_t)nb * kp, ybuf, G, sk, k, p, P16, nb, ids_d, outs[fi]);
       }
     }
     // breakdown flags of this batch
@@ -997,13 +1039,14 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
     B_TRY_HIP(hipStreamSynchronize(st));
     if (verbose) {
       const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-      std::fprintf(stderr, "[sfm] ROM build: subdomains %d..%d of %d done, %.2f s\n", s0, s0 + nb - 1, S, el);
+      std::fprintf(stderr, "[sfm] ROM build: batch %d (%d subdomains of %dx%dx%d cells) of %d subdomains done, %.2f s\n",
+                   bidx, nb, w[0], w[1], w[2], S, el);
       std::fflush(stderr);
     }
     if (fl[nbmax]) status = c->fail(SFM_EINVAL, "sound speed must be positive and finite at every node");
     for (int b = 0; b < nb && status == SFM_OK; ++b)
       if (fl[b])
-        status = c->fail(SFM_EBREAKDOWN, "subdomain " + std::to_string(s0 + b) +
+        status = c->fail(SFM_EBREAKDOWN, "subdomain " + std::to_string(ids[b]) +
                                              ": block Lanczos breakdown or non-SPD Gamma_j");
   }
   if (status != SFM_OK) {

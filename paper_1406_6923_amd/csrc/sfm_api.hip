@@ -118,9 +118,10 @@ sfm_status locate_points(sfm_ctx c, int32_t nsrc, const int32_t* src_ijk, int32_
   if (nsrc < 0 || nrec < 0) return c->fail(SFM_EINVAL, "negative source or receiver count");
   if ((nsrc > 0 && !src_ijk) || (nrec > 0 && !rec_ijk)) return c->fail(SFM_EINVAL, "missing node array");
   auto local = [&](int s, const int32_t* g) {
-    int o[3];
+    int o[3], w[3];
     t.origin(s, o);
-    return ((g[2] - o[2]) * t.nodes_local[1] + (g[1] - o[1])) * t.nodes_local[0] + (g[0] - o[0]);
+    t.cells(s, w);
+    return ((g[2] - o[2]) * (w[1] + 1) + (g[1] - o[1])) * (w[0] + 1) + (g[0] - o[0]);
   };
   src_sub.resize(nsrc);
   src_local.resize(nsrc);
@@ -296,7 +297,9 @@ using namespace sfm;
 // ----------------------------------------------------------------------------- ABI
 extern "C" {
 
-sfm_status sfm_create(const sfm_config* cfg, sfm_ctx* out) {
+sfm_status sfm_create(const sfm_config* cfg, sfm_ctx* out) { return sfm_create_boxes(cfg, nullptr, nullptr, out); }
+
+sfm_status sfm_create_boxes(const sfm_config* cfg, const int32_t* nbox, const int32_t* box_cells, sfm_ctx* out) {
   if (!out) {
     g_create_error = "out is NULL";
     return SFM_EINVAL;
@@ -307,7 +310,7 @@ sfm_status sfm_create(const sfm_config* cfg, sfm_ctx* out) {
     return SFM_EINVAL;
   }
   Topology topo;
-  const std::string msg = topo.init(*cfg);
+  const std::string msg = topo.init(*cfg, nbox, box_cells);
   if (!msg.empty()) {
     g_create_error = msg;
     return SFM_EINVAL;

@@ -62,19 +62,23 @@ struct TileGeometry {
   void word_map(std::vector<int32_t>& rows, std::vector<int32_t>& cols, int elem_bytes) const;
 };
 
-// Decomposition of the global box into equal subdomains and their faces.
+// Decomposition of the global box into a tensor product of boxes and their faces.
 struct Topology {
-  int ncell[3] = {}, sub[3] = {}, nsub[3] = {};
+  int ncell[3] = {}, nsub[3] = {};
+  std::vector<int32_t> cut[3];           // per axis: box planes 0 = x_0 < ... < x_nsub = ncell
   int S = 0, m = 0, m1 = 0, m2 = 0, p = 0, k = 0;
-  int nodes_local[3] = {};               // sub + 1
-  int64_t N_local = 0;                   // nodes per subdomain
+  int64_t N_max = 0;                     // nodes of the largest subdomain
   std::vector<int32_t> nbr;              // [S][6], -1 = outer face
 
-  std::string init(const sfm_config& cfg);   // returns "" or an error message
+  // box_cells: per axis the cell counts of its boxes (nbox[d] of them), or null for equal boxes
+  // of cfg.sub_cells cells.  Returns "" or an error message.
+  std::string init(const sfm_config& cfg, const int32_t* nbox = nullptr, const int32_t* box_cells = nullptr);
   int index(int bx, int by, int bz) const { return (bz * nsub[1] + by) * nsub[0] + bx; }
+  void box_of(int s, int b[3]) const;
   // Subdomain holding global node (i, j, l): strictly inside if strict, else lowest index.
   int owner(int i, int j, int l, bool strict) const;
   void origin(int s, int o[3]) const;
+  void cells(int s, int c[3]) const;     // cells per edge of subdomain s
 };
 
 struct StepParams {

@@ -1,8 +1,9 @@
 // Host-side geometry: subdomain decomposition, faces, and the tile layout of the
 // coefficient stream.
 //
-// Decomposition (Introduction; Stage 1 section): the box of ncell cells is split into
-// nsub = ncell / sub_cells equal box subdomains that share their interface nodes.
+// Decomposition (Introduction; Stage 1 section): the box of ncell cells is split into a
+// tensor product of box subdomains (per axis, equal boxes of sub_cells cells or a list of box
+// sizes) that share their interface nodes; neighbours across a face share the whole face.
 // Faces are ordered x-, x+, y-, y+, z-, z+; face f of subdomain s is an interface
 // when a neighbour box exists (nbr >= 0) and outer otherwise.  Boundary entry
 // q = f * m + patch of the boundary layer U_1 is shared with entry (f ^ 1) * m + patch
@@ -85,16 +86,32 @@ static std::string fmt(const char* f, long a = 0, long b = 0, long c = 0) {
   return buf;
 }
 
-std::string Topology::init(const sfm_config& cfg) {
+std::string Topology::init(const sfm_config& cfg, const int32_t* nbox, const int32_t* box_cells) {
+  if ((nbox == nullptr) != (box_cells == nullptr)) return "nbox and box_cells go together";
+  int64_t used = 0;
   for (int d = 0; d < 3; ++d) {
     if (cfg.ncell[d] < 1) return fmt("ncell[%ld] = %ld must be positive", d, cfg.ncell[d]);
-    if (cfg.sub_cells[d] < 2) return fmt("sub_cells[%ld] = %ld must be at least 2", d, cfg.sub_cells[d]);
-    if (cfg.ncell[d] % cfg.sub_cells[d] != 0)
-      return fmt("ncell[%ld] = %ld is not a multiple of sub_cells = %ld", d, cfg.ncell[d], cfg.sub_cells[d]);
     ncell[d] = cfg.ncell[d];
-    sub[d] = cfg.sub_cells[d];
-    nsub[d] = ncell[d] / sub[d];
-    nodes_local[d] = sub[d] + 1;
+    cut[d].assign(1, 0);
+    if (!box_cells) {
+      if (cfg.sub_cells[d] < 2) return fmt("sub_cells[%ld] = %ld must be at least 2", d, cfg.sub_cells[d]);
+      if (cfg.ncell[d] % cfg.sub_cells[d] != 0)
+        return fmt("ncell[%ld] = %ld is not a multiple of sub_cells = %ld", d, cfg.ncell[d], cfg.sub_cells[d]);
+      for (int b = 0; b < cfg.ncell[d] / cfg.sub_cells[d]; ++b) cut[d].push_back(cut[d].back() + cfg.sub_cells[d]);
+    } else {
+      if (nbox[d] < 1 || nbox[d] > cfg.ncell[d]) return fmt("nbox[%ld] = %ld out of range", d, nbox[d]);
+      for (int b = 0; b < nbox[d]; ++b) {
+        const int32_t w = box_cells[used + b];
+        if (w < 2) return fmt("box %ld along axis %ld has %ld cells; at least 2 are needed", b, d, w);
+        if ((int64_t)cut[d].back() + w > cfg.ncell[d])
+          return fmt("box sizes along axis %ld add up to more than ncell = %ld", d, cfg.ncell[d]);
+        cut[d].push_back(cut[d].back() + w);
+      }
+      if (cut[d].back() != cfg.ncell[d])
+        return fmt("box sizes along axis %ld add up to %ld, not ncell = %ld", d, cut[d].back(), cfg.ncell[d]);
+      used += nbox[d];
+    }
+    nsub[d] = (int)cut[d].size() - 1;
   }
   if (!(cfg.h > 0.0)) return "h must be positive";
   if (cfg.m < 1) return "m must be at least 1";
@@ -111,12 +128,22 @@ std::string Topology::init(const sfm_config& cfg) {
   m2 = 1;
   for (int d = 1; d * d <= m; ++d)
     if (m % d == 0) { m2 = d; m1 = m / d; }
-  const int smin = std::min(sub[0], std::min(sub[1], sub[2]));
+  int wmin[3], wmax[3];
+  for (int d = 0; d < 3; ++d) {
+    wmin[d] = ncell[d];
+    wmax[d] = 0;
+    for (int b = 0; b < nsub[d]; ++b) {
+      wmin[d] = std::min(wmin[d], cut[d][b + 1] - cut[d][b]);
+      wmax[d] = std::max(wmax[d], cut[d][b + 1] - cut[d][b]);
+    }
+  }
+  const int smin = std::min(wmin[0], std::min(wmin[1], wmin[2]));
   if (m1 >= smin)
     return fmt("patch count %ld along a face edge needs more than %ld cells per subdomain edge", m1, m1);
-  N_local = (int64_t)nodes_local[0] * nodes_local[1] * nodes_local[2];
-  if ((int64_t)p * k > N_local)
-    return fmt("ROM size 6mk = %ld exceeds the %ld nodes of a subdomain", (long)p * k, (long)N_local);
+  const int64_t nmin = (int64_t)(wmin[0] + 1) * (wmin[1] + 1) * (wmin[2] + 1);
+  N_max = (int64_t)(wmax[0] + 1) * (wmax[1] + 1) * (wmax[2] + 1);
+  if ((int64_t)p * k > nmin)
+    return fmt("ROM size 6mk = %ld exceeds the %ld nodes of the smallest subdomain", (long)p * k, (long)nmin);
   const int64_t S64 = (int64_t)nsub[0] * nsub[1] * nsub[2];
   if (S64 > (1 << 24)) return "too many subdomains";
   S = (int)S64;
@@ -136,29 +163,41 @@ std::string Topology::init(const sfm_config& cfg) {
   return "";
 }
 
+void Topology::box_of(int s, int b[3]) const {
+  b[0] = s % nsub[0];
+  b[1] = (s / nsub[0]) % nsub[1];
+  b[2] = s / (nsub[0] * nsub[1]);
+}
+
 int Topology::owner(int i, int j, int l, bool strict) const {
   const int g[3] = {i, j, l};
   int b[3];
   for (int d = 0; d < 3; ++d) {
     if (g[d] < 0 || g[d] > ncell[d]) return -1;
-    const int q = g[d] / sub[d], r = g[d] % sub[d];
+    // q: the box with cut[q] <= g < cut[q + 1] (the last box for g = ncell)
+    int q = (int)(std::upper_bound(cut[d].begin(), cut[d].end(), g[d]) - cut[d].begin()) - 1;
+    q = std::min(q, nsub[d] - 1);
+    const bool on_plane = g[d] == cut[d][q] || g[d] == cut[d][q + 1];
     if (strict) {
-      if (r == 0) return -1;   // on a subdomain plane (interface or outer boundary)
+      if (on_plane) return -1;   // on a subdomain plane (interface or outer boundary)
       b[d] = q;
     } else {
-      b[d] = (r == 0 && q > 0) ? q - 1 : q;   // lowest box holding the node
+      b[d] = (g[d] == cut[d][q] && q > 0) ? q - 1 : q;   // lowest box holding the node
     }
   }
   return index(b[0], b[1], b[2]);
 }
 
 void Topology::origin(int s, int o[3]) const {
-  const int bx = s % nsub[0];
-  const int by = (s / nsub[0]) % nsub[1];
-  const int bz = s / (nsub[0] * nsub[1]);
-  o[0] = bx * sub[0];
-  o[1] = by * sub[1];
-  o[2] = bz * sub[2];
+  int b[3];
+  box_of(s, b);
+  for (int d = 0; d < 3; ++d) o[d] = cut[d][b[d]];
+}
+
+void Topology::cells(int s, int c[3]) const {
+  int b[3];
+  box_of(s, b);
+  for (int d = 0; d < 3; ++d) c[d] = cut[d][b[d] + 1] - cut[d][b[d]];
 }
 
 }  // namespace sfm

@@ -63,6 +63,7 @@ _D = ctypes.c_double
 # name -> (restype, argtypes); mirrors include/sfm.h
 SIGNATURES = {
     "sfm_create": (_I32, [ctypes.POINTER(sfm_config), ctypes.POINTER(_VP)]),
+    "sfm_create_boxes": (_I32, [ctypes.POINTER(sfm_config), _VP, _VP, ctypes.POINTER(_VP)]),
     "sfm_destroy": (None, [_VP]),
     "sfm_last_error": (ctypes.c_char_p, [_VP]),
     "sfm_query": (_I32, [_VP, ctypes.POINTER(sfm_info)]),
@@ -148,11 +149,21 @@ def _check(ctx, status: int):
 # ------------------------------------------------------------------ entry points
 def sfm_create(ncell, sub_cells, h: float, m: int, k: int, precision: int = SFM_PREC_FP32,
                build_batch: int = 0) -> int:
+    """sub_cells: per axis one box size (equal boxes) or the list of box sizes (uneven boxes)."""
     lib = load_library()
-    cfg = sfm_config((ctypes.c_int32 * 3)(*ncell), (ctypes.c_int32 * 3)(*sub_cells), float(h), int(m), int(k),
+    uneven = any(np.ndim(sc) > 0 for sc in sub_cells)
+    even = [0, 0, 0] if uneven else [int(sc) for sc in sub_cells]
+    cfg = sfm_config((ctypes.c_int32 * 3)(*ncell), (ctypes.c_int32 * 3)(*even), float(h), int(m), int(k),
                      int(precision), int(build_batch))
     out = _VP()
-    status = lib.sfm_create(ctypes.byref(cfg), ctypes.byref(out))
+    if uneven:
+        lists = [[int(sc)] * (int(n) // int(sc)) if np.ndim(sc) == 0 else [int(x) for x in sc]
+                 for n, sc in zip(ncell, sub_cells)]
+        nbox = np.array([len(x) for x in lists], dtype=np.int32)
+        cells = np.array(sum(lists, []), dtype=np.int32)
+        status = lib.sfm_create_boxes(ctypes.byref(cfg), _ptr(nbox), _ptr(cells), ctypes.byref(out))
+    else:
+        status = lib.sfm_create(ctypes.byref(cfg), ctypes.byref(out))
     _check(None, status)
     return out.value
 

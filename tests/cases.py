@@ -19,6 +19,11 @@ def case_config(name: str) -> W.Workload:
         cfg = W.Workload(name="ragged_p18", ncell=(30, 20, 24), sub_cells=(10, 10, 12), h=10.0, m=3, k=5,
                          f_peak=15.0, nsteps=300, src=((14, 7, 5),), rec_grid=(10, 8),
                          velocity="layered_inclusions", seed=5)
+    elif name == "uneven":
+        # a tensor product of boxes of uneven size: 2 x 2 x 2 boxes from (12, 16) x (8, 12) x (10, 8)
+        cfg = W.Workload(name="uneven_28x20x18", ncell=(28, 20, 18), sub_cells=((12, 16), (8, 12), (10, 8)),
+                         h=10.0, m=4, k=5, f_peak=15.0, nsteps=300, src=((3, 11, 4),), rec_grid=(10, 8),
+                         velocity="layered_inclusions", seed=9)
     elif name == "mid":
         # The large workload's subdomain size and ROM sizes (33^3 nodes, m = 16, k = 16) on 2 x 2 x 1.
         cfg = W.scaled_large((2, 2, 1), nsteps=150)

@@ -49,6 +49,11 @@ def test_struct_layouts_match_header():
     (dict(m=4, k=300), "exceeds"),
     # FP64 blocks of p = 96 at k = 40 need 169 KB of LDS per work-group
     (dict(m=16, k=40, precision=2), "LDS"),
+    # uneven boxes: sizes must add up to ncell, each box at least 2 cells, ROM fits the smallest box
+    (dict(sub_cells=((12, 16), 16, 16)), "add up to 28"),
+    (dict(sub_cells=((16, 20), 16, 16)), "more than ncell"),
+    (dict(sub_cells=((30, 1, 1), 16, 16)), "at least 2"),
+    (dict(sub_cells=(16, (29, 3), 16), k=100), "smallest subdomain"),
 ])
 def test_create_rejects_bad_config_without_gpu(kwargs, fragment):
     args = dict(ncell=(32, 32, 32), sub_cells=(16, 16, 16), h=10.0, m=4, k=8, precision=0)
