@@ -313,6 +313,17 @@ sfm_status sfm_shots_init(sfm_ctx ctx, int32_t nshot, const int32_t* shot_src, v
 sfm_status sfm_shots_step(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet_dev, float* traces_dev,
                           int64_t ld, void* stream);
 
+/* hipGraph replay of the shot step loop.  With enable = 1 (the default) sfm_shots_step captures
+ * one window of 32 steps (main, boundary and receiver kernels of each step, the window's trace
+ * flush and a step-counter increment) into a graph once per (wavelet_dev, traces_dev, ld, dt,
+ * level table, ROMs) and replays it floor(nsteps / 32) times (calls of fewer than 64 steps, and
+ * calls with per-kernel timing on, launch every kernel); the kernels of a replay add a device
+ * step counter to their relative step, and the remaining steps are launched directly.  Results
+ * are bit-identical to enable = 0.  enable < 0 only queries.  *replays (may be NULL): windows
+ * replayed so far.  Capture runs on a stream of the context's own (default priority); replays
+ * go to the caller's stream. */
+sfm_status sfm_shots_graph(sfm_ctx ctx, int32_t enable, int64_t* replays);
+
 /* Copy the shot state U^n and D = U^n - U^{n-1} to / from host arrays float [S][k][p][nshot].
  * Synchronize.  Errors: SFM_ESTATE, SFM_EINVAL. */
 sfm_status sfm_shots_get_state(sfm_ctx ctx, float* u_host, float* d_host);

@@ -375,6 +375,8 @@ void sfm_destroy(sfm_ctx c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  sfm::drop_shot_graph(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   destroy_blas(c);
   c->dfree_all();
   (void)hipSetDevice(cur);
@@ -840,6 +842,7 @@ sfm_status sfm_set_levels(sfm_ctx c, const int32_t* k_per_sub) {
   }
   SFM_TRY_HIP(c, hipSetDevice(c->device));
   SFM_TRY_HIP(c, hipDeviceSynchronize());
+  sfm::drop_shot_graph(c);
   c->dfree(c->k_of_d);
   c->k_of_d = nullptr;
   c->k_of = ks;

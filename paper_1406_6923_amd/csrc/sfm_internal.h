@@ -178,6 +178,7 @@ sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vec
                          hipStream_t st);
 void release_roms(sfm_ctx c);
 void release_shots(sfm_ctx c);
+void drop_shot_graph(sfm_ctx c);   // destroys the cached shot-window graph (synchronizes)
 // Zero the levels j >= k_of[s] of a [S][k][P16][cols] state (no-op without a level table).
 hipError_t clear_extra_levels(sfm_ctx c, float* X, int cols, hipStream_t st);
 sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, hipStream_t st);
@@ -242,6 +243,13 @@ struct sfm_ctx_s {
   double shots_ms[3] = {0, 0, 0};   // main, face, record
   int shots_variant = 0;            // main-kernel variant chosen by the autotuner
   double shots_tune_ms[4] = {0, 0, 0, 0};
+  // hipGraph of one receiver window of shot steps (replayed by sfm_shots_step)
+  bool shots_graph = true;
+  int64_t* shot_base_d = nullptr;   // device step counter read by the replayed kernels
+  hipStream_t cap_stream = nullptr; // capture stream (the caller's may be the null stream)
+  hipGraphExec_t shot_exec = nullptr;
+  std::vector<uint64_t> shot_exec_key;
+  int64_t shots_replays = 0;
   // scratch
   double* red_d = nullptr;          // reduction scratch
   float* work_a_d = nullptr;        // [S][k][P16] operator scratch

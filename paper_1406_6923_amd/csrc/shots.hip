@@ -50,7 +50,8 @@ struct ShotParams {
   const int32_t* src_ids;
   const int32_t* src_shot;     // [nsrc] shot driven by each source (-1: none)
   const float* src_vec;        // [nsrc][k][P]
-  const float* wavelet;        // [nsteps][nshot] (row `step`)
+  const float* wavelet;        // [nsteps][nshot] (row `step`, plus *step_base when set)
+  const int64_t* step_base;    // device step counter of a replayed window (or null)
   int nshot;
   int64_t step;
   float dt2;
@@ -189,7 +190,8 @@ __global__ __launch_bounds__(128 * (kMaxShotP16 / kTile), kMinWaves) void shots_
         const int src = prm.src_ids[q];
         const int n = prm.src_shot[src];
         if (n < 0 || (n & 15) != li || (n >> 4) < sh || (n >> 4) > sh + 1) continue;
-        const float wv = prm.wavelet[prm.step * prm.nshot + n];
+        const int64_t stp = prm.step + (prm.step_base ? *prm.step_base : 0);
+        const float wv = prm.wavelet[stp * prm.nshot + n];
         const float* sv = prm.src_vec + ((size_t)src * k + j) * P + row0;
         const int h = (n >> 4) - sh;
 #pragma unroll
@@ -226,6 +228,7 @@ struct ShotFaceParams {
   const float* sw_w;
   const int32_t* src_shot;
   const float* wavelet;
+  const int64_t* step_base;    // as in ShotParams
   int nshot;
   int64_t step;
   float dt2;
@@ -249,11 +252,12 @@ __global__ void shots_face_kernel(ShotFaceParams prm) {
   if (nb >= 0) flux += *reinterpret_cast<const f4*>(prm.exch + ((size_t)nb * prm.P + (f ^ 1) * prm.m + pat) * kShotCols + n0);
   f4 a = prm.C[(size_t)s * prm.P + q] * flux;
   if (prm.sw_off) {
+    const int64_t stp = prm.step + (prm.step_base ? *prm.step_base : 0);
     for (int e = prm.sw_off[s]; e < prm.sw_off[s + 1]; ++e) {
       if (prm.sw_q[e] != q) continue;
       const int n = prm.src_shot[prm.sw_src[e]];
       if (n < n0 || n >= n0 + 4) continue;
-      a[n - n0] = fmaf(prm.sw_w[e], prm.wavelet[prm.step * prm.nshot + n], a[n - n0]);
+      a[n - n0] = fmaf(prm.sw_w[e], prm.wavelet[stp * prm.nshot + n], a[n - n0]);
     }
   }
   const size_t u = ((size_t)s * prm.k * prm.P + q) * kShotCols + n0;
@@ -276,7 +280,8 @@ struct ShotRecParams {
   int k, P, nrec, nshot;
   int64_t ld;
   int slot;                    // time slot of this step in the window
-  int64_t col0;                // flush: trace column of slot 0
+  int64_t col0;                // flush: trace column of slot 0 (plus *step_base when set)
+  const int64_t* step_base;
   int w;                       // flush: filled slots
 };
 
@@ -358,10 +363,16 @@ __global__ __launch_bounds__(256) void shots_flush_kernel(ShotRecParams prm) {
   }
   __syncthreads();
   const size_t orow = (size_t)prm.perm[r];
+  const int64_t col0 = prm.col0 + (prm.step_base ? *prm.step_base : 0);
   for (int e = threadIdx.x; e < prm.w * prm.nshot; e += 256) {
     const int n = e / prm.w, t = e - n * prm.w;
-    prm.out[((size_t)n * prm.nrec + orow) * prm.ld + prm.col0 + t] = tile[t][n];
+    prm.out[((size_t)n * prm.nrec + orow) * prm.ld + col0 + t] = tile[t][n];
   }
+}
+
+// The replayed window's last node: advance the step counter (one thread, a vector store).
+__global__ void step_base_kernel(int64_t* base, int64_t add, int set) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) base[0] = set ? add : base[0] + add;
 }
 
 typedef void (*ShotKernel)(ShotParams);
@@ -378,11 +389,22 @@ size_t shots_lds_bytes(int P) {
 
 }  // namespace
 
+void drop_shot_graph(sfm_ctx c) {
+  if (c->shot_exec) {
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(c->shot_exec);
+  }
+  c->shot_exec = nullptr;
+  c->shot_exec_key.clear();
+}
+
 void release_shots(sfm_ctx c) {
-  void* bufs[] = {c->Us_d, c->Ds_d, c->exch_s_d, c->src_shot_d, c->rec_stage_d};
+  drop_shot_graph(c);
+  void* bufs[] = {c->Us_d, c->Ds_d, c->exch_s_d, c->src_shot_d, c->rec_stage_d, c->shot_base_d};
   for (void* b : bufs) c->dfree(b);
   c->Us_d = c->Ds_d = c->exch_s_d = c->rec_stage_d = nullptr;
   c->src_shot_d = nullptr;
+  c->shot_base_d = nullptr;
   c->nshot = 0;
   c->shots_n = 0;
 }
@@ -433,6 +455,7 @@ sfm_status sfm_shots_init(sfm_ctx c, int32_t nshot, const int32_t* shot_src, voi
   c->Ds_d = static_cast<float*>(c->dalloc(nstate * sizeof(float), &e));
   c->exch_s_d = static_cast<float*>(c->dalloc((size_t)t.S * c->geo.P16 * kShotCols * sizeof(float), &e));
   c->src_shot_d = static_cast<int32_t*>(c->dalloc(src_shot.size() * sizeof(int32_t), &e));
+  c->shot_base_d = static_cast<int64_t*>(c->dalloc(sizeof(int64_t), &e));
   if (c->nrec > 0)
     c->rec_stage_d = static_cast<float*>(c->dalloc((size_t)kShotWindow * c->nrec * kShotCols * sizeof(float), &e));
   if (e != hipSuccess) {
@@ -481,10 +504,10 @@ ShotParams main_params(sfm_ctx c, const float* wavelet_dev, double dt) {
   return prm;
 }
 
-hipError_t launch_shots_main(int variant, const ShotParams& prm, int nt, hipStream_t st) {
+hipError_t launch_shots_main(int variant, const ShotParams& prm, int nt, hipStream_t st, bool set_attr = true) {
   const size_t lds = shots_lds_bytes(prm.P);
   const ShotKernel kern = kShotVariants[variant];
-  if (lds > kDefaultLdsBytes) {
+  if (lds > kDefaultLdsBytes && set_attr) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -575,17 +598,86 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
   const int64_t nface = (int64_t)t.S * t.p * (kShotCols / 4);
   const bool record = traces_dev && c->nrec > 0;
   const dim3 rgrid((c->rs_max + 63) / 64, c->n_rs);
-  hipEvent_t ev[4] = {};
-  const bool timing = c->timing;
-  for (int n = 0; n < nsteps; ++n) {
+  // one step at relative index n (absolute with base == null); closes the window with a flush
+  auto launch_step = [&](int n, int64_t col0, bool close, const int64_t* base, hipStream_t s,
+                         bool set_attr) -> hipError_t {
     prm.step = n;
+    prm.step_base = base;
     fp.step = n;
+    fp.step_base = base;
+    hipError_t e = launch_shots_main(c->shots_variant, prm, g.nt, s, set_attr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(shots_face_kernel, dim3((unsigned)((nface + 255) / 256)), dim3(256), 0, s, fp);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (record) {
+      rp.slot = n % kShotWindow;
+      hipLaunchKernelGGL(shots_record_kernel, rgrid, dim3(256), 0, s, rp);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if (close) {
+        rp.w = rp.slot + 1;
+        rp.col0 = col0;
+        rp.step_base = base;
+        hipLaunchKernelGGL(shots_flush_kernel, dim3(c->nrec), dim3(256), 0, s, rp);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+    }
+    return hipSuccess;
+  };
+  const bool timing = c->timing;
+  const int nwin = nsteps / kShotWindow;
+  int n_done = 0;
+  if (c->shots_graph && !timing && nwin >= 2) {
+    // Capture one window of kShotWindow steps (relative steps 0..W-1, flush at the end, counter
+    // += W) and replay it nwin times; the kernels add the device counter to their step.
+    const uint64_t dtb = (uint64_t)__builtin_bit_cast(uint32_t, prm.dt2);
+    const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)wavelet_dev, (uint64_t)(uintptr_t)traces_dev,
+                                       (uint64_t)ld, dtb, (uint64_t)c->shots_variant,
+                                       (uint64_t)(uintptr_t)c->k_of_d, (uint64_t)(uintptr_t)c->Us_d,
+                                       (uint64_t)(uintptr_t)c->tiles_d};
+    if (c->shot_exec && key != c->shot_exec_key) drop_shot_graph(c);
+    if (!c->shot_exec) {
+      if (!c->cap_stream) SH_TRY_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      SH_TRY_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t e = hipSuccess;
+      for (int q = 0; q < kShotWindow && e == hipSuccess; ++q)
+        e = launch_step(q, 0, q == kShotWindow - 1, c->shot_base_d, c->cap_stream, false);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(step_base_kernel, dim3(1), dim3(64), 0, c->cap_stream, c->shot_base_d,
+                           (int64_t)kShotWindow, 0);
+        e = hipGetLastError();
+      }
+      hipGraph_t graph = nullptr;
+      const hipError_t ee = hipStreamEndCapture(c->cap_stream, &graph);
+      if (e == hipSuccess) e = ee;
+      if (e == hipSuccess) e = hipGraphInstantiate(&c->shot_exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        c->shot_exec = nullptr;
+        return c->fail(SFM_EHIP, std::string("shot-window graph capture: ") + hipGetErrorString(e));
+      }
+      c->shot_exec_key = key;
+    }
+    hipLaunchKernelGGL(step_base_kernel, dim3(1), dim3(64), 0, st, c->shot_base_d, (int64_t)0, 1);
+    SH_TRY_HIP(hipGetLastError());
+    for (int r = 0; r < nwin; ++r) SH_TRY_HIP(hipGraphLaunch(c->shot_exec, st));
+    c->shots_replays += nwin;
+    // the rest of the steps eagerly, relative to the counter (now nwin W)
+    for (int n = 0; n < nsteps - nwin * kShotWindow; ++n)
+      SH_TRY_HIP(launch_step(n, 0, n + 1 == nsteps - nwin * kShotWindow, c->shot_base_d, st, true));
+    n_done = nsteps;
+  }
+  hipEvent_t ev[4] = {};
+  for (int n = n_done; n < nsteps; ++n) {
     if (timing) {
       for (auto& x : ev) SH_TRY_HIP(hipEventCreate(&x));
       SH_TRY_HIP(hipEventRecord(ev[0], st));
     }
+    prm.step = n;
+    prm.step_base = nullptr;
     SH_TRY_HIP(launch_shots_main(c->shots_variant, prm, g.nt, st));
     if (timing) SH_TRY_HIP(hipEventRecord(ev[1], st));
+    fp.step = n;
+    fp.step_base = nullptr;
     hipLaunchKernelGGL(shots_face_kernel, dim3((unsigned)((nface + 255) / 256)), dim3(256), 0, st, fp);
     SH_TRY_HIP(hipGetLastError());
     if (timing) SH_TRY_HIP(hipEventRecord(ev[2], st));
@@ -596,6 +688,7 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
       if (rp.slot == kShotWindow - 1 || n + 1 == nsteps) {
         rp.w = rp.slot + 1;
         rp.col0 = n - rp.slot;
+        rp.step_base = nullptr;
         hipLaunchKernelGGL(shots_flush_kernel, dim3(c->nrec), dim3(256), 0, st, rp);
         SH_TRY_HIP(hipGetLastError());
       }
@@ -611,6 +704,17 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
     }
   }
   c->shots_n += nsteps;
+  return SFM_OK;
+}
+
+sfm_status sfm_shots_graph(sfm_ctx c, int32_t enable, int64_t* replays) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (enable >= 0) {
+    c->shots_graph = enable != 0;
+    if (!c->shots_graph) drop_shot_graph(c);
+  }
+  if (replays) *replays = c->shots_replays;
   return SFM_OK;
 }
 

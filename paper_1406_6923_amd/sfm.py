@@ -74,6 +74,7 @@ SIGNATURES = {
     "sfm_adjoint_gradient": (_I32, [_VP, _I32, _D, _VP, _VP, _I64, _I32, _VP, _VP, _VP]),
     "sfm_shots_init": (_I32, [_VP, _I32, _VP, _VP]),
     "sfm_shots_step": (_I32, [_VP, _I32, _D, _VP, _VP, _I64, _VP]),
+    "sfm_shots_graph": (_I32, [_VP, _I32, ctypes.POINTER(_I64)]),
     "sfm_shots_get_state": (_I32, [_VP, _VP, _VP]),
     "sfm_shots_set_state": (_I32, [_VP, _VP, _VP]),
     "sfm_shots_timing": (_I32, [_VP, ctypes.POINTER(_I64), _VP]),
@@ -337,6 +338,13 @@ def sfm_set_state(ctx: int, u_now=None, u_incr=None, n: int = 0) -> None:
     u = _host(u_now, np.float32)
     d = _host(u_incr, np.float32)
     _check(ctx, load_library().sfm_set_state(ctx, _ptr(u), _ptr(d), int(n)))
+
+
+def sfm_shots_graph(ctx: int, enable: int = -1) -> int:
+    """Enable (1) / disable (0) graph replay of shot windows, or query (-1); returns the replays so far."""
+    n = _I64()
+    _check(ctx, load_library().sfm_shots_graph(ctx, int(enable), ctypes.byref(n)))
+    return n.value
 
 
 def sfm_set_levels(ctx: int, k_per_sub=None) -> None:

@@ -141,3 +141,45 @@ def test_shots_errors():
         sfm.sfm_shots_init(h.ctx, 1)
     assert ei.value.status == sfm.SFM_EINVAL
     h.close()
+
+
+def test_shots_graph_replay_is_bit_identical():
+    """Graph-replayed windows of 32 steps against every kernel launched directly: four calls of
+    100, 64, 96 and 40 steps (a fresh capture, a new trace buffer, a cached graph, a call too
+    short to replay), with state reads between them; traces and states bit-identical."""
+    from paper_1406_6923_amd import sfm
+    cfg, c, subs, roms, cs = oracle_case("small")
+    nrun = 8
+    srcs = _shot_sources(cfg, nrun)
+    cs_all = coupled.CoupledSystem(subs, roms, srcs, cfg.receivers())
+    _, _, src_vec, _ = rom_arrays(cs_all)
+    shot_src = np.full(NSHOT, -1)
+    shot_src[:nrun] = np.arange(nrun)
+    hs = []
+    for graph in (0, 1):
+        h = _load(cfg, cs, np.asarray(srcs), src_vec)
+        sfm.sfm_shots_init(h.ctx, NSHOT, shot_src)
+        sfm.sfm_shots_graph(h.ctx, graph)
+        hs.append(h)
+    dt = 0.9 * cs.cfl_dt()
+    wav = np.zeros((100, NSHOT))
+    for n in range(nrun):
+        wav[:, n] = W.ricker(cfg.f_peak * (0.8 + 0.05 * n), dt, 100)
+    wav_d = torch.tensor(wav, dtype=torch.float32, device="cuda")
+    nrec = len(cfg.receivers())
+    bufs = [[torch.full((NSHOT, nrec, 100), -1.0, device="cuda") for _ in range(2)] for _ in hs]
+    for call, (nsteps, b) in enumerate([(100, 0), (64, 1), (96, 1), (40, 0)]):
+        print(f"[case] shots graph replay: call {call}, {nsteps} steps", flush=True)
+        out = []
+        for h, bb in zip(hs, bufs):
+            sfm.sfm_shots_step(h.ctx, nsteps, dt, wav_d, bb[b], 100)
+            torch.cuda.synchronize()
+            out.append((bb[b][..., :nsteps].cpu().numpy(), sfm.sfm_shots_get_state(h.ctx, NSHOT)))
+        (t0, (u0, d0)), (t1, (u1, d1)) = out
+        assert np.array_equal(t0, t1), call
+        assert np.array_equal(u0, u1) and np.array_equal(d0, d1), call
+        assert np.abs(t0[:nrun]).max() > 0
+    assert sfm.sfm_shots_graph(hs[0].ctx) == 0
+    assert sfm.sfm_shots_graph(hs[1].ctx) == 3 + 2 + 3
+    for h in hs:
+        h.close()
