@@ -165,6 +165,7 @@ def finite_shift_probe(torch, sfm, dev, stream, n: int = 4, steps: int = 200, si
 
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def shot_sources(cfg: W.Workload, n: int, seed: int = 2024):
@@ -225,6 +226,101 @@ def shots_probe(torch, sfm, h, cfg, dev, stream, dt, ratio, nshot, first_src, wa
         f"{main_ms:.3f} ms = {achieved:.1f} TFLOP/s FP32 MFMA ({100 * achieved / FP32_MFMA_PEAK_TFLOPS:.1f}%), "
         f"{out['roofline']['hbm_gbs']:.0f} GB/s")
     del tr
+    return out
+
+
+def uneven_shots_probe(torch, sfm, dev, stream, nsteps: int, nshot: int = 64, compare_steps: int = 192):
+    """Many-shot workload: uneven boxes, a ROM size per subdomain, 64 shots, all receivers; the
+    step loop replayed from a hipGraph, then the same steps with every kernel launched directly."""
+    cfg = W.CFG_SHOTS
+    log(f"[bench] many-shot workload {cfg.name}: generating velocity {cfg.nodes}")
+    c = cfg.velocity_model()
+    c_max = float(c.max())
+    vel = torch.from_numpy(c.astype(np.float32)).to(dev)
+    del c
+    srcs = np.asarray(W.surface_shots(cfg, nshot))
+    rec = cfg.receivers()
+    # FP64 coefficient storage: at k = 24 and 32 the S-fraction blocks of the 48-cell boxes do not
+    # survive FP32 rounding (the rounded operator's spectral radius grows by up to 1e6)
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k, precision=sfm.SFM_PREC_FP64)
+    S = h.info()["n_subdomains"]
+    ks = W.level_choices(S, seed=W.SHOTS_LEVEL_SEED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sfm.sfm_build_roms(h.ctx, vel, srcs, rec, stream=stream)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    del vel
+    sfm.sfm_set_levels(h.ctx, ks)
+    dt = 0.9 * sfm.sfm_cfl_dt(h.ctx, 200, stream=stream)
+    ratio = dt / (0.9 * cfg.h / (math.sqrt(3.0) * c_max))
+    sfm.sfm_shots_init(h.ctx, nshot, np.arange(nshot), stream=stream)
+    chosen, variants = sfm.sfm_shots_tuning(h.ctx)
+    total = nsteps + 64
+    wav = torch.tensor(np.repeat(W.ricker(cfg.f_peak, dt, total)[:, None], nshot, axis=1), dtype=torch.float32,
+                       device=dev)
+    tr = torch.zeros((nshot, len(rec), nsteps), dtype=torch.float32, device=dev)
+    sfm.sfm_shots_step(h.ctx, 64, dt, wav[:64].contiguous(), None, stream=stream)       # warm-up, graph capture
+    torch.cuda.synchronize()
+    r0 = sfm.sfm_shots_graph(h.ctx)
+    t0 = time.perf_counter()
+    sfm.sfm_shots_step(h.ctx, nsteps, dt, wav[64:].contiguous(), tr, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    replays = sfm.sfm_shots_graph(h.ctx) - r0
+    finite = bool(torch.isfinite(tr).all().item())
+    del tr
+    # graph replay against direct launches on the same number of steps (6 windows)
+    tr2 = torch.zeros((nshot, len(rec), compare_steps), dtype=torch.float32, device=dev)
+    w2 = wav[:compare_steps].contiguous()
+    per = {}
+    for mode in (1, 0):
+        sfm.sfm_shots_graph(h.ctx, mode)
+        sfm.sfm_shots_step(h.ctx, compare_steps, dt, w2, tr2, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sfm.sfm_shots_step(h.ctx, compare_steps, dt, w2, tr2, stream=stream)
+        torch.cuda.synchronize()
+        per["graph" if mode else "direct"] = (time.perf_counter() - t0) / compare_steps * 1e3
+    sfm.sfm_shots_graph(h.ctx, 1)
+    # per-kernel device times (direct launches with events)
+    sfm.sfm_shots_timing(h.ctx)
+    sfm.sfm_set_timing(h.ctx, True)
+    sfm.sfm_shots_step(h.ctx, 32, dt, w2[:32].contiguous(), tr2, stream=stream)
+    torch.cuda.synchronize()
+    sfm.sfm_set_timing(h.ctx, False)
+    nt, ms = sfm.sfm_shots_timing(h.ctx)
+    del tr2
+    p = cfg.p
+    main_ms = ms[0] / max(nt, 1)
+    flops = float(sum(2.0 * (2 * int(k) - 1) * p * p * nshot for k in ks))
+    hbm = float(sum((2 * int(k) - 1) * p * (p + 1) // 2 * 4 + 4 * int(k) * p * nshot * 4 for k in ks))
+    achieved = flops / (main_ms * 1e-3) / 1e12
+    hbm = float(sum((2 * int(k) - 1) * p * (p + 1) // 2 * 8 + 4 * int(k) * p * nshot * 4 for k in ks))
+    box = [list(cfg.box_cells(d)) for d in range(3)]
+    out = {
+        "workload": cfg.name, "subdomains": S, "box_cells": box,
+        "box_shapes": len({(a, b, c_) for a in box[0] for b in box[1] for c_ in box[2]}),
+        "m": cfg.m, "k_built": cfg.k, "k_levels": sorted(set(int(x) for x in ks)), "k_mean": float(ks.mean()),
+        "nshot": nshot, "steps": nsteps, "receivers": len(rec), "dt_ratio": ratio,
+        "build_seconds": t_build, "builds_per_s": S / t_build,
+        "ms_per_step": wall / nsteps * 1e3, "graph_replays": replays,
+        "value": cfg.n_cells * nshot * nsteps * ratio / wall / 1e9, "unit": "Gcell-updates/s (all shots)",
+        "graph_ms_per_step": per["graph"], "direct_ms_per_step": per["direct"],
+        "main_kernel_ms": main_ms, "face_kernel_ms": ms[1] / max(nt, 1), "record_kernel_ms": ms[2] / max(nt, 1),
+        "coefficients": "fp64 (FP64 MFMA), states fp32",
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "kernel": "shots_main_kernel<double>",
+                     "flops_per_launch": flops, "algorithmic_bytes_per_launch": hbm,
+                     "hbm_gbs": hbm / (main_ms * 1e-3) / 1e9},
+        "traces_finite": finite,
+        "autotune": {"chosen_waves_per_simd": chosen,
+                     "variants": [{"waves_per_simd": w, "ms": m} for w, m in variants]},
+    }
+    log(f"[bench] many-shot workload: build {t_build:.1f} s ({S} subdomains), {out['ms_per_step']:.3f} ms/step "
+        f"over {nsteps} steps, {out['value']:.1f} Gcell-updates/s; graph {per['graph']:.3f} vs direct "
+        f"{per['direct']:.3f} ms/step; main kernel {main_ms:.3f} ms = {achieved:.1f} TFLOP/s")
+    h.close()
     return out
 
 
@@ -292,6 +388,8 @@ def main():
     ap.add_argument("--shots", type=int, default=64,
                     help="shots stepped together through the same ROMs after the single-shot run (0: skip)")
     ap.add_argument("--shot-steps", type=int, default=100)
+    ap.add_argument("--uneven-steps", type=int, default=1500,
+                    help="steps of the many-shot uneven-box workload (0: skip it)")
     ap.add_argument("--adjoint-steps", type=int, default=4000,
                     help="steps of the misfit-gradient probe on the 256^3 gradient workload (0: skip)")
     ap.add_argument("--no-finite-shift", action="store_true",
@@ -471,6 +569,8 @@ def main():
     if nshot:
         out["shots"] = shots_probe(torch, sfm, h, cfg, dev, stream, dt, ratio, nshot, n_main_src, 10,
                                    args.shot_steps, nrec, ms_per_step)
+    if args.uneven_steps:
+        out["many_shots_uneven"] = uneven_shots_probe(torch, sfm, dev, stream, args.uneven_steps)
     if not args.no_finite_shift:
         out["finite_shift"] = finite_shift_probe(torch, sfm, dev, stream)
     if args.adjoint_steps:

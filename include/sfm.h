@@ -294,9 +294,11 @@ sfm_status sfm_adjoint_gradient(sfm_ctx ctx, int32_t nsteps, double dt, const fl
 /* ---- many shots through the same ROMs (Stage 2 with a 64-column right-hand side) ----
  * The S-fraction blocks do not depend on the source, so up to 64 shots share one pass over
  * the coefficient stream per step: the block products of eq. "intrtstep" become (6m x 6m) x
- * (6m x 64) products on the FP32 matrix cores.  Shot n is driven by source shot_src[n] of the
- * last sfm_build_roms / sfm_load_roms (its own wavelet column) and recorded at every receiver.
- * Requires SFM_PREC_FP32 and 6m <= 112.  The single-shot state (sfm_step) is independent. */
+ * (6m x 64) products on the matrix cores: FP32 MFMA with SFM_PREC_FP32, FP64 MFMA with
+ * SFM_PREC_FP64 (for ROMs whose deep S-fraction levels do not survive FP32 rounding; the shot
+ * states stay FP32).  Shot n is driven by source shot_src[n] of the last sfm_build_roms /
+ * sfm_load_roms (its own wavelet column) and recorded at every receiver.  Requires FP32 or FP64
+ * coefficient storage and 6m <= 112.  The single-shot state (sfm_step) is independent. */
 
 /* Allocate and zero the shot state (U^0 = U^{-1} = 0) for nshot shots (1..64), then time every
  * compiled variant of the shot kernel on it (no sources, dt = 0: the state stays zero) and keep
@@ -331,7 +333,8 @@ sfm_status sfm_shots_set_state(sfm_ctx ctx, const float* u_host, const float* d_
 
 /* Autotuner result of the last sfm_shots_init: *chosen_waves = the register budget (minimum
  * waves per SIMD) of the chosen variant; ms (host, double [2 cap]) = {waves, ms per step} of
- * each variant (up to cap); *count = number of variants.  Errors: SFM_ESTATE. */
+ * each variant (up to cap; ms < 0 for a variant whose work-group limit is below this 6m, which
+ * is not run); *count = number of variants.  Errors: SFM_ESTATE. */
 sfm_status sfm_shots_tuning(sfm_ctx ctx, int32_t* chosen_waves, double* ms, int32_t cap, int32_t* count);
 
 /* Device times of the shot kernels summed over the steps run while sfm_set_timing was on:

@@ -3,7 +3,11 @@
 // coefficient stream serves every shot and the block products become small dense GEMMs
 //   phi_j = Gamma_j (U_{j+1} - U_j),   a_j = Gamma-hat_j (phi_j - phi_{j-1})    (eq. "intrtstep")
 // with a p x 64 right-hand side (one column per shot) instead of a matrix-vector product.
-// They run on the FP32 matrix cores (v_mfma_f32_16x16x4f32).
+// They run on the FP32 matrix cores (v_mfma_f32_16x16x4f32), or with FP64 coefficient storage on
+// the FP64 ones (v_mfma_f64_16x16x4f64, the same lane layout with doubles): the deep levels of a
+// large polynomial-Krylov S-fraction do not survive rounding to FP32 (the rounded operator's
+// spectral radius grows by orders of magnitude), so such ROMs are stepped with FP64 blocks and
+// FP64 products while the states stay FP32.
 //
 // State layout: U, D [S][k][P16][64] (shot fastest); exch [S][P16][64].
 //
@@ -23,6 +27,7 @@
 #include <chrono>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "sfm_internal.h"
@@ -31,14 +36,54 @@ namespace sfm {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Per coefficient type: the 16-byte load unit of the tile stream, 4-wide accumulator, MFMA.
+template <typename T>
+struct ShotMath;
+template <>
+struct ShotMath<float> {
+  typedef f4 Load;               // 4 words per 16-byte load
+  typedef f4 Acc;
+  static constexpr int kWords = 4;
+  static constexpr int kPrefetch = 2;   // 16-byte loads of the next block held per thread
+  __device__ __forceinline__ static Acc mfma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of output element v held by lane group g (column: the lane within its group of 16)
+  __device__ __forceinline__ static int out_row(int g, int v) { return 4 * g + v; }
+};
+template <>
+struct ShotMath<double> {
+  typedef d2 Load;               // 2 words per 16-byte load
+  typedef d4 Acc;
+  static constexpr int kWords = 2;
+  static constexpr int kPrefetch = 4;
+  __device__ __forceinline__ static Acc mfma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // the FP64 16x16x4 result interleaves the lane groups: element v of group g is row g + 4 v
+  __device__ __forceinline__ static int out_row(int g, int v) { return g + 4 * v; }
+};
+
+// Xt[col][rbase + out_row(g, v)] = x[v]: one 16-byte store where the four rows are consecutive.
+template <typename T>
+__device__ __forceinline__ void store_rows(T* __restrict__ dst, int g, const typename ShotMath<T>::Acc& x) {
+  if constexpr (std::is_same<T, float>::value) {
+    *reinterpret_cast<f4*>(dst + 4 * g) = x;
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[ShotMath<T>::out_row(g, v)] = x[v];
+  }
+}
 
 constexpr int kMaxShotP16 = 112;        // work-group size (2 P16 / 16 waves) and prefetch capacity
-constexpr int kPrefetchQuads = 2;       // 16-byte words of the next block held per thread
 constexpr int kShotRowsPerThread = 8;   // P16 rows x 64 shots over 2 P16 / 16 waves
 constexpr int kShotWindow = 32;         // receiver samples staged per shot before the flush
 
 struct ShotParams {
-  const float* tiles;          // packed FP32 tile stream [S][2k-1][words_per_block]
+  const void* tiles;           // packed tile stream [S][2k-1][words_per_block] (FP32 or FP64 words)
   int64_t words_per_sub, words_per_block;
   const uint32_t* wmap;        // [words_per_block]: (row << 16) | col of every stored word
   int S, k, P, PP;
@@ -61,33 +106,37 @@ __device__ __forceinline__ size_t block_word(const ShotParams& prm, int s, int b
   return (size_t)s * prm.words_per_sub + (size_t)b * prm.words_per_block;
 }
 
-__device__ __forceinline__ void prefetch_block(const float* __restrict__ blk, int nq, int tid, int nthr,
-                                               f4 (&buf)[kPrefetchQuads]) {
-  const f4* q = reinterpret_cast<const f4*>(blk);
+template <typename T>
+using ShotBuf = typename ShotMath<T>::Load[ShotMath<T>::kPrefetch];
+
+template <typename T>
+__device__ __forceinline__ void prefetch_block(const T* __restrict__ blk, int nq, int tid, int nthr, ShotBuf<T>& buf) {
+  typedef typename ShotMath<T>::Load L;
+  const L* q = reinterpret_cast<const L*>(blk);
 #pragma unroll
-  for (int i = 0; i < kPrefetchQuads; ++i) {
+  for (int i = 0; i < ShotMath<T>::kPrefetch; ++i) {
     const int qi = tid + i * nthr;
     if (qi < nq) buf[i] = __builtin_nontemporal_load(q + qi);
   }
 }
 
 // Dense symmetric copy of the block in LDS: word (r, c) goes to G[r][c] and G[c][r].
-__device__ __forceinline__ void expand_block(float* __restrict__ G, int PP, int P, const uint32_t* __restrict__ wmap,
-                                             int nq, int tid, int nthr, const f4 (&buf)[kPrefetchQuads]) {
-  const uint4* wm = reinterpret_cast<const uint4*>(wmap);
+template <typename T>
+__device__ __forceinline__ void expand_block(T* __restrict__ G, int PP, int P, const uint32_t* __restrict__ wmap,
+                                             int nq, int tid, int nthr, const ShotBuf<T>& buf) {
+  constexpr int kW = ShotMath<T>::kWords;
 #pragma unroll
-  for (int i = 0; i < kPrefetchQuads; ++i) {
+  for (int i = 0; i < ShotMath<T>::kPrefetch; ++i) {
     const int qi = tid + i * nthr;
     if (qi < nq) {
-      const uint4 m = wm[qi];
-      const uint32_t ms[4] = {m.x, m.y, m.z, m.w};
-      const float vs[4] = {buf[i].x, buf[i].y, buf[i].z, buf[i].w};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = (int)(ms[e] >> 16), c = (int)(ms[e] & 0xffff);
+      for (int e = 0; e < kW; ++e) {
+        const uint32_t m = wmap[(size_t)qi * kW + e];
+        const int r = (int)(m >> 16), c = (int)(m & 0xffff);
         if (r < P) {
-          G[r * PP + c] = vs[e];
-          G[c * PP + r] = vs[e];
+          const T v = buf[i][e];
+          G[r * PP + c] = v;
+          G[c * PP + r] = v;
         }
       }
     }
@@ -96,21 +145,24 @@ __device__ __forceinline__ void expand_block(float* __restrict__ G, int PP, int 
 
 // acc[h] (16 x 16, shots 16 (sh + h)..) = G[16 I .. 16 I + 15][:] * X[:][16 (sh + h) ..] for the
 // wave's two shot tiles, X held as Xt[shot][row].
-__device__ __forceinline__ void block_product(const float* __restrict__ G, const float* __restrict__ Xt, int PP,
-                                              int P, int I, int sh, int g, int li, f4 (&acc)[2]) {
+template <typename T>
+__device__ __forceinline__ void block_product(const T* __restrict__ G, const T* __restrict__ Xt, int PP, int P, int I,
+                                              int sh, int g, int li, typename ShotMath<T>::Acc (&acc)[2]) {
+  typedef typename ShotMath<T>::Acc A4;
+  typedef T V4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-  for (int h = 0; h < 2; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
-  const float* arow = G + (16 * I + li) * PP + 4 * g;
-  const float* brow = Xt + (16 * sh + li) * PP + 4 * g;
+  for (int h = 0; h < 2; ++h) acc[h] = A4{0, 0, 0, 0};
+  const T* arow = G + (16 * I + li) * PP + 4 * g;
+  const T* brow = Xt + (16 * sh + li) * PP + 4 * g;
   for (int kk = 0; kk < P; kk += 16) {
-    const f4 a = *reinterpret_cast<const f4*>(arow + kk);
+    const V4 a = *reinterpret_cast<const V4*>(arow + kk);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const f4 b = *reinterpret_cast<const f4*>(brow + 16 * h * PP + kk);
-      acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[h], 0, 0, 0);
-      acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[h], 0, 0, 0);
-      acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[h], 0, 0, 0);
-      acc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[h], 0, 0, 0);
+      const V4 b = *reinterpret_cast<const V4*>(brow + 16 * h * PP + kk);
+      acc[h] = ShotMath<T>::mfma(a.x, b.x, acc[h]);
+      acc[h] = ShotMath<T>::mfma(a.y, b.y, acc[h]);
+      acc[h] = ShotMath<T>::mfma(a.z, b.z, acc[h]);
+      acc[h] = ShotMath<T>::mfma(a.w, b.w, acc[h]);
     }
   }
 }
@@ -118,19 +170,21 @@ __device__ __forceinline__ void block_product(const float* __restrict__ G, const
 // kMinWaves: waves per SIMD the register allocation must allow (2: one work-group per CU, no
 // spills; 3: two work-groups per CU at 6m = 96, some registers spilled).  sfm_shots_init times
 // every instantiation and keeps the fastest.
-template <int kMinWaves>
-__global__ __launch_bounds__(128 * (kMaxShotP16 / kTile), kMinWaves) void shots_main_kernel(ShotParams prm) {
-  extern __shared__ __align__(16) float lds[];
+template <typename T, int kMinWaves, int kMaxNtWG = kMaxShotP16 / kTile>
+__global__ __launch_bounds__(128 * kMaxNtWG, kMinWaves) void shots_main_kernel(ShotParams prm) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  typedef typename ShotMath<T>::Acc A4;
   const int P = prm.P, PP = prm.PP, k = prm.k;
-  float* G = lds;                        // [P][PP]   dense block
-  float* Xt = G + P * PP;                // [64][PP]  block input, then a_j, transposed
+  T* G = reinterpret_cast<T*>(lds_raw);  // [P][PP]   dense block
+  T* Xt = G + P * PP;                    // [64][PP]  block input, then a_j, transposed
+  const T* tiles = static_cast<const T*>(prm.tiles);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index: uniform
   const int nw = nthr >> 6;              // = 2 P / 16: two waves per 16-row tile
   const int I = w >> 1, sh = 2 * (w & 1);   // row tile, first of the wave's two shot tiles
   const int lane = tid & 63, g = lane >> 4, li = lane & 15;
   const int s = blockIdx.x;
-  const int nq = (int)(prm.words_per_block / 4);
+  const int nq = (int)(prm.words_per_block / ShotMath<T>::kWords);
   const size_t sbase = (size_t)s * k * P * kShotCols;
   const int ns0 = prm.src_off ? prm.src_off[s] : 0;
   const int ns1 = prm.src_off ? prm.src_off[s + 1] : 0;
@@ -142,49 +196,50 @@ __global__ __launch_bounds__(128 * (kMaxShotP16 / kTile), kMinWaves) void shots_
   auto xrow = [&](int j, int i) { return ((j * P + i * nw) * kShotCols); };
   constexpr int R = kShotRowsPerThread;
   float Ua[R], Ub[R], Un[R], Dr[R];      // U_j, U_{j+1}, U_{j+2}, D_j
-  f4 phip[2];                            // phi_{j-1} in the MFMA output layout
-  f4 acc[2];
-  f4 buf[kPrefetchQuads];
-  prefetch_block(prm.tiles + block_word(prm, s, 0), nq, tid, nthr, buf);
+  A4 phip[2];                            // phi_{j-1} in the MFMA output layout
+  A4 acc[2];
+  ShotBuf<T> buf;
+  prefetch_block<T>(tiles + block_word(prm, s, 0), nq, tid, nthr, buf);
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     Ua[i] = Uw[xrow(0, i) + lane];
     Ub[i] = Uw[xrow(1, i) + lane];
   }
-  const int row0 = 16 * I + 4 * g;
+  const int rb = 16 * I;                 // first row of the wave's row tile
   for (int j = 0; j < ks; ++j) {
     __syncthreads();                                       // G, Xt free
-    expand_block(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma_j
+    expand_block<T>(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma_j
 #pragma unroll
-    for (int i = 0; i < R; ++i) Xt[lane * PP + w + i * nw] = Ub[i] - Ua[i];   // U_{j+1} - U_j
+    for (int i = 0; i < R; ++i) Xt[lane * PP + w + i * nw] = (T)Ub[i] - (T)Ua[i];   // U_{j+1} - U_j
     __syncthreads();
     if (j >= 1) {
-      prefetch_block(prm.tiles + block_word(prm, s, k + j - 1), nq, tid, nthr, buf);   // Gamma-hat_j
+      prefetch_block<T>(tiles + block_word(prm, s, k + j - 1), nq, tid, nthr, buf);   // Gamma-hat_j
 #pragma unroll
       for (int i = 0; i < R; ++i) Dr[i] = Dw[xrow(j, i) + lane];
     } else {
-      prefetch_block(prm.tiles + block_word(prm, s, 1), nq, tid, nthr, buf);           // Gamma_2
+      prefetch_block<T>(tiles + block_word(prm, s, 1), nq, tid, nthr, buf);           // Gamma_2
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) Un[i] = (j + 2 < ks) ? Uw[xrow(j + 2, i) + lane] : 0.f;
-    block_product(G, Xt, PP, P, I, sh, g, li, acc);        // phi_j
+    block_product<T>(G, Xt, PP, P, I, sh, g, li, acc);     // phi_j
     __syncthreads();                                       // every wave done with G, Xt
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int n = 16 * (sh + h) + li;
       if (j == 0) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) prm.exch[((size_t)s * P + row0 + v) * kShotCols + n] = acc[h][v];   // step 2.1
+        for (int v = 0; v < 4; ++v)
+          prm.exch[((size_t)s * P + rb + ShotMath<T>::out_row(g, v)) * kShotCols + n] = (float)acc[h][v];  // step 2.1
       } else {
-        *reinterpret_cast<f4*>(Xt + n * PP + row0) = acc[h] - phip[h];   // phi_j - phi_{j-1}
+        store_rows<T>(Xt + n * PP + rb, g, acc[h] - phip[h]);   // phi_j - phi_{j-1}
       }
       phip[h] = acc[h];
     }
     if (j >= 1) {
-      expand_block(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma-hat_j
+      expand_block<T>(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma-hat_j
       __syncthreads();
-      if (j + 1 < ks) prefetch_block(prm.tiles + block_word(prm, s, j + 1), nq, tid, nthr, buf);  // Gamma_{j+1}
-      block_product(G, Xt, PP, P, I, sh, g, li, acc);        // a_j
+      if (j + 1 < ks) prefetch_block<T>(tiles + block_word(prm, s, j + 1), nq, tid, nthr, buf);  // Gamma_{j+1}
+      block_product<T>(G, Xt, PP, P, I, sh, g, li, acc);     // a_j
       // sources of this subdomain: a_j += f_n(t) s_j for the shot n each source drives
       for (int q = ns0; q < ns1; ++q) {
         const int src = prm.src_ids[q];
@@ -192,19 +247,25 @@ __global__ __launch_bounds__(128 * (kMaxShotP16 / kTile), kMinWaves) void shots_
         if (n < 0 || (n & 15) != li || (n >> 4) < sh || (n >> 4) > sh + 1) continue;
         const int64_t stp = prm.step + (prm.step_base ? *prm.step_base : 0);
         const float wv = prm.wavelet[stp * prm.nshot + n];
-        const float* sv = prm.src_vec + ((size_t)src * k + j) * P + row0;
+        const float* sv = prm.src_vec + ((size_t)src * k + j) * P + rb;
         const int h = (n >> 4) - sh;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[h][v] = fmaf(wv, sv[v], acc[h][v]);
+        for (int v = 0; v < 4; ++v) {
+          const T x = (T)sv[ShotMath<T>::out_row(g, v)];
+          if constexpr (std::is_same<T, float>::value) acc[h][v] = fmaf(wv, x, acc[h][v]);
+          else acc[h][v] = fma((double)wv, x, acc[h][v]);
+        }
       }
       __syncthreads();                                     // every wave done reading Xt
 #pragma unroll
-      for (int h = 0; h < 2; ++h) *reinterpret_cast<f4*>(Xt + (16 * (sh + h) + li) * PP + row0) = acc[h];
+      for (int h = 0; h < 2; ++h) store_rows<T>(Xt + (16 * (sh + h) + li) * PP + rb, g, acc[h]);
       __syncthreads();
       // leapfrog in increment form: D_j += dt^2 a_j, U_j += D_j
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        const float d = fmaf(prm.dt2, Xt[lane * PP + w + i * nw], Dr[i]);
+        const float d = std::is_same<T, float>::value
+                            ? fmaf(prm.dt2, (float)Xt[lane * PP + w + i * nw], Dr[i])
+                            : (float)fma((double)prm.dt2, (double)Xt[lane * PP + w + i * nw], (double)Dr[i]);
         Dw[xrow(j, i) + lane] = d;
         Uw[xrow(j, i) + lane] = Ua[i] + d;
       }
@@ -376,16 +437,22 @@ __global__ void step_base_kernel(int64_t* base, int64_t add, int set) {
 }
 
 typedef void (*ShotKernel)(ShotParams);
-// 4 waves per SIMD: one 12-wave work-group per CU at 6m = 96 with no spills; 6: two work-groups
-// per CU with some registers spilled.
-constexpr ShotKernel kShotVariants[] = {shots_main_kernel<4>, shots_main_kernel<6>};
-constexpr int kShotVariantWaves[] = {4, 6};
+// FP32: 4 waves per SIMD, one 12-wave work-group per CU at 6m = 96 with no spills; 6: two
+// work-groups per CU with some registers spilled.  FP64 (twice the accumulator and prefetch
+// registers): for 6m <= 80 a work-group of at most 10 waves allows 3 waves per SIMD (170
+// registers, no spills); the 4-wave variant serves every 6m <= 112.
+constexpr ShotKernel kShotVariants[2][2] = {{shots_main_kernel<float, 4>, shots_main_kernel<float, 6>},
+                                            {shots_main_kernel<double, 3, 5>, shots_main_kernel<double, 4>}};
+constexpr int kShotVariantWaves[2][2] = {{4, 6}, {3, 4}};
+constexpr int kShotVariantMaxNt[2][2] = {{7, 7}, {5, 7}};   // largest P16 / 16 of each variant
 constexpr int kNumShotVariants = 2;
 
-size_t shots_lds_bytes(int P) {
+size_t shots_lds_bytes(int P, size_t elem) {
   const int PP = P + 4;
-  return sizeof(float) * ((size_t)P * PP + (size_t)kShotCols * PP);
+  return elem * ((size_t)P * PP + (size_t)kShotCols * PP);
 }
+
+int shot_kind(sfm_ctx c) { return c->cfg.precision == SFM_PREC_FP64 ? 1 : 0; }
 
 }  // namespace
 
@@ -429,11 +496,16 @@ sfm_status sfm_shots_init(sfm_ctx c, int32_t nshot, const int32_t* shot_src, voi
   if (!c) return SFM_EINVAL;
   c->err.clear();
   if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs: call sfm_build_roms or sfm_load_roms first");
-  if (c->cfg.precision != SFM_PREC_FP32) return c->fail(SFM_EINVAL, "shots need FP32 coefficient storage");
+  if (c->cfg.precision != SFM_PREC_FP32 && c->cfg.precision != SFM_PREC_FP64)
+    return c->fail(SFM_EINVAL, "shots need FP32 or FP64 coefficient storage");
   if (c->geo.P16 > kMaxShotP16)
     return c->fail(SFM_EINVAL, "shots support 6m <= " + std::to_string(kMaxShotP16) + " (LDS of one CU)");
-  if (c->geo.words_per_block > (int64_t)kPrefetchQuads * 4 * 128 * c->geo.nt)
+  const int64_t cap = shot_kind(c) ? (int64_t)ShotMath<double>::kPrefetch * ShotMath<double>::kWords
+                                    : (int64_t)ShotMath<float>::kPrefetch * ShotMath<float>::kWords;
+  if (c->geo.words_per_block > cap * 128 * c->geo.nt)
     return c->fail(SFM_EINVAL, "coefficient block larger than the shot kernel's prefetch");
+  if (shots_lds_bytes(c->geo.P16, shot_kind(c) ? sizeof(double) : sizeof(float)) > (size_t)kMaxLdsBytes)
+    return c->fail(SFM_EINVAL, "shot kernel LDS above the 160 KB of a CU for this 6m");
   if (nshot < 1 || nshot > kShotCols) return c->fail(SFM_EINVAL, "nshot must lie in 1..64");
   std::vector<int32_t> src_shot(std::max(c->nsrc, 1), -1);
   for (int n = 0; n < nshot; ++n) {
@@ -482,7 +554,7 @@ ShotParams main_params(sfm_ctx c, const float* wavelet_dev, double dt) {
   const Topology& t = c->topo;
   const TileGeometry& g = c->geo;
   ShotParams prm{};
-  prm.tiles = static_cast<const float*>(c->tiles_d);
+  prm.tiles = c->tiles_d;
   prm.words_per_block = g.words_per_block;
   prm.words_per_sub = (int64_t)(2 * t.k - 1) * g.words_per_block;
   prm.wmap = c->wmap_d;
@@ -504,9 +576,10 @@ ShotParams main_params(sfm_ctx c, const float* wavelet_dev, double dt) {
   return prm;
 }
 
-hipError_t launch_shots_main(int variant, const ShotParams& prm, int nt, hipStream_t st, bool set_attr = true) {
-  const size_t lds = shots_lds_bytes(prm.P);
-  const ShotKernel kern = kShotVariants[variant];
+hipError_t launch_shots_main(int kind, int variant, const ShotParams& prm, int nt, hipStream_t st,
+                             bool set_attr = true) {
+  const size_t lds = shots_lds_bytes(prm.P, kind ? sizeof(double) : sizeof(float));
+  const ShotKernel kern = kShotVariants[kind][variant];
   if (lds > kDefaultLdsBytes && set_attr) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -524,18 +597,20 @@ sfm_status autotune_shots(sfm_ctx c, hipStream_t st) {
   hipEvent_t a, b;
   SH_TRY_HIP(hipEventCreate(&a));
   SH_TRY_HIP(hipEventCreate(&b));
-  int best = 0;
+  int best = -1;
   for (int v = 0; v < kNumShotVariants; ++v) {
-    for (int r = 0; r < 2; ++r) SH_TRY_HIP(launch_shots_main(v, prm, c->geo.nt, st));
+    c->shots_tune_ms[v] = -1.0;
+    if (c->geo.nt > kShotVariantMaxNt[shot_kind(c)][v]) continue;   // work-group too large for it
+    for (int r = 0; r < 2; ++r) SH_TRY_HIP(launch_shots_main(shot_kind(c), v, prm, c->geo.nt, st));
     SH_TRY_HIP(hipEventRecord(a, st));
     constexpr int kReps = 5;
-    for (int r = 0; r < kReps; ++r) SH_TRY_HIP(launch_shots_main(v, prm, c->geo.nt, st));
+    for (int r = 0; r < kReps; ++r) SH_TRY_HIP(launch_shots_main(shot_kind(c), v, prm, c->geo.nt, st));
     SH_TRY_HIP(hipEventRecord(b, st));
     SH_TRY_HIP(hipEventSynchronize(b));
     float ms = 0.f;
     SH_TRY_HIP(hipEventElapsedTime(&ms, a, b));
     c->shots_tune_ms[v] = ms / kReps;
-    if (c->shots_tune_ms[v] < c->shots_tune_ms[best]) best = v;
+    if (best < 0 || c->shots_tune_ms[v] < c->shots_tune_ms[best]) best = v;
   }
   SH_TRY_HIP(hipEventDestroy(a));
   SH_TRY_HIP(hipEventDestroy(b));
@@ -605,7 +680,7 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
     prm.step_base = base;
     fp.step = n;
     fp.step_base = base;
-    hipError_t e = launch_shots_main(c->shots_variant, prm, g.nt, s, set_attr);
+    hipError_t e = launch_shots_main(shot_kind(c), c->shots_variant, prm, g.nt, s, set_attr);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(shots_face_kernel, dim3((unsigned)((nface + 255) / 256)), dim3(256), 0, s, fp);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -674,7 +749,7 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
     }
     prm.step = n;
     prm.step_base = nullptr;
-    SH_TRY_HIP(launch_shots_main(c->shots_variant, prm, g.nt, st));
+    SH_TRY_HIP(launch_shots_main(shot_kind(c), c->shots_variant, prm, g.nt, st));
     if (timing) SH_TRY_HIP(hipEventRecord(ev[1], st));
     fp.step = n;
     fp.step_base = nullptr;
@@ -770,10 +845,10 @@ sfm_status sfm_shots_tuning(sfm_ctx c, int32_t* chosen_waves, double* ms, int32_
   if (!c) return SFM_EINVAL;
   c->err.clear();
   if (c->nshot == 0) return c->fail(SFM_ESTATE, "call sfm_shots_init first");
-  if (chosen_waves) *chosen_waves = kShotVariantWaves[c->shots_variant];
+  if (chosen_waves) *chosen_waves = kShotVariantWaves[shot_kind(c)][c->shots_variant];
   if (count) *count = kNumShotVariants;
   for (int v = 0; v < std::min<int>(cap, kNumShotVariants); ++v) {
-    if (ms) ms[2 * v] = kShotVariantWaves[v];
+    if (ms) ms[2 * v] = kShotVariantWaves[shot_kind(c)][v];
     if (ms) ms[2 * v + 1] = c->shots_tune_ms[v];
   }
   return SFM_OK;

@@ -301,7 +301,9 @@ def sfm_shots_tuning(ctx: int):
     chosen, count = _I32(0), _I32(0)
     ms = np.zeros(16, np.float64)
     _check(ctx, load_library().sfm_shots_tuning(ctx, ctypes.byref(chosen), _ptr(ms), 8, ctypes.byref(count)))
-    return int(chosen.value), [(int(ms[2 * v]), float(ms[2 * v + 1])) for v in range(count.value)]
+    # variants whose work-group limit is below this 6m were not run (time < 0)
+    return int(chosen.value), [(int(ms[2 * v]), float(ms[2 * v + 1])) for v in range(count.value)
+                               if ms[2 * v + 1] >= 0]
 
 
 def sfm_shots_timing(ctx: int):

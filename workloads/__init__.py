@@ -209,3 +209,49 @@ CFG_ADJOINT = Workload(
     m=12, k=16, f_peak=12.0, nsteps=4000, src=((127, 127, 2),), rec_grid=(128, 128),
     velocity="layered_inclusions", seed=1406)
 ADJOINT_ANOMALY = dict(center=(128, 128, 128), radius=30.0, amplitude=0.05)
+
+
+def uneven_boxes(ncells: int, sizes=(24, 32, 48), seed: int = 0) -> Tuple[int, ...]:
+    """Seeded box sizes from ``sizes`` adding up to ``ncells`` along one axis: each box is drawn
+    uniformly among the sizes that still leave a remainder the sizes can fill."""
+    fill = [True] + [False] * ncells
+    for n in range(1, ncells + 1):
+        fill[n] = any(n >= s and fill[n - s] for s in sizes)
+    if not fill[ncells]:
+        raise ValueError(f"{ncells} cells cannot be split into boxes of {sizes}")
+    rng = np.random.default_rng(seed)
+    out, rem = [], ncells
+    while rem:
+        opts = [s for s in sizes if s <= rem and fill[rem - s]]
+        out.append(int(opts[int(rng.integers(len(opts)))]))
+        rem -= out[-1]
+    return tuple(out)
+
+
+def level_choices(n_subdomains: int, levels=(8, 12, 16, 24, 32), seed: int = 0) -> np.ndarray:
+    """Seeded ROM size per subdomain, uniform over ``levels``."""
+    rng = np.random.default_rng(seed)
+    return np.asarray(levels, dtype=np.int32)[rng.integers(len(levels), size=n_subdomains)]
+
+
+def surface_shots(cfg: Workload, n: int, seed: int = 2024, depth: int = 2) -> List[Tuple[int, int, int]]:
+    """n shot nodes uniformly random on the surface (at ``depth`` nodes), off every box plane."""
+    rng = np.random.default_rng(seed)
+    out: List[Tuple[int, int, int]] = []
+    while len(out) < n:
+        ijk = (int(rng.integers(1, cfg.ncell[0])), int(rng.integers(1, cfg.ncell[1])), depth)
+        if cfg.on_box_plane(ijk) or ijk in out:
+            continue
+        out.append(ijk)
+    return out
+
+
+# Many-shot workload: 384 x 384 x 256 cells as a tensor product of boxes of 24, 32 or 48 cells per
+# axis (seeded), m = 12 (p = 72), ROM size per subdomain from {8, 12, 16, 24, 32} (seeded; built
+# with k = 32), 64 shots at random surface nodes, 1500 steps, 192 x 192 surface receivers.
+CFG_SHOTS = Workload(
+    name="layered_384x384x256_uneven_m12_k8-32_64shots", ncell=(384, 384, 256),
+    sub_cells=(uneven_boxes(384, seed=11), uneven_boxes(384, seed=12), uneven_boxes(256, seed=13)),
+    h=10.0, m=12, k=32, f_peak=12.0, nsteps=1500, src=(), rec_grid=(192, 192),
+    velocity="layered_inclusions", seed=1406)
+SHOTS_LEVEL_SEED = 14
