@@ -341,6 +341,47 @@ sfm_status sfm_shots_tuning(sfm_ctx ctx, int32_t* chosen_waves, double* ms, int3
  * *timed_steps, ms3 = {main, face, record}; then resets the counters.  Never fails for a valid ctx. */
 sfm_status sfm_shots_timing(sfm_ctx ctx, int64_t* timed_steps, double* ms3);
 
+/* ------------------------------------------------------------------------------------------
+ * Learned ROM surrogate network (a model of the many ROM builds FWI needs; Introduction)
+ * ------------------------------------------------------------------------------------------
+ * A 3D CNN: four 3x3x3 convolutions of stride 2 and zero padding 1 (n -> (n - 1) / 2 + 1 nodes
+ * per axis), each with bias and ReLU, `channels` channels, then a dense head to n_out outputs.
+ * Every product runs on the bf16 matrix cores with FP32 accumulation (operands rounded to
+ * bfloat16, nearest-even); activations, gradients, master weights and Adam moments are FP32.
+ * Layouts: inputs float [batch][n_in][n_in][n_in]; activations channels-last; the flat FP32
+ * parameter vector is W1 b1 W2 b2 W3 b3 W4 b4 Wd bd with conv weights [co][t][ci] (tap
+ * t = 9 dz + 3 dy + dx) and the dense weights [n_out][features] over the last activation in
+ * [z][y][x][channel] order.  A net is bound to the current device; calls on one net do not
+ * overlap.  Errors: SFM_EINVAL (bad sizes), SFM_ENOMEM, SFM_EHIP; message in sfm_cnn_last_error. */
+typedef struct sfm_cnn_s* sfm_cnn;
+
+/* Allocate a net for batches up to max_batch; weights He-initialised from seed (biases 0). */
+sfm_status sfm_cnn_create(int32_t n_in, int32_t channels, int32_t n_out, int32_t max_batch, uint64_t seed,
+                          sfm_cnn* out);
+void sfm_cnn_destroy(sfm_cnn net);
+/* Last error message of net (net == NULL: of the last failed sfm_cnn_create on this thread). */
+const char* sfm_cnn_last_error(sfm_cnn net);
+/* *n_params = parameter count, *features = inputs of the dense head, nodes5 (host int32 [5], may
+ * be NULL) = nodes per axis of the input and of each activation. */
+sfm_status sfm_cnn_info(sfm_cnn net, int64_t* n_params, int32_t* features, int32_t* nodes5);
+/* Copy the flat parameters to get_host and/or from set_host (host float [n_params]; either may be
+ * NULL; setting clears the Adam moments).  Synchronizes. */
+sfm_status sfm_cnn_params(sfm_cnn net, float* get_host, const float* set_host);
+/* y_dev (device float [batch][n_out], may be NULL) = net(x_dev) (device float
+ * [batch][n_in^3]); x_dev must stay valid until a following sfm_cnn_backward. */
+sfm_status sfm_cnn_forward(sfm_cnn net, const float* x_dev, int32_t batch, float* y_dev, void* stream);
+/* Parameter gradients of sum(dy * y) for the last forward pass into grad_dev (device float
+ * [n_params], flat layout); dy_dev device float [batch][n_out].  Errors: SFM_ESTATE (no forward). */
+sfm_status sfm_cnn_backward(sfm_cnn net, const float* dy_dev, float* grad_dev, void* stream);
+/* Train on n_samples pairs (x_dev [n_samples][n_in^3], target_dev [n_samples][n_out], device):
+ * `epochs` passes in a seeded shuffled order, batches of `batch` (a final partial batch is
+ * dropped), loss = mean squared error, Adam (beta 0.9 / 0.999, eps 1e-8, learning rate lr).
+ * loss_per_epoch (host double [epochs], may be NULL): mean batch loss of each epoch.  Synchronizes
+ * once per batch. */
+sfm_status sfm_cnn_train(sfm_cnn net, const float* x_dev, const float* target_dev, int64_t n_samples,
+                         int32_t batch, int32_t epochs, float lr, uint64_t seed, double* loss_per_epoch,
+                         void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -63,6 +63,14 @@ _D = ctypes.c_double
 # name -> (restype, argtypes); mirrors include/sfm.h
 SIGNATURES = {
     "sfm_create": (_I32, [ctypes.POINTER(sfm_config), ctypes.POINTER(_VP)]),
+    "sfm_cnn_create": (_I32, [_I32, _I32, _I32, _I32, ctypes.c_uint64, ctypes.POINTER(_VP)]),
+    "sfm_cnn_destroy": (None, [_VP]),
+    "sfm_cnn_last_error": (ctypes.c_char_p, [_VP]),
+    "sfm_cnn_info": (_I32, [_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I32), _VP]),
+    "sfm_cnn_params": (_I32, [_VP, _VP, _VP]),
+    "sfm_cnn_forward": (_I32, [_VP, _VP, _I32, _VP, _VP]),
+    "sfm_cnn_backward": (_I32, [_VP, _VP, _VP, _VP]),
+    "sfm_cnn_train": (_I32, [_VP, _VP, _VP, _I64, _I32, _I32, ctypes.c_float, ctypes.c_uint64, _VP, _VP]),
     "sfm_create_boxes": (_I32, [ctypes.POINTER(sfm_config), _VP, _VP, ctypes.POINTER(_VP)]),
     "sfm_destroy": (None, [_VP]),
     "sfm_last_error": (ctypes.c_char_p, [_VP]),
@@ -407,3 +415,62 @@ class Sfm:
 
     def info(self):
         return sfm_query(self.ctx)
+
+
+# ------------------------------------------------------------------ surrogate network
+def _cnn_check(net, status: int):
+    if status != SFM_OK:
+        msg = load_library().sfm_cnn_last_error(net)
+        raise SfmError(status, msg.decode() if msg else "")
+
+
+class Cnn:
+    """Owning handle around an sfm_cnn (the surrogate network); arguments as in include/sfm.h."""
+
+    def __init__(self, n_in: int, channels: int, n_out: int, max_batch: int, seed: int = 0):
+        lib = load_library()
+        out = _VP()
+        _cnn_check(None, lib.sfm_cnn_create(int(n_in), int(channels), int(n_out), int(max_batch), int(seed),
+                                            ctypes.byref(out)))
+        self.net = out.value
+        self.n_in, self.channels, self.n_out, self.max_batch = n_in, channels, n_out, max_batch
+        n, f = _I64(), _I32()
+        nodes = np.zeros(5, np.int32)
+        _cnn_check(self.net, lib.sfm_cnn_info(self.net, ctypes.byref(n), ctypes.byref(f), _ptr(nodes)))
+        self.n_params, self.features, self.nodes = int(n.value), int(f.value), nodes.tolist()
+
+    def close(self):
+        if getattr(self, "net", None):
+            load_library().sfm_cnn_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        _cnn_check(self.net, load_library().sfm_cnn_params(self.net, _ptr(out), None))
+        return out
+
+    def set_params(self, flat) -> None:
+        arr = _host(flat, np.float32)
+        if arr.size != self.n_params:
+            raise ValueError(f"need {self.n_params} parameters")
+        _cnn_check(self.net, load_library().sfm_cnn_params(self.net, None, _ptr(arr)))
+
+    def forward(self, x, y=None, stream=None) -> None:
+        _cnn_check(self.net, load_library().sfm_cnn_forward(self.net, _dev(x), int(x.shape[0]), _dev(y),
+                                                            _stream(stream)))
+
+    def backward(self, dy, grad, stream=None) -> None:
+        _cnn_check(self.net, load_library().sfm_cnn_backward(self.net, _dev(dy), _dev(grad), _stream(stream)))
+
+    def train(self, x, target, batch: int, epochs: int, lr: float, seed: int = 0, stream=None) -> np.ndarray:
+        losses = np.zeros(max(epochs, 1), np.float64)
+        _cnn_check(self.net, load_library().sfm_cnn_train(self.net, _dev(x), _dev(target), int(x.shape[0]),
+                                                          int(batch), int(epochs), float(lr), int(seed),
+                                                          _ptr(losses), _stream(stream)))
+        return losses[:epochs]
