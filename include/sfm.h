@@ -361,9 +361,10 @@ sfm_status sfm_cnn_create(int32_t n_in, int32_t channels, int32_t n_out, int32_t
 void sfm_cnn_destroy(sfm_cnn net);
 /* Last error message of net (net == NULL: of the last failed sfm_cnn_create on this thread). */
 const char* sfm_cnn_last_error(sfm_cnn net);
-/* *n_params = parameter count, *features = inputs of the dense head, nodes5 (host int32 [5], may
- * be NULL) = nodes per axis of the input and of each activation. */
-sfm_status sfm_cnn_info(sfm_cnn net, int64_t* n_params, int32_t* features, int32_t* nodes5);
+/* *n_params = parameter count, *features = inputs of the dense head, nodes5 (host int32 [5]) =
+ * nodes per axis of the input and of each activation, dims4 (host int32 [4]) = {n_in, channels,
+ * n_out, max_batch}; any may be NULL. */
+sfm_status sfm_cnn_info(sfm_cnn net, int64_t* n_params, int32_t* features, int32_t* nodes5, int32_t* dims4);
 /* Copy the flat parameters to get_host and/or from set_host (host float [n_params]; either may be
  * NULL; setting clears the Adam moments).  Synchronizes. */
 sfm_status sfm_cnn_params(sfm_cnn net, float* get_host, const float* set_host);
@@ -373,6 +374,12 @@ sfm_status sfm_cnn_forward(sfm_cnn net, const float* x_dev, int32_t batch, float
 /* Parameter gradients of sum(dy * y) for the last forward pass into grad_dev (device float
  * [n_params], flat layout); dy_dev device float [batch][n_out].  Errors: SFM_ESTATE (no forward). */
 sfm_status sfm_cnn_backward(sfm_cnn net, const float* dy_dev, float* grad_dev, void* stream);
+/* Output scale: per output, the mean and standard deviation (1 for a constant output) of
+ * target_dev (device float [n_samples][n_out]); afterwards the net is trained on (target - mean)
+ * / sd and sfm_cnn_forward returns mean + sd * (net output).  mean_host / sd_host (host float
+ * [n_out], may be NULL) receive the scale. */
+sfm_status sfm_cnn_fit_scale(sfm_cnn net, const float* target_dev, int64_t n_samples, float* mean_host,
+                             float* sd_host, void* stream);
 /* Train on n_samples pairs (x_dev [n_samples][n_in^3], target_dev [n_samples][n_out], device):
  * `epochs` passes in a seeded shuffled order, batches of `batch` (a final partial batch is
  * dropped), loss = mean squared error, Adam (beta 0.9 / 0.999, eps 1e-8, learning rate lr).
@@ -381,6 +388,40 @@ sfm_status sfm_cnn_backward(sfm_cnn net, const float* dy_dev, float* grad_dev, v
 sfm_status sfm_cnn_train(sfm_cnn net, const float* x_dev, const float* target_dev, int64_t n_samples,
                          int32_t batch, int32_t epochs, float lr, uint64_t seed, double* loss_per_epoch,
                          void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Learned ROMs with block Lanczos as judge and fallback
+ * ------------------------------------------------------------------------------------------
+ * The network sees a subdomain's log(c / 3000 m/s) on its (n+1)^3 nodes ([z][y][x]; equal cubic
+ * subdomains only) and predicts the upper triangles (row-major, i <= j) of Gamma_1..Gamma_k then
+ * Gamma-hat_1..Gamma-hat_k: n_out = 2 k p(p+1)/2. */
+
+/* Network inputs of every subdomain: x_dev device float [S][(n+1)^3] from vel_dev (as in
+ * sfm_build_roms).  Errors: SFM_EINVAL (uneven or non-cubic boxes).  Synchronizes. */
+sfm_status sfm_rom_inputs(sfm_ctx ctx, const float* vel_dev, float* x_dev, void* stream);
+
+/* Training targets from the current ROMs: t_dev device float [S][n_out].  Synchronizes. */
+sfm_status sfm_rom_targets(sfm_ctx ctx, float* t_dev, void* stream);
+
+/* err_host[s] (host double [S]) = max over the 8 Laplace frequencies s_f = 2 pi f_peak {1/4, 1/2,
+ * 3/4, 1, 3/2, 2, 5/2, 3} of ||M_a(s_f) - M(s_f)||_F / ||M(s_f)||_F, where M is the matrix
+ * S-fraction NtD map (Stage 2 section) of the current ROM of subdomain s and M_a that of the
+ * blocks coef_dev (device double [S][2][k][p][p], Gamma then Gamma-hat), evaluated in FP64 on
+ * the device (Gauss-Jordan inverses with partial pivoting; a singular block gives +inf).
+ * Requires 6m <= 64.  Synchronizes. */
+sfm_status sfm_ntd_error(sfm_ctx ctx, const double* coef_dev, double f_peak, double* err_host, void* stream);
+
+/* Learned ROM build: block Lanczos ROMs of every subdomain (as sfm_build_roms without initial
+ * conditions; they judge and back up the network), the network's predictions of every
+ * subdomain's blocks (Gamma-hat_1, the face masses, always taken from Lanczos), the NtD judge
+ * above, and the prediction kept where its error is <= tol and the subdomain holds no source or
+ * receiver.  accepted (host int32 [S]), ntd_err (host double [S]) and seconds (host double [4]:
+ * Lanczos, network, judge, repack) may be NULL.  Afterwards the context steps the mixed ROMs
+ * (call sfm_cfl_dt again).  Errors as sfm_build_roms, SFM_EINVAL for a network whose input or
+ * output size does not match (n+1 nodes, 2 k p(p+1)/2 outputs) or 6m > 64.  Synchronizes. */
+sfm_status sfm_build_roms_surrogate(sfm_ctx ctx, sfm_cnn net, double tol, double f_peak, const float* vel_dev,
+                                    int32_t nsrc, const int32_t* src_ijk, int32_t nrec, const int32_t* rec_ijk,
+                                    int32_t* accepted, double* ntd_err, double* seconds, void* stream);
 
 #ifdef __cplusplus
 }

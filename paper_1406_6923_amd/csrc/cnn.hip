@@ -290,6 +290,35 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
   }
 }
 
+// Per-output mean and standard deviation over n samples of [n][cols] (FP64 sums); a constant
+// output gets std 1.
+__global__ void fit_scale_kernel(const float* __restrict__ t, int64_t n, int64_t cols, float* __restrict__ mean,
+                                 float* __restrict__ sd) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cols; c += (int64_t)gridDim.x * blockDim.x) {
+    double s1 = 0.0;
+    for (int64_t r = 0; r < n; ++r) s1 += t[r * cols + c];
+    const double mu = s1 / (double)n;
+    double s2 = 0.0;
+    for (int64_t r = 0; r < n; ++r) {
+      const double d = t[r * cols + c] - mu;
+      s2 += d * d;
+    }
+    const double sdv = sqrt(s2 / (double)n);
+    mean[c] = (float)mu;
+    sd[c] = sdv > 1e-30 * (fabs(mu) + 1e-300) && sdv > 0.0 ? (float)sdv : 1.f;
+  }
+}
+
+// x[r][c] = (x[r][c] - mean[c]) / sd[c]  (dir = +1), or mean[c] + sd[c] x[r][c]  (dir = -1)
+__global__ void apply_scale_kernel(float* __restrict__ x, int64_t rows, int64_t cols, const float* __restrict__ mean,
+                                   const float* __restrict__ sd, int dir) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e % cols;
+    x[e] = dir > 0 ? (x[e] - mean[c]) / sd[c] : fmaf(sd[c], x[e], mean[c]);
+  }
+}
+
 // rows of x gathered by index: dst[r] = src[idx[r]] (rows of `len` floats)
 __global__ void gather_rows_kernel(const float* __restrict__ src, const int32_t* __restrict__ idx, int rows, int64_t len,
                                    float* __restrict__ dst) {
@@ -329,6 +358,9 @@ struct sfm_cnn_s {
   float* dact[kConv + 1] = {};
   float* y = nullptr;
   float* dy = nullptr;
+  float* out_mean = nullptr;            // output scale: the net predicts (target - mean) / sd
+  float* out_sd = nullptr;
+  bool scaled = false;
   float* part = nullptr;                // split-K / column-sum partials
   int64_t part_len = 0;
   double* loss_part = nullptr;
@@ -536,6 +568,8 @@ sfm_status sfm_cnn_create(int32_t n_in, int32_t channels, int32_t n_out, int32_t
   }
   net->y = F((int64_t)max_batch * n_out);
   net->dy = F((int64_t)max_batch * n_out);
+  net->out_mean = F(n_out);
+  net->out_sd = F(n_out);
   net->part_len = partial_len(*net, max_batch);
   net->part = F(net->part_len);
   net->loss_part = static_cast<double*>(net->alloc(4096 * sizeof(double), &e));
@@ -575,12 +609,18 @@ void sfm_cnn_destroy(sfm_cnn net) {
 
 const char* sfm_cnn_last_error(sfm_cnn net) { return net ? net->err.c_str() : g_cnn_create_error.c_str(); }
 
-sfm_status sfm_cnn_info(sfm_cnn net, int64_t* n_params, int32_t* feat, int32_t* nodes5) {
+sfm_status sfm_cnn_info(sfm_cnn net, int64_t* n_params, int32_t* feat, int32_t* nodes5, int32_t* dims4) {
   if (!net) return SFM_EINVAL;
   if (n_params) *n_params = net->n_params;
   if (feat) *feat = (int32_t)net->feat;
   if (nodes5)
     for (int l = 0; l <= kConv; ++l) nodes5[l] = net->nodes[l];
+  if (dims4) {
+    dims4[0] = net->n_in;
+    dims4[1] = net->ch;
+    dims4[2] = net->n_out;
+    dims4[3] = net->max_batch;
+  }
   return SFM_OK;
 }
 
@@ -607,8 +647,32 @@ sfm_status sfm_cnn_forward(sfm_cnn net, const float* x_dev, int32_t batch, float
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const sfm_status rc = forward_pass(net, x_dev, batch, st);
   if (rc != SFM_OK) return rc;
-  if (y_dev)
+  if (y_dev) {
     CNN_TRY(hipMemcpyAsync(y_dev, net->y, (size_t)batch * net->n_out * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (net->scaled) {
+      hipLaunchKernelGGL(apply_scale_kernel, dim3(blocks_for((int64_t)batch * net->n_out)), dim3(256), 0, st, y_dev,
+                         (int64_t)batch, (int64_t)net->n_out, net->out_mean, net->out_sd, -1);
+      CNN_TRY(hipGetLastError());
+    }
+  }
+  return SFM_OK;
+}
+
+sfm_status sfm_cnn_fit_scale(sfm_cnn net, const float* target_dev, int64_t n_samples, float* mean_host,
+                             float* sd_host, void* stream) {
+  if (!net) return SFM_EINVAL;
+  net->err.clear();
+  if (!target_dev || n_samples < 1) return net->fail(SFM_EINVAL, "need target_dev and n_samples >= 1");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(fit_scale_kernel, dim3(blocks_for(net->n_out)), dim3(256), 0, st, target_dev, n_samples,
+                     (int64_t)net->n_out, net->out_mean, net->out_sd);
+  CNN_TRY(hipGetLastError());
+  net->scaled = true;
+  if (mean_host || sd_host) {
+    CNN_TRY(hipStreamSynchronize(st));
+    if (mean_host) CNN_TRY(hipMemcpy(mean_host, net->out_mean, (size_t)net->n_out * sizeof(float), hipMemcpyDeviceToHost));
+    if (sd_host) CNN_TRY(hipMemcpy(sd_host, net->out_sd, (size_t)net->n_out * sizeof(float), hipMemcpyDeviceToHost));
+  }
   return SFM_OK;
 }
 
@@ -645,6 +709,11 @@ sfm_status sfm_cnn_train(sfm_cnn net, const float* x_dev, const float* target_de
       hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks_for((int64_t)batch * net->n_out)), dim3(256), 0, st,
                          target_dev, net->idx_d, batch, (int64_t)net->n_out, net->tgt);
       CNN_TRY(hipGetLastError());
+      if (net->scaled) {
+        hipLaunchKernelGGL(apply_scale_kernel, dim3(blocks_for((int64_t)batch * net->n_out)), dim3(256), 0, st,
+                           net->tgt, (int64_t)batch, (int64_t)net->n_out, net->out_mean, net->out_sd, 1);
+        CNN_TRY(hipGetLastError());
+      }
       sfm_status rc = forward_pass(net, net->xin, batch, st);
       if (rc != SFM_OK) return rc;
       const int64_t ny = (int64_t)batch * net->n_out;

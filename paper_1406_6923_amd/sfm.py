@@ -66,10 +66,15 @@ SIGNATURES = {
     "sfm_cnn_create": (_I32, [_I32, _I32, _I32, _I32, ctypes.c_uint64, ctypes.POINTER(_VP)]),
     "sfm_cnn_destroy": (None, [_VP]),
     "sfm_cnn_last_error": (ctypes.c_char_p, [_VP]),
-    "sfm_cnn_info": (_I32, [_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I32), _VP]),
+    "sfm_cnn_info": (_I32, [_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I32), _VP, _VP]),
+    "sfm_rom_inputs": (_I32, [_VP, _VP, _VP, _VP]),
+    "sfm_rom_targets": (_I32, [_VP, _VP, _VP]),
+    "sfm_ntd_error": (_I32, [_VP, _VP, _D, _VP, _VP]),
+    "sfm_build_roms_surrogate": (_I32, [_VP, _VP, _D, _D, _VP, _I32, _VP, _I32, _VP, _VP, _VP, _VP, _VP]),
     "sfm_cnn_params": (_I32, [_VP, _VP, _VP]),
     "sfm_cnn_forward": (_I32, [_VP, _VP, _I32, _VP, _VP]),
     "sfm_cnn_backward": (_I32, [_VP, _VP, _VP, _VP]),
+    "sfm_cnn_fit_scale": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP]),
     "sfm_cnn_train": (_I32, [_VP, _VP, _VP, _I64, _I32, _I32, ctypes.c_float, ctypes.c_uint64, _VP, _VP]),
     "sfm_create_boxes": (_I32, [ctypes.POINTER(sfm_config), _VP, _VP, ctypes.POINTER(_VP)]),
     "sfm_destroy": (None, [_VP]),
@@ -436,7 +441,7 @@ class Cnn:
         self.n_in, self.channels, self.n_out, self.max_batch = n_in, channels, n_out, max_batch
         n, f = _I64(), _I32()
         nodes = np.zeros(5, np.int32)
-        _cnn_check(self.net, lib.sfm_cnn_info(self.net, ctypes.byref(n), ctypes.byref(f), _ptr(nodes)))
+        _cnn_check(self.net, lib.sfm_cnn_info(self.net, ctypes.byref(n), ctypes.byref(f), _ptr(nodes), None))
         self.n_params, self.features, self.nodes = int(n.value), int(f.value), nodes.tolist()
 
     def close(self):
@@ -468,9 +473,45 @@ class Cnn:
     def backward(self, dy, grad, stream=None) -> None:
         _cnn_check(self.net, load_library().sfm_cnn_backward(self.net, _dev(dy), _dev(grad), _stream(stream)))
 
+    def fit_scale(self, target, stream=None):
+        mean = np.empty(self.n_out, np.float32)
+        sd = np.empty(self.n_out, np.float32)
+        _cnn_check(self.net, load_library().sfm_cnn_fit_scale(self.net, _dev(target), int(target.shape[0]), _ptr(mean),
+                                                              _ptr(sd), _stream(stream)))
+        return mean, sd
+
     def train(self, x, target, batch: int, epochs: int, lr: float, seed: int = 0, stream=None) -> np.ndarray:
         losses = np.zeros(max(epochs, 1), np.float64)
         _cnn_check(self.net, load_library().sfm_cnn_train(self.net, _dev(x), _dev(target), int(x.shape[0]),
                                                           int(batch), int(epochs), float(lr), int(seed),
                                                           _ptr(losses), _stream(stream)))
         return losses[:epochs]
+
+
+def sfm_rom_inputs(ctx: int, vel, x, stream=None) -> None:
+    _check(ctx, load_library().sfm_rom_inputs(ctx, _dev(vel), _dev(x), _stream(stream)))
+
+
+def sfm_rom_targets(ctx: int, t, stream=None) -> None:
+    _check(ctx, load_library().sfm_rom_targets(ctx, _dev(t), _stream(stream)))
+
+
+def sfm_ntd_error(ctx: int, coef, f_peak: float, stream=None) -> np.ndarray:
+    err = np.empty(sfm_query(ctx)["n_subdomains"], np.float64)
+    _check(ctx, load_library().sfm_ntd_error(ctx, _dev(coef), float(f_peak), _ptr(err), _stream(stream)))
+    return err
+
+
+def sfm_build_roms_surrogate(ctx: int, net: "Cnn", tol: float, f_peak: float, vel, src_ijk=None, rec_ijk=None,
+                             stream=None):
+    """Returns (accepted [S] bool, ntd_err [S], seconds [4])."""
+    src = _host(np.zeros((0, 3)) if src_ijk is None else src_ijk, np.int32).reshape(-1, 3)
+    rec = _host(np.zeros((0, 3)) if rec_ijk is None else rec_ijk, np.int32).reshape(-1, 3)
+    S = sfm_query(ctx)["n_subdomains"]
+    acc = np.zeros(S, np.int32)
+    err = np.zeros(S, np.float64)
+    secs = np.zeros(4, np.float64)
+    _check(ctx, load_library().sfm_build_roms_surrogate(ctx, net.net, float(tol), float(f_peak), _dev(vel), len(src),
+                                                        _ptr(src), len(rec), _ptr(rec), _ptr(acc), _ptr(err),
+                                                        _ptr(secs), _stream(stream)))
+    return acc.astype(bool), err, secs

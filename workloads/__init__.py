@@ -255,3 +255,29 @@ CFG_SHOTS = Workload(
     h=10.0, m=12, k=32, f_peak=12.0, nsteps=1500, src=(), rec_grid=(192, 192),
     velocity="layered_inclusions", seed=1406)
 SHOTS_LEVEL_SEED = 14
+
+
+def surrogate_velocity(nodes, seed: int, layer_cells: float = 6.0, sigma: float = 0.1, blob_density: float = 2e-5,
+                       blob_radius=(3.0, 10.0), blob_speed: float = 4500.0) -> np.ndarray:
+    """Training media of the learned ROMs: horizontal layers (thicknesses ~ Exp(layer_cells) cells,
+    speeds ~U(1500, 4000) m/s), times a pointwise lognormal factor exp(sigma N(0, 1)), plus
+    spherical bodies of ``blob_speed`` (about blob_density per node, radii ~U(blob_radius))."""
+    nx, ny, nz = nodes
+    rng = np.random.default_rng(seed)
+    tops = np.cumsum(rng.exponential(layer_cells, size=int(4 * nz / layer_cells) + 8))
+    layer = np.searchsorted(tops, np.arange(nz, dtype=np.float64), side="right")
+    speeds = rng.uniform(1500.0, 4000.0, size=layer.max() + 1)
+    c = np.empty((nz, ny, nx), dtype=np.float64)
+    c[:] = speeds[layer][:, None, None]
+    c *= np.exp(sigma * rng.standard_normal(c.shape))
+    nblob = rng.poisson(blob_density * nx * ny * nz)
+    centres = rng.uniform([0, 0, 0], [nx - 1, ny - 1, nz - 1], size=(nblob, 3))
+    radii = rng.uniform(blob_radius[0], blob_radius[1], size=nblob)
+    for (cx, cy, cz), r in zip(centres, radii):
+        lo = [max(0, int(math.floor(v - r))) for v in (cx, cy, cz)]
+        hi = [min(n - 1, int(math.ceil(v + r))) for v, n in zip((cx, cy, cz), (nx, ny, nz))]
+        zs, ys, xs = np.arange(lo[2], hi[2] + 1), np.arange(lo[1], hi[1] + 1), np.arange(lo[0], hi[0] + 1)
+        d2 = (zs[:, None, None] - cz) ** 2 + (ys[None, :, None] - cy) ** 2 + (xs[None, None, :] - cx) ** 2
+        view = c[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]
+        view[d2 <= r * r] = blob_speed
+    return c
