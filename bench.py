@@ -324,6 +324,73 @@ def uneven_shots_probe(torch, sfm, dev, stream, nsteps: int, nshot: int = 64, co
     return out
 
 
+def surrogate_probe(torch, sfm, dev, stream, n_samples: int, epochs: int, tol: float = 1e-3):
+    """Learned ROMs: a training set of n_samples 32^3-cell subdomains (m = 8, k = 16) of seeded
+    layered / lognormal / blob media labelled by the device Lanczos build, the network trained on
+    the device, then the learned build (judge and fallback) of a 256^3 grid of unseen media."""
+    m, k, cells, h = 8, 16, 32, 10.0
+    p = 6 * m
+    n_out = 2 * k * p * (p + 1) // 2
+    nn = cells + 1
+    per_domain = (16, 16, 16)
+    n_dom = max(1, -(-n_samples // int(np.prod(per_domain))))
+    xs = torch.empty((n_dom * int(np.prod(per_domain)), nn ** 3), dtype=torch.float32, device=dev)
+    ts = torch.empty((xs.shape[0], n_out), dtype=torch.float32, device=dev)
+    t_label = 0.0
+    for d in range(n_dom):
+        ncell = tuple(cells * b for b in per_domain)
+        c = W.surrogate_velocity(tuple(x + 1 for x in ncell), seed=5000 + d).astype(np.float32)
+        vel = torch.from_numpy(c).to(dev)
+        del c
+        hd = sfm.Sfm(ncell, (cells, cells, cells), h, m, k, precision=sfm.SFM_PREC_FP64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sfm.sfm_build_roms(hd.ctx, vel, stream=stream)
+        torch.cuda.synchronize()
+        t_label += time.perf_counter() - t0
+        S = int(np.prod(per_domain))
+        sfm.sfm_rom_inputs(hd.ctx, vel, xs[d * S:(d + 1) * S], stream=stream)
+        sfm.sfm_rom_targets(hd.ctx, ts[d * S:(d + 1) * S], stream=stream)
+        hd.close()
+        del vel
+        log(f"[bench] surrogate training set: domain {d + 1}/{n_dom} labelled")
+    xs, ts = xs[:n_samples], ts[:n_samples]
+    net = sfm.Cnn(nn, 32, n_out, max_batch=64, seed=11)
+    net.fit_scale(ts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = net.train(xs, ts, batch=64, epochs=epochs, lr=1e-3, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del xs, ts
+    log(f"[bench] surrogate: {n_samples} samples, {epochs} epochs in {t_train:.1f} s, loss {losses[0]:.3f} -> "
+        f"{losses[-1]:.3f}")
+    ncell = (256, 256, 256)
+    c = W.surrogate_velocity(tuple(x + 1 for x in ncell), seed=777).astype(np.float32)
+    vel = torch.from_numpy(c).to(dev)
+    hs = sfm.Sfm(ncell, (cells, cells, cells), h, m, k, precision=sfm.SFM_PREC_FP64)
+    acc, err, secs = sfm.sfm_build_roms_surrogate(hs.ctx, net, tol, 12.0, vel, stream=stream)
+    S = len(acc)
+    out = {
+        "training_subdomains": n_samples, "m": m, "k": k, "box_cells": cells, "n_out": n_out,
+        "params": net.n_params, "epochs": epochs, "batch": 64,
+        "label_seconds": t_label, "train_seconds": t_train,
+        "train_samples_per_s": n_samples * epochs / t_train, "loss_first_epoch": float(losses[0]),
+        "loss_last_epoch": float(losses[-1]),
+        "eval_workload": "256^3 cells, 512 subdomains of unseen seeded media", "tol": tol,
+        "accepted": int(acc.sum()), "subdomains": S,
+        "ntd_error_min": float(err.min()), "ntd_error_median": float(np.median(err)),
+        "ntd_error_max": float(err.max()),
+        "lanczos_seconds": float(secs[0]), "network_seconds": float(secs[1]), "judge_seconds": float(secs[2]),
+        "network_roms_per_s": S / max(float(secs[1]), 1e-9), "lanczos_roms_per_s": S / max(float(secs[0]), 1e-9),
+    }
+    log(f"[bench] learned build of {S} subdomains: accepted {out['accepted']} at tol {tol}, NtD errors median "
+        f"{out['ntd_error_median']:.2e}; Lanczos {secs[0]:.3f} s, network {secs[1]:.4f} s, judge {secs[2]:.3f} s")
+    hs.close()
+    net.close()
+    return out
+
+
 def adjoint_probe(torch, sfm, dev, stream, nsteps: int, checkpoint_every: int = 100):
     """Misfit gradient on the gradient workload: observed traces from the medium with the Gaussian
     anomaly, ROMs of the background medium, J = 1/2 ||traces - observed||^2, dJ/d(Gamma, Gamma-hat)
@@ -388,6 +455,9 @@ def main():
     ap.add_argument("--shots", type=int, default=64,
                     help="shots stepped together through the same ROMs after the single-shot run (0: skip)")
     ap.add_argument("--shot-steps", type=int, default=100)
+    ap.add_argument("--surrogate-samples", type=int, default=20000,
+                    help="training subdomains of the learned ROMs (0: skip)")
+    ap.add_argument("--surrogate-epochs", type=int, default=6)
     ap.add_argument("--uneven-steps", type=int, default=1500,
                     help="steps of the many-shot uneven-box workload (0: skip it)")
     ap.add_argument("--adjoint-steps", type=int, default=4000,
@@ -571,6 +641,8 @@ def main():
                                    args.shot_steps, nrec, ms_per_step)
     if args.uneven_steps:
         out["many_shots_uneven"] = uneven_shots_probe(torch, sfm, dev, stream, args.uneven_steps)
+    if args.surrogate_samples:
+        out["learned_roms"] = surrogate_probe(torch, sfm, dev, stream, args.surrogate_samples, args.surrogate_epochs)
     if not args.no_finite_shift:
         out["finite_shift"] = finite_shift_probe(torch, sfm, dev, stream)
     if args.adjoint_steps:
