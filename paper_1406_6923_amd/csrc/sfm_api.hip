@@ -352,7 +352,7 @@ sfm_status sfm_create_boxes(const sfm_config* cfg, const int32_t* nbox, const in
   if (e == hipSuccess) c->U_d = static_cast<float*>(c->dalloc(nstate * sizeof(float), &e));
   if (e == hipSuccess) c->D_d = static_cast<float*>(c->dalloc(nstate * sizeof(float), &e));
   if (e == hipSuccess) c->exch_d = static_cast<float*>(c->dalloc((size_t)topo.S * c->geo.P16 * sizeof(float), &e));
-  if (e == hipSuccess) c->red_d = static_cast<double*>(c->dalloc(64 * sizeof(double), &e));
+  if (e == hipSuccess) c->red_d = static_cast<double*>(c->dalloc((kNormScratch0 + 1024) * sizeof(double), &e));
   if (e == hipSuccess) c->work_a_d = static_cast<float*>(c->dalloc(nstate * sizeof(float), &e));
   if (e == hipSuccess) c->work_b_d = static_cast<float*>(c->dalloc(nstate * sizeof(float), &e));
   if (e == hipSuccess) e = hipMemset(c->U_d, 0, nstate * sizeof(float));

@@ -167,6 +167,8 @@ hipError_t launch_pad_rows(const double* src, int64_t nrows, int p, int P16, flo
 size_t step_lds_bytes(const StepParams& prm, int precision);
 hipError_t launch_gather_rows(const double* src, const int32_t* idx, int n, int64_t width, double* dst,
                               hipStream_t st);
+// out: device double [kNormScratch0 + 1024]; out[0] = ||x||^2, the rest is scratch.
+constexpr int kNormScratch0 = 64;
 hipError_t launch_norm2(const float* x, int64_t n, double* out, hipStream_t st);
 hipError_t launch_scale(const float* x, int64_t n, const double* num, float* y, hipStream_t st);
 

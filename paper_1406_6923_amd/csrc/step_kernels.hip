@@ -173,11 +173,28 @@ __global__ void pad_rows_kernel(const double* __restrict__ src, int64_t nrows, i
 }
 
 // Sum of squares of x (FP64 accumulation), single work-group (used by the CFL estimate).
-__global__ __launch_bounds__(1024) void norm2_kernel(const float* __restrict__ x, int64_t n, double* out) {
-  __shared__ double red[1024];
+// ||x||^2 in two passes: kNormBlocks partial sums (FP64) into part, then one work-group sums them
+// in a fixed order (the result does not depend on scheduling).
+constexpr int kNormBlocks = 1024;
+
+__global__ __launch_bounds__(256) void norm2_partial_kernel(const float* __restrict__ x, int64_t n,
+                                                            double* __restrict__ part) {
+  __shared__ double red[256];
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += (double)x[i] * (double)x[i];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    acc += (double)x[i] * (double)x[i];
   red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(1024) void norm2_final_kernel(const double* __restrict__ part, int np, double* out) {
+  __shared__ double red[1024];
+  red[threadIdx.x] = (int)threadIdx.x < np ? part[threadIdx.x] : 0.0;
   __syncthreads();
   for (int o = blockDim.x / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
@@ -264,7 +281,11 @@ hipError_t launch_gather_rows(const double* src, const int32_t* idx, int n, int6
 }
 
 hipError_t launch_norm2(const float* x, int64_t n, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(norm2_kernel, dim3(1), dim3(1024), 0, st, x, n, out);
+  // out[0] receives the result; out[kNormScratch0 ..] holds the partial sums
+  hipLaunchKernelGGL(norm2_partial_kernel, dim3(kNormBlocks), dim3(256), 0, st, x, n, out + kNormScratch0);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(norm2_final_kernel, dim3(1), dim3(1024), 0, st, out + kNormScratch0, kNormBlocks, out);
   return hipGetLastError();
 }
 
