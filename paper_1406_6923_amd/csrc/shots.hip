@@ -125,13 +125,15 @@ template <typename T>
 __device__ __forceinline__ void expand_block(T* __restrict__ G, int PP, int P, const uint32_t* __restrict__ wmap,
                                              int nq, int tid, int nthr, const ShotBuf<T>& buf) {
   constexpr int kW = ShotMath<T>::kWords;
+  typedef uint32_t MapLoad __attribute__((ext_vector_type(kW)));   // the map entries of one load
 #pragma unroll
   for (int i = 0; i < ShotMath<T>::kPrefetch; ++i) {
     const int qi = tid + i * nthr;
     if (qi < nq) {
+      const MapLoad ms = reinterpret_cast<const MapLoad*>(wmap)[qi];
 #pragma unroll
       for (int e = 0; e < kW; ++e) {
-        const uint32_t m = wmap[(size_t)qi * kW + e];
+        const uint32_t m = ms[e];
         const int r = (int)(m >> 16), c = (int)(m & 0xffff);
         if (r < P) {
           const T v = buf[i][e];
