@@ -33,7 +33,16 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kConv = 4;
 constexpr int kBM = 64, kBN = 64, kBK = 16, kThreads = 256;
-constexpr int64_t kSplitK = 8192;     // K per work-group slice of the long-K products
+constexpr int64_t kSplitTarget = 2048;   // work-groups a split-K product aims for
+
+// K per work-group slice of a product whose M x N tiles alone do not fill the device: enough
+// slices for about kSplitTarget work-groups, at least 256 per slice (a multiple of the K step).
+int64_t split_k(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  if (tiles >= kSplitTarget) return K;
+  const int64_t want = (K * tiles + kSplitTarget - 1) / kSplitTarget;
+  return std::min<int64_t>(K, std::max<int64_t>(256, (want + 15) / 16 * 16));
+}
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
@@ -397,10 +406,12 @@ int64_t partial_len(const sfm_cnn_s& c, int B) {
   for (int l = 0; l < kConv; ++l) {
     const int ci = l == 0 ? 1 : c.ch;
     const int64_t K = (int64_t)B * c.nodes[l + 1] * c.nodes[l + 1] * c.nodes[l + 1];
-    need = std::max<int64_t>(need, (K + kSplitK - 1) / kSplitK * c.ch * 27 * ci);
+    const int64_t ks = split_k(c.ch, 27LL * ci, K);
+    need = std::max<int64_t>(need, (K + ks - 1) / ks * c.ch * 27 * ci);
     need = std::max<int64_t>(need, (int64_t)4096 * c.ch);               // column sums
   }
-  need = std::max<int64_t>(need, ((int64_t)c.n_out + kSplitK - 1) / kSplitK * B * c.feat);
+  const int64_t kd = split_k(B, c.feat, c.n_out);
+  need = std::max<int64_t>(need, ((int64_t)c.n_out + kd - 1) / kd * B * c.feat);
   return need;
 }
 
@@ -471,8 +482,10 @@ sfm_status backward_pass(sfm_cnn net, const float* dy, int B, float* g, hipStrea
     d.dy = dy;
     d.Wd = net->params + net->off_Wd;
     d.part = net->part;
-    CNN_TRY(launch_gemm(d, kSplitK, st));
-    const int slices = (int)((d.K + kSplitK - 1) / kSplitK);
+    const int64_t kd = split_k(d.M, d.N, d.K);
+    const int slices = (int)((d.K + kd - 1) / kd);
+    if ((int64_t)slices * d.M * d.N > net->part_len) return net->fail(SFM_EINVAL, "partial-sum buffer too small");
+    CNN_TRY(launch_gemm(d, kd, st));
     hipLaunchKernelGGL(sum_slices_kernel, dim3(blocks_for((int64_t)B * F)), dim3(256), 0, st, net->part, slices,
                        (int64_t)B * F, net->dact[kConv]);
     CNN_TRY(hipGetLastError());
@@ -491,8 +504,10 @@ sfm_status backward_pass(sfm_cnn net, const float* dy, int B, float* g, hipStrea
     w.gi = Grid3{n};
     w.go = Grid3{m};
     w.ci = ci;
-    CNN_TRY(launch_gemm(w, kSplitK, st));
-    const int slices = (int)((rows + kSplitK - 1) / kSplitK);
+    const int64_t kw = split_k(w.M, w.N, w.K);
+    const int slices = (int)((rows + kw - 1) / kw);
+    if ((int64_t)slices * w.M * w.N > net->part_len) return net->fail(SFM_EINVAL, "partial-sum buffer too small");
+    CNN_TRY(launch_gemm(w, kw, st));
     hipLaunchKernelGGL(sum_slices_kernel, dim3(blocks_for(w.M * w.N)), dim3(256), 0, st, net->part, slices,
                        w.M * w.N, g + net->off_W[l]);
     CNN_TRY(hipGetLastError());
@@ -570,7 +585,8 @@ sfm_status sfm_cnn_create(int32_t n_in, int32_t channels, int32_t n_out, int32_t
   net->dy = F((int64_t)max_batch * n_out);
   net->out_mean = F(n_out);
   net->out_sd = F(n_out);
-  net->part_len = partial_len(*net, max_batch);
+  net->part_len = 0;
+  for (int b = 1; b <= max_batch; ++b) net->part_len = std::max<int64_t>(net->part_len, partial_len(*net, b));
   net->part = F(net->part_len);
   net->loss_part = static_cast<double*>(net->alloc(4096 * sizeof(double), &e));
   net->idx_d = static_cast<int32_t*>(net->alloc((size_t)max_batch * sizeof(int32_t), &e));
