@@ -247,11 +247,10 @@ def uneven_shots_probe(torch, sfm, dev, stream, nsteps: int, nshot: int = 64, co
     ks = W.level_choices(S, seed=W.SHOTS_LEVEL_SEED)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sfm.sfm_build_roms(h.ctx, vel, srcs, rec, stream=stream)
+    sfm.sfm_build_roms_levels(h.ctx, ks, vel, srcs, rec, stream=stream)   # k_s Lanczos steps per subdomain
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     del vel
-    sfm.sfm_set_levels(h.ctx, ks)
     dt = 0.9 * sfm.sfm_cfl_dt(h.ctx, 200, stream=stream)
     ratio = dt / (0.9 * cfg.h / (math.sqrt(3.0) * c_max))
     sfm.sfm_shots_init(h.ctx, nshot, np.arange(nshot), stream=stream)
@@ -301,7 +300,7 @@ def uneven_shots_probe(torch, sfm, dev, stream, nsteps: int, nshot: int = 64, co
     out = {
         "workload": cfg.name, "subdomains": S, "box_cells": box,
         "box_shapes": len({(a, b, c_) for a in box[0] for b in box[1] for c_ in box[2]}),
-        "m": cfg.m, "k_built": cfg.k, "k_levels": sorted(set(int(x) for x in ks)), "k_mean": float(ks.mean()),
+        "m": cfg.m, "k_max": cfg.k, "k_levels": sorted(set(int(x) for x in ks)), "k_mean": float(ks.mean()),
         "nshot": nshot, "steps": nsteps, "receivers": len(rec), "dt_ratio": ratio,
         "build_seconds": t_build, "builds_per_s": S / t_build,
         "ms_per_step": wall / nsteps * 1e3, "graph_replays": replays,

@@ -243,6 +243,15 @@ sfm_status sfm_set_state(sfm_ctx ctx, const float* u_now, const float* u_incr, i
  * previous table stays). */
 sfm_status sfm_set_levels(sfm_ctx ctx, const int32_t* k_per_sub);
 
+/* As sfm_build_roms (sigma = inf) with a ROM size of its own per subdomain: block Lanczos and the
+ * S-fraction recursion run k_per_sub[s] steps on subdomain s (host int32 [S], 2 <= k_s <= k), its
+ * later levels are stored as zero, and the level table is installed as by sfm_set_levels.  The
+ * build batches subdomains of one box shape and one k_s together, so the cost follows the sizes
+ * actually used.  Errors as sfm_build_roms and sfm_set_levels. */
+sfm_status sfm_build_roms_levels(sfm_ctx ctx, const int32_t* k_per_sub, const float* vel_dev, int32_t nsrc,
+                                 const int32_t* src_ijk, int32_t nrec, const int32_t* rec_ijk, const float* u0_dev,
+                                 const float* v0_dev, void* stream);
+
 /* The levels in use per subdomain, host int32 [S] (k everywhere without a table). */
 sfm_status sfm_get_levels(sfm_ctx ctx, int32_t* k_per_sub);
 

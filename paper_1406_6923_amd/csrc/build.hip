@@ -512,8 +512,8 @@ __global__ void scatter_blocks_kernel(const double* __restrict__ src, int64_t ss
 }
 
 // Source vectors s_j = G_j z_j and receiver rows r_j = z_j^T G_j^{-1} with z = M^{-1/2} Z^T e_node.
-__global__ void project_points_kernel(const double* __restrict__ Z, const double* __restrict__ S, int64_t N, int k, int p,
-                                      const double* __restrict__ G, const double* __restrict__ Gi, int64_t sg,
+__global__ void project_points_kernel(const double* __restrict__ Z, const double* __restrict__ S, int64_t N, int k, int kb,
+                                      int p, const double* __restrict__ G, const double* __restrict__ Gi, int64_t sg,
                                       const int32_t* __restrict__ pb, const int32_t* __restrict__ pnode,
                                       const int32_t* __restrict__ pid, int npts, int mode, double* __restrict__ out) {
   const int64_t total = (int64_t)npts * k * p;
@@ -523,6 +523,10 @@ __global__ void project_points_kernel(const double* __restrict__ Z, const double
     const int64_t pj = idx / p;
     const int j = (int)(pj % k);
     const int pt = (int)(pj / k);
+    if (j >= kb) {                      // a level past this batch's ROM size
+      out[((int64_t)pid[pt] * k + j) * p + e] = 0.0;
+      continue;
+    }
     const int b = pb[pt];
     const int64_t n = pnode[pt];
     const double sn = S[(int64_t)b * N + n];
@@ -557,18 +561,20 @@ __global__ void project_field_kernel(BoxGeo g, const double* __restrict__ Z, con
 }
 
 // U_j = G_j y_j into the FP32 state layout [S][k][P16].
-__global__ void apply_g_kernel(const double* __restrict__ y, const double* __restrict__ G, int64_t sg, int k, int p,
-                               int P16, int nb, const int32_t* __restrict__ ids, float* __restrict__ U) {
+__global__ void apply_g_kernel(const double* __restrict__ y, const double* __restrict__ G, int64_t sg, int k, int kb,
+                               int p, int P16, int nb, const int32_t* __restrict__ ids, float* __restrict__ U) {
   const int64_t total = (int64_t)nb * k * p;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     const int e = (int)(idx % p);
     const int64_t bj = idx / p;
     const int j = (int)(bj % k);
     const int b = (int)(bj / k);
-    const double* M = G + b * sg + (int64_t)j * p * p;
-    const double* yj = y + (int64_t)b * k * p + (int64_t)j * p;
     double acc = 0.0;
-    for (int c = 0; c < p; ++c) acc += M[e + (int64_t)c * p] * yj[c];
+    if (j < kb) {                       // levels past this batch's ROM size stay zero
+      const double* M = G + b * sg + (int64_t)j * p * p;
+      const double* yj = y + (int64_t)b * k * p + (int64_t)j * p;
+      for (int c = 0; c < p; ++c) acc += M[e + (int64_t)c * p] * yj[c];
+    }
     U[(((int64_t)ids[b]) * k + j) * P16 + e] = (float)acc;
   }
 }
@@ -648,9 +654,11 @@ struct ShiftSpec {
 
 constexpr int kCgCheck = 10;   // CG iterations between convergence checks on the host
 
+// levels: optional [S] ROM size per subdomain (block Lanczos and the S-fraction run levels[s]
+// steps there; the blocks and projections of later levels are zero).  sigma = inf only.
 sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, int32_t nsrc, const int32_t* src_ijk,
                       int32_t nrec, const int32_t* rec_ijk, const float* u0_dev, const float* v0_dev,
-                      int32_t* cg_iters_out, void* stream) {
+                      int32_t* cg_iters_out, void* stream, const int32_t* levels = nullptr) {
   c->err.clear();
   if (!vel_dev) return c->fail(SFM_EINVAL, "vel_dev is NULL");
   const bool finite = std::isfinite(shift.sigma);
@@ -679,6 +687,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
   hipError_t e = hipSuccess;
   c->coef64_d = static_cast<double*>(c->dalloc((size_t)S * 2 * k * pp * sizeof(double), &e));
   if (!c->coef64_d) return c->fail(SFM_ENOMEM, "FP64 coefficients: out of device memory");
+  if (levels) B_TRY_HIP(hipMemsetAsync(c->coef64_d, 0, (size_t)S * 2 * k * pp * sizeof(double), st));
   if (nsrc > 0) c->src_vec64_d = static_cast<double*>(c->dalloc((size_t)nsrc * kp * sizeof(double), &e));
   if (nrec > 0) c->rec_rows64_d = static_cast<double*>(c->dalloc((size_t)nrec * kp * sizeof(double), &e));
   const bool ic = u0_dev || v0_dev;
@@ -760,7 +769,8 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
   auto shape_key = [&](int s) {
     int w[3];
     t.cells(s, w);
-    return ((int64_t)w[2] * (t.ncell[1] + 1) + w[1]) * (t.ncell[0] + 1) + w[0];
+    const int64_t kb = levels ? levels[s] : k;   // one ROM size per batch too
+    return ((kb * (t.ncell[2] + 1) + w[2]) * (t.ncell[1] + 1) + w[1]) * (t.ncell[0] + 1) + w[0];
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return shape_key(a) < shape_key(b); });
   std::vector<int32_t> batch_of(S), pos_of(S);
@@ -776,6 +786,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
       pos_of[ids[b]] = b;
     }
     const int bidx = nbatch_done++;
+    const int kb = levels ? levels[ids[0]] : k;    // Lanczos steps and S-fraction levels of this batch
     int w[3];
     t.cells(ids[0], w);
     const BoxGeo g{{w[0], w[1], w[2]}, {w[0] + 1, w[1] + 1, w[2] + 1}, t.m, t.m1, t.m2, p, c->cfg.h};
@@ -830,7 +841,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
     auto lanczos = [&](double* Zb, int64_t rows, int nsteps, const double* thrp, auto&& apply) -> sfm_status {
       const int64_t sZb = rows * kp;
       for (int jj = 0; jj < nsteps; ++jj) {
-        const bool last = jj + 1 == k;
+        const bool last = jj + 1 == kb;
         double* W = last ? Wl : Zb + (int64_t)(jj + 1) * p;
         const int ldw = last ? p : kp;
         const int64_t sW = last ? rows * p : sZb;
@@ -874,7 +885,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
 
     if (!finite) {
       // polynomial space: block Lanczos on (A_+, F)
-      rc = lanczos(Z, N, k, thr, [&](int jj, double* W, int ldw, int64_t sW) -> sfm_status {
+      rc = lanczos(Z, N, kb, thr, [&](int jj, double* W, int ldw, int64_t sW) -> sfm_status {
         B_LAUNCH(stencil_kernel, (int64_t)nb * N * p, g, Sd, N, nb, Z + (int64_t)jj * p, kp, sZ, W, ldw, sW, 0.0);
         return SFM_OK;
       });
@@ -961,7 +972,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
     const int64_t sk = (int64_t)k * pp;
     B_LAUNCH(diag_kernel, (int64_t)nb * pp, Hb, p, nb, G, sk, 0);
     B_LAUNCH(diag_kernel, (int64_t)nb * pp, Hb, p, nb, Gi, sk, 1);
-    for (int jj = 0; jj < k; ++jj) {
+    for (int jj = 0; jj < kb; ++jj) {
       double* Gj = G + jj * pp;
       double* Gij = Gi + jj * pp;
       double* Gamj = Gam + jj * pp;
@@ -977,7 +988,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
         B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, p, p, &one, Gij, p, sk, T1, p, pp, &mone, Gamj, p, sk, nb));
       }
       B_LAUNCH(symmetrize_kernel, (int64_t)nb * pp, Gamj, p, sk, nb);
-      if (jj + 1 == k) break;
+      if (jj + 1 == kb) break;
       // Cholesky of Gamma_j (must be SPD for j < k)
       B_LAUNCH(copy_blocks_kernel, (int64_t)nb * pp, Gamj, sk, L1, pp, pp, nb, 1.0);
       hipLaunchKernelGGL(cholesky_kernel, dim3(nb), dim3(256), 0, st, L1, p, pp, (const double*)nullptr, 0.0, flags);
@@ -997,8 +1008,8 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
                                                p, p, &mone, Btn, p, sk, Gin, p, sk, nb));
     }
     // coefficients to the FP64 store [S][2][k][p][p] (symmetric: column-major = row-major)
-    B_LAUNCH(scatter_blocks_kernel, (int64_t)nb * sk, Gam, sk, c->coef64_d, 2 * sk, sk, nb, ids_d);
-    B_LAUNCH(scatter_blocks_kernel, (int64_t)nb * sk, Gh, sk, c->coef64_d + sk, 2 * sk, sk, nb, ids_d);
+    B_LAUNCH(scatter_blocks_kernel, (int64_t)nb * kb * pp, Gam, sk, c->coef64_d, 2 * sk, (int64_t)kb * pp, nb, ids_d);
+    B_LAUNCH(scatter_blocks_kernel, (int64_t)nb * kb * pp, Gh, sk, c->coef64_d + sk, 2 * sk, (int64_t)kb * pp, nb, ids_d);
 
     // a4: projections of the points of this batch
     for (int mode = 0; mode < 2; ++mode) {
@@ -1018,7 +1029,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
       packed.insert(packed.end(), pn.begin(), pn.end());
       packed.insert(packed.end(), pid.begin(), pid.end());
       B_TRY_HIP(hipMemcpyAsync(pts, packed.data(), packed.size() * 4, hipMemcpyHostToDevice, st));
-      B_LAUNCH(project_points_kernel, (int64_t)npts * kp, Z, Sd, N, k, p, G, Gi, sk, pts, pts + npts, pts + 2 * npts,
+      B_LAUNCH(project_points_kernel, (int64_t)npts * kp, Z, Sd, N, k, kb, p, G, Gi, sk, pts, pts + npts, pts + 2 * npts,
                npts, mode, mode == 0 ? c->src_vec64_d : c->rec_rows64_d);
       B_TRY_HIP(hipStreamSynchronize(st));   // pts is reused
     }
@@ -1030,7 +1041,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
         hipLaunchKernelGGL(project_field_kernel, dim3((nb * kp + 255) / 256), dim3(256), 0, st, g, Z, Sd, N, kp, nb,
                            fields[fi], t.ncell[0], t.ncell[1], org_d, ybuf);
         B_TRY_HIP(hipGetLastError());
-        B_LAUNCH(apply_g_kernel, (int64_t)nb * kp, ybuf, G, sk, k, p, P16, nb, ids_d, outs[fi]);
+        B_LAUNCH(apply_g_kernel, (int64_t)nb * kp, ybuf, G, sk, k, kb, p, P16, nb, ids_d, outs[fi]);
       }
     }
     // breakdown flags of this batch
@@ -1081,6 +1092,24 @@ extern "C" sfm_status sfm_build_roms(sfm_ctx c, const float* vel_dev, int32_t ns
   if (!c) return SFM_EINVAL;
   const ShiftSpec spec{INFINITY, 0.0, 0};
   const sfm_status rc = build_roms(c, spec, vel_dev, nsrc, src_ijk, nrec, rec_ijk, u0_dev, v0_dev, nullptr, stream);
+  if (rc != SFM_OK) release_roms(c);
+  return rc;
+}
+
+extern "C" sfm_status sfm_build_roms_levels(sfm_ctx c, const int32_t* k_per_sub, const float* vel_dev, int32_t nsrc,
+                                            const int32_t* src_ijk, int32_t nrec, const int32_t* rec_ijk,
+                                            const float* u0_dev, const float* v0_dev, void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!k_per_sub) return c->fail(SFM_EINVAL, "k_per_sub is NULL");
+  const Topology& t = c->topo;
+  for (int s = 0; s < t.S; ++s)
+    if (k_per_sub[s] < 2 || k_per_sub[s] > t.k)
+      return c->fail(SFM_EINVAL, "subdomain " + std::to_string(s) + ": levels " + std::to_string(k_per_sub[s]) +
+                                     " outside [2, " + std::to_string(t.k) + "]");
+  const ShiftSpec spec{INFINITY, 0.0, 0};
+  sfm_status rc = build_roms(c, spec, vel_dev, nsrc, src_ijk, nrec, rec_ijk, u0_dev, v0_dev, nullptr, stream, k_per_sub);
+  if (rc == SFM_OK) rc = sfm_set_levels(c, k_per_sub);
   if (rc != SFM_OK) release_roms(c);
   return rc;
 }

@@ -103,6 +103,7 @@ SIGNATURES = {
     "sfm_get_state": (_I32, [_VP, _VP, _VP, ctypes.POINTER(_I64)]),
     "sfm_set_state": (_I32, [_VP, _VP, _VP, _I64]),
     "sfm_set_levels": (_I32, [_VP, _VP]),
+    "sfm_build_roms_levels": (_I32, [_VP, _VP, _VP, _I32, _VP, _I32, _VP, _VP, _VP, _VP]),
     "sfm_get_levels": (_I32, [_VP, _VP]),
     "sfm_fdtd_run": (_I32, [_VP, _D, _VP, _D, _I32, _I32, _VP, _VP, _I32, _VP, _VP, _I64, ctypes.POINTER(_D), _VP]),
     "sfm_fdtd_last_error": (ctypes.c_char_p, []),
@@ -366,6 +367,15 @@ def sfm_set_levels(ctx: int, k_per_sub=None) -> None:
     """Per-subdomain ROM levels (int per subdomain, 2..k); None restores k everywhere."""
     ks = None if k_per_sub is None else _host(np.asarray(k_per_sub), np.int32)
     _check(ctx, load_library().sfm_set_levels(ctx, _ptr(ks)))
+
+
+def sfm_build_roms_levels(ctx: int, k_per_sub, vel, src_ijk=None, rec_ijk=None, u0=None, v0=None,
+                          stream=None) -> None:
+    ks = _host(np.asarray(k_per_sub), np.int32)
+    src = _host(np.zeros((0, 3)) if src_ijk is None else src_ijk, np.int32).reshape(-1, 3)
+    rec = _host(np.zeros((0, 3)) if rec_ijk is None else rec_ijk, np.int32).reshape(-1, 3)
+    _check(ctx, load_library().sfm_build_roms_levels(ctx, _ptr(ks), _dev(vel), len(src), _ptr(src), len(rec),
+                                                     _ptr(rec), _dev(u0), _dev(v0), _stream(stream)))
 
 
 def sfm_get_levels(ctx: int) -> np.ndarray:

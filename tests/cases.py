@@ -22,7 +22,7 @@ def case_config(name: str) -> W.Workload:
     elif name == "uneven":
         # a tensor product of boxes of uneven size: 2 x 2 x 2 boxes from (12, 16) x (8, 12) x (10, 8)
         cfg = W.Workload(name="uneven_28x20x18", ncell=(28, 20, 18), sub_cells=((12, 16), (8, 12), (10, 8)),
-                         h=10.0, m=4, k=5, f_peak=15.0, nsteps=300, src=((3, 11, 4),), rec_grid=(10, 8),
+                         h=10.0, m=4, k=5, f_peak=15.0, nsteps=300, src=((3, 3, 4),), rec_grid=(10, 8),
                          velocity="layered_inclusions", seed=9)
     elif name == "mid":
         # The large workload's subdomain size and ROM sizes (33^3 nodes, m = 16, k = 16) on 2 x 2 x 1.

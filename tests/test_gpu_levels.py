@@ -169,3 +169,45 @@ def test_levels_errors_and_reset():
     sfm.sfm_load_roms(h.ctx, gam, hat, cfg.sources(), src, cfg.receivers(), rec)   # a new load clears it
     assert (sfm.sfm_get_levels(h.ctx) == cfg.k).all()
     h.close()
+
+
+@pytest.mark.parametrize("name, nsteps", [("small", 500), ("uneven", 300)])
+def test_levels_build_matches_oracle(name, nsteps):
+    """The device build run k_s steps per subdomain: blocks within the per-level FP64 tolerance of
+    the oracle's k_s-step ROMs, zero past k_s; projections 1e-7; traces 1e-5."""
+    from paper_1406_6923_amd import sfm
+    from tests.cases import case_level_tolerance
+    cfg, c, subs, roms, cs = oracle_case(name)
+    cfg, subs, roms_ks, cs_ks, ks = mixed_level_case(name)
+    print(f"[case] levels build {name}: {ks.tolist()}", flush=True)
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
+    sfm.sfm_build_roms_levels(h.ctx, ks, torch.from_numpy(c.astype(np.float32)).cuda(), cfg.sources(),
+                              cfg.receivers())
+    assert np.array_equal(sfm.sfm_get_levels(h.ctx), ks)
+    gam, hat = sfm.sfm_export_roms(h.ctx)
+    tol = case_level_tolerance(name)
+    for a, r in enumerate(roms_ks):
+        for j in range(cfg.k):
+            if j >= ks[a]:
+                assert not gam[a, j].any() and not hat[a, j].any()
+                continue
+            for got, ref in ((gam[a, j], r.sf.gamma[j]), (hat[a, j], r.sf.gamma_hat[j])):
+                assert np.abs(got - ref).max() / np.abs(ref).max() < tol[j], (a, j)
+    src, rec = sfm.sfm_export_projections(h.ctx)
+    ref_src = pad_levels([v for (_, v, _) in cs_ks.sources], cfg.k)
+    ref_rec = pad_levels([row for (_, row) in cs_ks.receivers], cfg.k)
+    for got, ref in ((src, ref_src), (rec, ref_rec)):
+        if np.linalg.norm(ref) == 0:           # a point deeper than a k_s-level ROM reaches
+            assert not got.any()
+        else:
+            assert rel_l2(got, ref) < 1e-7
+    dt = 0.9 * cs_ks.cfl_dt()
+    wav = W.ricker(cfg.f_peak, dt, nsteps)[:, None]
+    ref = cs_ks.run(dt, wav)
+    tr = torch.zeros((len(cs_ks.receivers), nsteps), dtype=torch.float32, device="cuda")
+    sfm.sfm_step(h.ctx, nsteps, dt, torch.tensor(wav, dtype=torch.float32, device="cuda"), tr)
+    torch.cuda.synchronize()
+    err = rel_l2(tr.cpu().numpy(), ref)
+    print(f"{name}: levels build, traces rel-L2 {err:.2e}")
+    assert err < 1e-5
+    h.close()
