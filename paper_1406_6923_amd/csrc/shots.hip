@@ -106,28 +106,29 @@ __device__ __forceinline__ size_t block_word(const ShotParams& prm, int s, int b
   return (size_t)s * prm.words_per_sub + (size_t)b * prm.words_per_block;
 }
 
-template <typename T>
-using ShotBuf = typename ShotMath<T>::Load[ShotMath<T>::kPrefetch];
+template <typename T, int kPF = ShotMath<T>::kPrefetch>
+using ShotBuf = typename ShotMath<T>::Load[kPF];
 
-template <typename T>
-__device__ __forceinline__ void prefetch_block(const T* __restrict__ blk, int nq, int tid, int nthr, ShotBuf<T>& buf) {
+template <typename T, int kPF>
+__device__ __forceinline__ void prefetch_block(const T* __restrict__ blk, int nq, int tid, int nthr,
+                                               ShotBuf<T, kPF>& buf) {
   typedef typename ShotMath<T>::Load L;
   const L* q = reinterpret_cast<const L*>(blk);
 #pragma unroll
-  for (int i = 0; i < ShotMath<T>::kPrefetch; ++i) {
+  for (int i = 0; i < kPF; ++i) {
     const int qi = tid + i * nthr;
     if (qi < nq) buf[i] = __builtin_nontemporal_load(q + qi);
   }
 }
 
 // Dense symmetric copy of the block in LDS: word (r, c) goes to G[r][c] and G[c][r].
-template <typename T>
+template <typename T, int kPF>
 __device__ __forceinline__ void expand_block(T* __restrict__ G, int PP, int P, const uint32_t* __restrict__ wmap,
-                                             int nq, int tid, int nthr, const ShotBuf<T>& buf) {
+                                             int nq, int tid, int nthr, const ShotBuf<T, kPF>& buf) {
   constexpr int kW = ShotMath<T>::kWords;
   typedef uint32_t MapLoad __attribute__((ext_vector_type(kW)));   // the map entries of one load
 #pragma unroll
-  for (int i = 0; i < ShotMath<T>::kPrefetch; ++i) {
+  for (int i = 0; i < kPF; ++i) {
     const int qi = tid + i * nthr;
     if (qi < nq) {
       const MapLoad ms = reinterpret_cast<const MapLoad*>(wmap)[qi];
@@ -172,85 +173,104 @@ __device__ __forceinline__ void block_product(const T* __restrict__ G, const T* 
 // kMinWaves: waves per SIMD the register allocation must allow (2: one work-group per CU, no
 // spills; 3: two work-groups per CU at 6m = 96, some registers spilled).  sfm_shots_init times
 // every instantiation and keeps the fastest.
-template <typename T, int kMinWaves, int kMaxNtWG = kMaxShotP16 / kTile>
-__global__ __launch_bounds__(128 * kMaxNtWG, kMinWaves) void shots_main_kernel(ShotParams prm) {
+// kCols = 64: one work-group per subdomain, two waves per row tile (32 shots each).  kCols = 32:
+// two work-groups per subdomain (shots 0..31 and 32..63), one wave per row tile; the half-size
+// Xt lets two work-groups share a CU where the 64-shot one needs most of its LDS (FP64 blocks).
+// Work-groups g and g + 8 of every 16 take the two halves of one subdomain: the same XCD (and L2)
+// reads the subdomain's blocks for both.  kPF: 16-byte prefetch loads per thread.
+template <typename T, int kMinWaves, int kMaxNtWG = kMaxShotP16 / kTile, int kCols = 64,
+          int kPF = ShotMath<T>::kPrefetch>
+__global__ __launch_bounds__((kCols == 64 ? 128 : 64) * kMaxNtWG, kMinWaves) void shots_main_kernel(ShotParams prm) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   typedef typename ShotMath<T>::Acc A4;
   const int P = prm.P, PP = prm.PP, k = prm.k;
-  T* G = reinterpret_cast<T*>(lds_raw);  // [P][PP]   dense block
-  T* Xt = G + P * PP;                    // [64][PP]  block input, then a_j, transposed
+  T* G = reinterpret_cast<T*>(lds_raw);  // [P][PP]      dense block
+  T* Xt = G + P * PP;                    // [kCols][PP]  block input, then a_j, transposed
   const T* tiles = static_cast<const T*>(prm.tiles);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index: uniform
-  const int nw = nthr >> 6;              // = 2 P / 16: two waves per 16-row tile
-  const int I = w >> 1, sh = 2 * (w & 1);   // row tile, first of the wave's two shot tiles
+  const int nw = nthr >> 6;              // 2 P / 16 (kCols = 64) or P / 16 waves
+  const int I = kCols == 64 ? w >> 1 : w;              // row tile
+  const int sh = kCols == 64 ? 2 * (w & 1) : 0;        // first of the wave's two shot tiles (local)
   const int lane = tid & 63, g = lane >> 4, li = lane & 15;
-  const int s = blockIdx.x;
+  int s = blockIdx.x, c0 = 0;
+  if (kCols == 32) {
+    const int grp = blockIdx.x >> 4, r = blockIdx.x & 15;
+    s = grp * 8 + (r & 7);
+    c0 = (r >> 3) * 32;
+    if (s >= prm.S) return;              // the whole work-group: the last group of 8 is partial
+  }
   const int nq = (int)(prm.words_per_block / ShotMath<T>::kWords);
   const size_t sbase = (size_t)s * k * P * kShotCols;
   const int ns0 = prm.src_off ? prm.src_off[s] : 0;
   const int ns1 = prm.src_off ? prm.src_off[s + 1] : 0;
   const int ks = prm.k_of ? prm.k_of[s] : k;   // this ROM's levels (>= 2); the others stay zero
-  // X layout: this thread owns shot `lane` of rows w + i nw (i < 8) of every level; its global
-  // accesses are 256-byte rows of 64 shots at a wave-uniform row offset.
-  float* const Uw = prm.U + sbase + (size_t)w * kShotCols;
-  float* const Dw = prm.D + sbase + (size_t)w * kShotCols;
-  auto xrow = [&](int j, int i) { return ((j * P + i * nw) * kShotCols); };
+  // X layout: this thread owns column col of rows (w + i nw) * (64 / kCols) + lane / kCols (i < 8)
+  // of every level; a wave's global accesses are whole 64-shot rows (kCols = 64) or two 32-shot
+  // halves of consecutive rows, at a wave-uniform offset.
+  constexpr int kRowMul = 64 / kCols;
+  const int xl = lane % kCols;           // local column (shot c0 + xl)
+  const int ro = lane / kCols;
+  float* const Uw = prm.U + sbase + (size_t)(w * kRowMul + ro) * kShotCols + c0 + xl;
+  float* const Dw = prm.D + sbase + (size_t)(w * kRowMul + ro) * kShotCols + c0 + xl;
+  auto xrow = [&](int j, int i) { return ((j * P + i * nw * kRowMul) * kShotCols); };
+  auto trow = [&](int i) { return (w + i * nw) * kRowMul + ro; };   // row of the thread's i-th value
   constexpr int R = kShotRowsPerThread;
   float Ua[R], Ub[R], Un[R], Dr[R];      // U_j, U_{j+1}, U_{j+2}, D_j
   A4 phip[2];                            // phi_{j-1} in the MFMA output layout
   A4 acc[2];
-  ShotBuf<T> buf;
-  prefetch_block<T>(tiles + block_word(prm, s, 0), nq, tid, nthr, buf);
+  ShotBuf<T, kPF> buf;
+  prefetch_block<T, kPF>(tiles + block_word(prm, s, 0), nq, tid, nthr, buf);
 #pragma unroll
   for (int i = 0; i < R; ++i) {
-    Ua[i] = Uw[xrow(0, i) + lane];
-    Ub[i] = Uw[xrow(1, i) + lane];
+    Ua[i] = Uw[xrow(0, i)];
+    Ub[i] = Uw[xrow(1, i)];
   }
   const int rb = 16 * I;                 // first row of the wave's row tile
   for (int j = 0; j < ks; ++j) {
     __syncthreads();                                       // G, Xt free
-    expand_block<T>(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma_j
+    expand_block<T, kPF>(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma_j
 #pragma unroll
-    for (int i = 0; i < R; ++i) Xt[lane * PP + w + i * nw] = (T)Ub[i] - (T)Ua[i];   // U_{j+1} - U_j
+    for (int i = 0; i < R; ++i) Xt[xl * PP + trow(i)] = (T)Ub[i] - (T)Ua[i];   // U_{j+1} - U_j
     __syncthreads();
     if (j >= 1) {
-      prefetch_block<T>(tiles + block_word(prm, s, k + j - 1), nq, tid, nthr, buf);   // Gamma-hat_j
+      prefetch_block<T, kPF>(tiles + block_word(prm, s, k + j - 1), nq, tid, nthr, buf);   // Gamma-hat_j
 #pragma unroll
-      for (int i = 0; i < R; ++i) Dr[i] = Dw[xrow(j, i) + lane];
+      for (int i = 0; i < R; ++i) Dr[i] = Dw[xrow(j, i)];
     } else {
-      prefetch_block<T>(tiles + block_word(prm, s, 1), nq, tid, nthr, buf);           // Gamma_2
+      prefetch_block<T, kPF>(tiles + block_word(prm, s, 1), nq, tid, nthr, buf);           // Gamma_2
     }
 #pragma unroll
-    for (int i = 0; i < R; ++i) Un[i] = (j + 2 < ks) ? Uw[xrow(j + 2, i) + lane] : 0.f;
+    for (int i = 0; i < R; ++i) Un[i] = (j + 2 < ks) ? Uw[xrow(j + 2, i)] : 0.f;
     block_product<T>(G, Xt, PP, P, I, sh, g, li, acc);     // phi_j
     __syncthreads();                                       // every wave done with G, Xt
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int n = 16 * (sh + h) + li;
+      const int n = 16 * (sh + h) + li;   // local column
       if (j == 0) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          prm.exch[((size_t)s * P + rb + ShotMath<T>::out_row(g, v)) * kShotCols + n] = (float)acc[h][v];  // step 2.1
+          prm.exch[((size_t)s * P + rb + ShotMath<T>::out_row(g, v)) * kShotCols + c0 + n] = (float)acc[h][v];  // 2.1
       } else {
         store_rows<T>(Xt + n * PP + rb, g, acc[h] - phip[h]);   // phi_j - phi_{j-1}
       }
       phip[h] = acc[h];
     }
     if (j >= 1) {
-      expand_block<T>(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma-hat_j
+      expand_block<T, kPF>(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma-hat_j
       __syncthreads();
-      if (j + 1 < ks) prefetch_block<T>(tiles + block_word(prm, s, j + 1), nq, tid, nthr, buf);  // Gamma_{j+1}
+      if (j + 1 < ks) prefetch_block<T, kPF>(tiles + block_word(prm, s, j + 1), nq, tid, nthr, buf);  // Gamma_{j+1}
       block_product<T>(G, Xt, PP, P, I, sh, g, li, acc);     // a_j
       // sources of this subdomain: a_j += f_n(t) s_j for the shot n each source drives
       for (int q = ns0; q < ns1; ++q) {
         const int src = prm.src_ids[q];
         const int n = prm.src_shot[src];
-        if (n < 0 || (n & 15) != li || (n >> 4) < sh || (n >> 4) > sh + 1) continue;
+        const int nl = n - c0;               // local column of the shot (outside: another half)
+        if (n < 0 || nl < 0 || nl >= kCols || (nl & 15) != li || (nl >> 4) < sh || (nl >> 4) > sh + 1) continue;
         const int64_t stp = prm.step + (prm.step_base ? *prm.step_base : 0);
         const float wv = prm.wavelet[stp * prm.nshot + n];
         const float* sv = prm.src_vec + ((size_t)src * k + j) * P + rb;
-        const int h = (n >> 4) - sh;
+        const int h = (nl >> 4) - sh;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const T x = (T)sv[ShotMath<T>::out_row(g, v)];
@@ -266,10 +286,10 @@ __global__ __launch_bounds__(128 * kMaxNtWG, kMinWaves) void shots_main_kernel(S
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const float d = std::is_same<T, float>::value
-                            ? fmaf(prm.dt2, (float)Xt[lane * PP + w + i * nw], Dr[i])
-                            : (float)fma((double)prm.dt2, (double)Xt[lane * PP + w + i * nw], (double)Dr[i]);
-        Dw[xrow(j, i) + lane] = d;
-        Uw[xrow(j, i) + lane] = Ua[i] + d;
+                            ? fmaf(prm.dt2, (float)Xt[xl * PP + trow(i)], Dr[i])
+                            : (float)fma((double)prm.dt2, (double)Xt[xl * PP + trow(i)], (double)Dr[i]);
+        Dw[xrow(j, i)] = d;
+        Uw[xrow(j, i)] = Ua[i] + d;
       }
     }
 #pragma unroll
@@ -443,15 +463,20 @@ typedef void (*ShotKernel)(ShotParams);
 // work-groups per CU with some registers spilled.  FP64 (twice the accumulator and prefetch
 // registers): for 6m <= 80 a work-group of at most 10 waves allows 3 waves per SIMD (170
 // registers, no spills); the 4-wave variant serves every 6m <= 112.
-constexpr ShotKernel kShotVariants[2][2] = {{shots_main_kernel<float, 4>, shots_main_kernel<float, 6>},
-                                            {shots_main_kernel<double, 3, 5>, shots_main_kernel<double, 4>}};
-constexpr int kShotVariantWaves[2][2] = {{4, 6}, {3, 4}};
-constexpr int kShotVariantMaxNt[2][2] = {{7, 7}, {5, 7}};   // largest P16 / 16 of each variant
-constexpr int kNumShotVariants = 2;
+// Third variant of each: 32 shots per work-group (two per subdomain), with twice the prefetch
+// loads per thread since the work-group is half the size.
+constexpr int kNumShotVariants = 3;
+constexpr ShotKernel kShotVariants[2][kNumShotVariants] = {
+    {shots_main_kernel<float, 4>, shots_main_kernel<float, 6>, shots_main_kernel<float, 3, 7, 32, 4>},
+    {shots_main_kernel<double, 3, 5>, shots_main_kernel<double, 4>, shots_main_kernel<double, 3, 5, 32, 6>}};
+constexpr int kShotVariantWaves[2][kNumShotVariants] = {{4, 6, 3}, {3, 4, 3}};
+constexpr int kShotVariantMaxNt[2][kNumShotVariants] = {{7, 7, 7}, {5, 7, 5}};   // largest P16 / 16
+constexpr int kShotVariantCols[kNumShotVariants] = {64, 64, 32};
+constexpr int kShotVariantPrefetch[2][kNumShotVariants] = {{2, 2, 4}, {4, 4, 6}};
 
-size_t shots_lds_bytes(int P, size_t elem) {
+size_t shots_lds_bytes(int P, size_t elem, int cols = kShotCols) {
   const int PP = P + 4;
-  return elem * ((size_t)P * PP + (size_t)kShotCols * PP);
+  return elem * ((size_t)P * PP + (size_t)cols * PP);
 }
 
 int shot_kind(sfm_ctx c) { return c->cfg.precision == SFM_PREC_FP64 ? 1 : 0; }
@@ -580,15 +605,26 @@ ShotParams main_params(sfm_ctx c, const float* wavelet_dev, double dt) {
 
 hipError_t launch_shots_main(int kind, int variant, const ShotParams& prm, int nt, hipStream_t st,
                              bool set_attr = true) {
-  const size_t lds = shots_lds_bytes(prm.P, kind ? sizeof(double) : sizeof(float));
+  const int cols = kShotVariantCols[variant];
+  const size_t lds = shots_lds_bytes(prm.P, kind ? sizeof(double) : sizeof(float), cols);
   const ShotKernel kern = kShotVariants[kind][variant];
   if (lds > kDefaultLdsBytes && set_attr) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(prm.S), dim3(128 * nt), lds, st, prm);
+  const unsigned grid = cols == 64 ? (unsigned)prm.S : (unsigned)((prm.S + 7) / 8 * 16);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3((cols == 64 ? 128 : 64) * nt), lds, st, prm);
   return hipGetLastError();
+}
+
+// The variant's prefetch holds a whole coefficient block for this 6m and fits its work-group limit.
+bool shot_variant_fits(sfm_ctx c, int v) {
+  const int kind = shot_kind(c);
+  const int64_t words = kind ? ShotMath<double>::kWords : ShotMath<float>::kWords;
+  const int64_t threads = (kShotVariantCols[v] == 64 ? 128 : 64) * (int64_t)c->geo.nt;
+  return c->geo.nt <= kShotVariantMaxNt[kind][v] &&
+         c->geo.words_per_block <= (int64_t)kShotVariantPrefetch[kind][v] * words * threads;
 }
 
 // Times every kernel variant on the (zero) shot state with no sources and dt = 0, which leaves
@@ -602,7 +638,7 @@ sfm_status autotune_shots(sfm_ctx c, hipStream_t st) {
   int best = -1;
   for (int v = 0; v < kNumShotVariants; ++v) {
     c->shots_tune_ms[v] = -1.0;
-    if (c->geo.nt > kShotVariantMaxNt[shot_kind(c)][v]) continue;   // work-group too large for it
+    if (!shot_variant_fits(c, v)) continue;   // work-group limit or prefetch capacity below this 6m
     for (int r = 0; r < 2; ++r) SH_TRY_HIP(launch_shots_main(shot_kind(c), v, prm, c->geo.nt, st));
     SH_TRY_HIP(hipEventRecord(a, st));
     constexpr int kReps = 5;
