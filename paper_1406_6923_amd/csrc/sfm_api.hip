@@ -93,6 +93,8 @@ void release_roms(sfm_ctx c) {
   c->rs_off_d = nullptr; c->hist_slot_d = nullptr; c->hist_d = nullptr; c->plain_blocks_d = nullptr;
   c->dfree(c->k_of_d);
   c->k_of_d = nullptr;
+  c->dfree(c->order_d);
+  c->order_d = nullptr;
   c->k_of.clear();
   c->n_rs = 0;
   c->rs_max = 0;
@@ -845,11 +847,19 @@ sfm_status sfm_set_levels(sfm_ctx c, const int32_t* k_per_sub) {
   sfm::drop_shot_graph(c);
   c->dfree(c->k_of_d);
   c->k_of_d = nullptr;
+  c->dfree(c->order_d);
+  c->order_d = nullptr;
   c->k_of = ks;
   if (!ks.empty()) {
+    std::vector<int32_t> order(t.S);
+    for (int s = 0; s < t.S; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ks[a] > ks[b]; });
     hipError_t e = hipSuccess;
     c->k_of_d = alloc_copy(c, ks, &e);
-    if (!c->k_of_d) {
+    if (c->k_of_d && e == hipSuccess) c->order_d = alloc_copy(c, order, &e);
+    if (!c->k_of_d || !c->order_d) {
+      c->dfree(c->k_of_d);
+      c->k_of_d = nullptr;
       c->k_of.clear();
       return c->fail(SFM_ENOMEM, "level table: out of device memory");
     }

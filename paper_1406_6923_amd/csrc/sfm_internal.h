@@ -258,6 +258,8 @@ struct sfm_ctx_s {
   float* work_b_d = nullptr;
 
   int32_t* k_of_d = nullptr;        // [S] per-subdomain levels (null: every subdomain uses k)
+  int32_t* order_d = nullptr;       // [S] subdomains by decreasing levels (launch order of the shot
+                                    // kernel: the longest first, so the grid's tail is short)
   std::vector<int32_t> k_of;        // host copy
 
   bool has_roms = false;

@@ -91,6 +91,7 @@ struct ShotParams {
   float* D;
   float* exch;                 // [S][P][64]
   const int32_t* k_of;         // [S] levels of each subdomain's ROM (null: all k)
+  const int32_t* order;        // [S] subdomain of each launch slot (null: the identity)
   const int32_t* src_off;      // [S+1] interior sources of each subdomain
   const int32_t* src_ids;
   const int32_t* src_shot;     // [nsrc] shot driven by each source (-1: none)
@@ -200,6 +201,7 @@ __global__ __launch_bounds__((kCols == 64 ? 128 : 64) * kMaxNtWG, kMinWaves) voi
     c0 = (r >> 3) * 32;
     if (s >= prm.S) return;              // the whole work-group: the last group of 8 is partial
   }
+  if (prm.order) s = prm.order[s];
   const int nq = (int)(prm.words_per_block / ShotMath<T>::kWords);
   const size_t sbase = (size_t)s * k * P * kShotCols;
   const int ns0 = prm.src_off ? prm.src_off[s] : 0;
@@ -588,6 +590,7 @@ ShotParams main_params(sfm_ctx c, const float* wavelet_dev, double dt) {
   prm.S = t.S;
   prm.k = t.k;
   prm.k_of = c->k_of_d;
+  prm.order = c->order_d;
   prm.P = g.P16;
   prm.PP = g.P16 + 4;
   prm.U = c->Us_d;
