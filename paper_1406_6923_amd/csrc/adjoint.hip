@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kStepThreads) void adj_main_kernel(AdjParams prm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* smem = reinterpret_cast<float*>(smem_raw);
   const StepParams& gp = prm.geo;
-  const int s = blockIdx.x, tid = threadIdx.x;
+  const int s = gp.order ? gp.order[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
   const int k = gp.k, P = gp.P16;
   float* xs = smem;                       // [k][P] block inputs
   float* zs = xs + k * P;                 // [k][P] z = M^{-1} psi, later the fluxes phi

@@ -547,6 +547,7 @@ static StepParams make_step_params(sfm_ctx c) {
   prm.S = c->topo.S;
   prm.k = c->topo.k;
   prm.k_of = c->k_of_d;
+  prm.order = c->order_d;
   prm.P16 = g.P16;
   prm.nt = g.nt;
   prm.npairs = g.npairs;

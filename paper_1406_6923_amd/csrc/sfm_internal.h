@@ -102,6 +102,7 @@ struct StepParams {
   float dt2;
   int mode;                   // 0 = leapfrog step, 1 = apply operator
   const int32_t* k_of;        // optional [S]: levels of each subdomain's ROM (<= k; null: all k)
+  const int32_t* order;       // optional [S]: subdomain of each work-group (longest ROMs first)
   float* kx_out;              // optional [S][k][P16]: the interior flux differences phi_j - phi_{j-1}
                               // (j >= 2) of this step, for the adjoint's recomputed segments
   float* hist;                // receiver-subdomain state history [Tw][n_rs][k][P16] (or null)

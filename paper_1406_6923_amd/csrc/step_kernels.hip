@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kStepThreads) void step_main_kernel(StepParams prm)
   typedef typename Acc<T>::type R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* smem = reinterpret_cast<R*>(smem_raw);
-  const int s = blockIdx.x;
+  const int s = prm.order ? prm.order[blockIdx.x] : (int)blockIdx.x;
   const int tid = threadIdx.x;
   const int k = prm.k, P = prm.P16;
   const int vstride = P;
