@@ -360,6 +360,7 @@ struct ShotRecParams {
   const int32_t* rec_sub;      // sorted receivers: subdomain
   const int32_t* perm;         // sorted receivers: caller index
   const float* U;              // [S][k][P][64]
+  const int32_t* k_of;         // [S] levels of each subdomain's ROM (null: all k)
   float* stage;                // [kShotWindow][nrec][64] samples of the current window (sorted order)
   float* out;                  // [nshot][nrec][ld]
   int k, P, nrec, nshot;
@@ -383,8 +384,10 @@ __global__ __launch_bounds__(256) void shots_record_kernel(ShotRecParams prm) {
   const int r0 = prm.rs_off[slot] + blockIdx.x * kR;
   const int r1 = prm.rs_off[slot + 1];
   if (r0 >= r1) return;
-  const int K = prm.k * prm.P;            // a multiple of 16 (P = P16)
-  const float* Ub = prm.U + (size_t)prm.rec_sub[r0] * K * kShotCols;
+  const int K = prm.k * prm.P;            // row length and level stride; a multiple of 16 (P = P16)
+  const int sub = prm.rec_sub[r0];
+  const int Kr = (prm.k_of ? prm.k_of[sub] : prm.k) * prm.P;   // levels past k_s are zero: skipped
+  const float* Ub = prm.U + (size_t)sub * K * kShotCols;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, g = lane >> 4, li = lane & 15;
   // loader layout: 4 passes of 16 rows x 16 quads
   const int lr = tid >> 4, lq = tid & 15;
@@ -394,16 +397,16 @@ __global__ __launch_bounds__(256) void shots_record_kernel(ShotRecParams prm) {
     for (int pass = 0; pass < 4; ++pass) {
       const int rr = lr + 16 * pass;
       const int r = r0 + rr, e = k0 + 4 * lq;
-      rbuf[pass] = (r < r1 && e < K) ? *reinterpret_cast<const f4*>(prm.rows + (size_t)r * K + e) : f4{0.f, 0.f, 0.f, 0.f};
+      rbuf[pass] = (r < r1 && e < Kr) ? *reinterpret_cast<const f4*>(prm.rows + (size_t)r * K + e) : f4{0.f, 0.f, 0.f, 0.f};
       const int e2 = k0 + rr;
-      ubuf[pass] = e2 < K ? *reinterpret_cast<const f4*>(Ub + (size_t)e2 * kShotCols + 4 * lq) : f4{0.f, 0.f, 0.f, 0.f};
+      ubuf[pass] = e2 < Kr ? *reinterpret_cast<const f4*>(Ub + (size_t)e2 * kShotCols + 4 * lq) : f4{0.f, 0.f, 0.f, 0.f};
     }
   };
   f4 acc[4];
 #pragma unroll
   for (int h = 0; h < 4; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
   load(0);
-  for (int k0 = 0; k0 < K; k0 += kK) {
+  for (int k0 = 0; k0 < Kr; k0 += kK) {
     __syncthreads();
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
@@ -411,7 +414,7 @@ __global__ __launch_bounds__(256) void shots_record_kernel(ShotRecParams prm) {
       *reinterpret_cast<f4*>(&Us[lr + 16 * pass][4 * lq]) = ubuf[pass];
     }
     __syncthreads();
-    if (k0 + kK < K) load(k0 + kK);
+    if (k0 + kK < Kr) load(k0 + kK);
 #pragma unroll
     for (int kk = 0; kk < kK; kk += 16) {
       const f4 a = *reinterpret_cast<const f4*>(&Rs[16 * wv + li][kk + 4 * g]);
@@ -704,6 +707,7 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
   rp.rec_sub = c->rec_sub_d;
   rp.perm = c->rec_perm_d;
   rp.U = c->Us_d;
+  rp.k_of = c->k_of_d;
   rp.stage = c->rec_stage_d;
   rp.out = traces_dev;
   rp.k = t.k;
