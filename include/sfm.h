@@ -288,12 +288,14 @@ sfm_status sfm_step_plain(sfm_ctx ctx, int32_t nsteps, double dt, const float* w
  * parts; Gamma-hat_1, the face masses, and the source / receiver projections held fixed, so
  * grad_gamma_hat[.][0] = 0).  The adjoint runs backward with A^T = -K M^{-1} (the step with its
  * two block products swapped) and the residuals injected through the receiver rows; forward
- * states come from checkpoints every checkpoint_every steps and a recomputation of each segment.
+ * states come from checkpoints every checkpoint_every = L steps and a recomputation of each
+ * segment but the last, which the first forward pass stores: L >= nsteps runs the forward once.
  *   wavelet_dev      device, float [nsteps][nsrc] (as sfm_step)
  *   grad_traces_dev  device, float [nrec][ld]: r^n in column n (caller's receiver order)
  *   grad_gamma, grad_gamma_hat  host, double [S][k][p][p]
- * Device memory: checkpoints 2 ceil(nsteps / L) states, a segment of 2 L + 2 states, 64 window
- * states and S (2k-1) p^2 doubles (state = S k P16 floats).  Requires SFM_PREC_FP32 and
+ * Device memory: checkpoints 2 (ceil(nsteps / L) - 1) states, a segment of 2 L + 1 states, 128
+ * window states, 64 receiver-injection slices of n_rs k P16 floats, S (2k-1) p^2 doubles and
+ * 2 S k p^2 doubles of output staging (state = S k P16 floats).  Requires SFM_PREC_FP32 and
  * receivers.  Synchronizes; the single-shot state is left at rest (n = 0).
  * Errors: SFM_ESTATE, SFM_EINVAL, SFM_EUNSTABLE, SFM_ENOMEM. */
 sfm_status sfm_adjoint_gradient(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet_dev,

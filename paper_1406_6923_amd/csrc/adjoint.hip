@@ -15,8 +15,11 @@
 // Gamma-hat_j psi_j (blocks k.. of the tile stream) and z_1 = C psi_1, then the fluxes
 // phi_j = Gamma_j (z_{j+1} - z_j) and the interior update; adj_face_kernel sums phi_1 over both
 // sides of a shared entry (no C: it was applied to z).  The forward states come from checkpoints
-// every L steps and a recomputation of each segment (U^m and (-K X^m) stored per step); the
-// gradient pairs of up to 32 adjoint steps are accumulated by one product per block into FP64.
+// every L steps and a recomputation of each segment (U^m and (-K X^m) stored per step; the last
+// segment is stored by the first forward pass, so L >= nsteps runs the forward once).  The
+// receiver injections R^T r of 64 adjoint steps come from one tiled product per window, and the
+// gradient pairs of up to 64 adjoint steps are accumulated by one product per block into FP64,
+// symmetric part only.
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -26,7 +29,8 @@
 namespace sfm {
 namespace {
 
-constexpr int kGradWindow = 32;
+constexpr int kGradWindow = 64;   // adjoint steps per gradient accumulation
+constexpr int kInjWindow = 64;    // adjoint steps per receiver-injection product
 
 struct AdjParams {
   StepParams geo;              // tile stream and block geometry
@@ -125,16 +129,56 @@ __global__ void adj_face_kernel(AdjParams prm, const int32_t* __restrict__ nbr) 
   prm.Psi[u] = prm.Psi[u] + fv;
 }
 
-// gslot[slot][e] = sum over the slot's receivers r of res[perm[r]][col] rows[r][e]  (R^T r).
-__global__ void adj_inject_kernel(const float* __restrict__ rows, const int32_t* __restrict__ rs_off,
-                                  const int32_t* __restrict__ perm, const float* __restrict__ res, int64_t ld,
-                                  int64_t col, int K, float* __restrict__ gslot) {
-  const int slot = blockIdx.y;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= K) return;
-  float acc = 0.f;
-  for (int r = rs_off[slot]; r < rs_off[slot + 1]; ++r) acc = fmaf(res[(size_t)perm[r] * ld + col], rows[(size_t)r * K + e], acc);
-  gslot[(size_t)slot * K + e] = acc;
+constexpr int kIE = 64;   // injection entries per tile
+constexpr int kIT = 64;   // adjoint steps per tile (= kInjWindow)
+constexpr int kIR = 32;   // receivers per reduction chunk
+
+// inj[t][slot][e] = sum over the slot's receivers r of res[perm[r]][col0 - t] rows[r][e], t < w:
+// R^T r for w consecutive adjoint steps, so each receiver row is read once per window.
+// blockIdx.y = receiver-subdomain slot, blockIdx.x = tile of 64 entries e; 4 x 4 outputs a thread.
+__global__ __launch_bounds__(256) void adj_inject_window_kernel(const float* __restrict__ rows,
+                                                                const int32_t* __restrict__ rs_off,
+                                                                const int32_t* __restrict__ perm,
+                                                                const float* __restrict__ res, int64_t ld,
+                                                                int64_t col0, int w, int K, int n_rs,
+                                                                float* __restrict__ inj) {
+  __shared__ __align__(16) float Rs[kIR][kIE + 4];
+  __shared__ __align__(16) float Qs[kIR][kIT + 4];
+  const int slot = blockIdx.y, e0 = blockIdx.x * kIE, tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;        // entries e0 + 4tx.., steps 4ty..
+  const int r0 = rs_off[slot], r1 = rs_off[slot + 1];
+  float acc[4][4] = {};
+  for (int rb = r0; rb < r1; rb += kIR) {
+    for (int q = tid; q < kIR * kIE; q += 256) {
+      const int rr = q / kIE, ee = q - rr * kIE;
+      const int r = rb + rr, e = e0 + ee;
+      Rs[rr][ee] = (r < r1 && e < K) ? rows[(size_t)r * K + e] : 0.f;
+      Qs[rr][ee] = (r < r1 && ee < w) ? res[(size_t)perm[r] * ld + col0 - ee] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < kIR; ++rr) {
+      const float4 a = *reinterpret_cast<const float4*>(&Qs[rr][ty * 4]);
+      const float4 b = *reinterpret_cast<const float4*>(&Rs[rr][tx * 4]);
+      const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(av[i], bv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int t = ty * 4 + i;
+    if (t >= w) continue;
+    float* out = inj + ((size_t)t * n_rs + slot) * K;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = e0 + tx * 4 + j;
+      if (e < K) out[e] = acc[i][j];
+    }
+  }
 }
 
 struct GradParams {
@@ -151,12 +195,16 @@ struct GradParams {
   double* G;                   // [S][2k-1][p][p] accumulators
 };
 
-// One work-group per (subdomain, block): G[s][b] += factor sum_t x_t y_t^T.
+// One work-group per (subdomain, block): G[s][b] += factor sum_t (x_t y_t^T + y_t x_t^T), the
+// symmetric part (twice it) of the pair products, on the tiles of 4 x 4 entries on or above the
+// diagonal; below the diagonal only the diagonal tiles write (their mirror values).  The window
+// of x and y sits in LDS ([w][P] each); a thread keeps one 4 x 4 tile in registers.
 __global__ __launch_bounds__(256) void grad_accum_kernel(GradParams prm) {
-  __shared__ float xs[kGradWindow][kTile * kMaxNt];
-  __shared__ float ys[kGradWindow][kTile * kMaxNt];
+  extern __shared__ __align__(16) unsigned char gsm_raw[];
   const int s = blockIdx.x, b = blockIdx.y;
   const int k = prm.k, P = prm.P, p = prm.p;
+  float* xs = reinterpret_cast<float*>(gsm_raw);   // [w][P]
+  float* ys = xs + (size_t)prm.w * P;              // [w][P]
   const bool hat = b >= k;
   const int j = hat ? b - k + 1 : b;           // layer index (0-based)
   if (j >= (prm.k_of ? prm.k_of[s] : k)) return;   // a level this ROM does not have: gradient zero
@@ -165,23 +213,65 @@ __global__ __launch_bounds__(256) void grad_accum_kernel(GradParams prm) {
     const size_t lay = ((size_t)s * k + j) * P + i;
     const size_t slot = (size_t)(prm.first - t);
     if (hat) {
-      xs[t][i] = prm.win_psi[(size_t)t * prm.state + lay];
-      ys[t][i] = prm.kxseg[slot * prm.state + lay];
+      xs[e] = prm.win_psi[(size_t)t * prm.state + lay];
+      ys[e] = prm.kxseg[slot * prm.state + lay];
     } else {
-      xs[t][i] = prm.win_dz[(size_t)t * prm.state + lay];
+      xs[e] = prm.win_dz[(size_t)t * prm.state + lay];
       const float* u = prm.useg + slot * prm.state;
-      ys[t][i] = (j + 1 < k ? u[lay + P] : 0.f) - u[lay];
+      ys[e] = (j + 1 < k ? u[lay + P] : 0.f) - u[lay];
     }
   }
   __syncthreads();
   const double factor = hat ? prm.dt2 : -prm.dt2;
   double* G = prm.G + ((size_t)s * (2 * k - 1) + b) * p * p;
-  for (int e = threadIdx.x; e < p * p; e += 256) {
-    const int r = e / p, c = e - r * p;
-    float acc = 0.f;
-    for (int t = 0; t < prm.w; ++t) acc = fmaf(xs[t][r], ys[t][c], acc);
-    G[e] += factor * (double)acc;
+  const int nt = (p + 3) / 4;                  // 4 nt <= P: the tile reads stay inside a row
+  for (int u = threadIdx.x; u < nt * (nt + 1) / 2; u += 256) {
+    int bi = 0, rem = u;
+    while (rem >= nt - bi) {
+      rem -= nt - bi;
+      ++bi;
+    }
+    const int r0 = 4 * bi, c0 = 4 * (bi + rem);
+    float acc[4][4] = {};
+    for (int t = 0; t < prm.w; ++t) {
+      const float4 xr = *reinterpret_cast<const float4*>(xs + (size_t)t * P + r0);
+      const float4 yr = *reinterpret_cast<const float4*>(ys + (size_t)t * P + r0);
+      const float4 xc = *reinterpret_cast<const float4*>(xs + (size_t)t * P + c0);
+      const float4 yc = *reinterpret_cast<const float4*>(ys + (size_t)t * P + c0);
+      const float xrv[4] = {xr.x, xr.y, xr.z, xr.w}, yrv[4] = {yr.x, yr.y, yr.z, yr.w};
+      const float xcv[4] = {xc.x, xc.y, xc.z, xc.w}, ycv[4] = {yc.x, yc.y, yc.z, yc.w};
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = fmaf(xrv[a], ycv[c], fmaf(yrv[a], xcv[c], acc[a][c]));
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int r = r0 + a, col = c0 + c;
+        if (r < p && col < p) G[r * p + col] += factor * (double)acc[a][c];
+      }
   }
+}
+
+size_t grad_lds_bytes(int w, int P) { return (size_t)2 * w * P * sizeof(float); }
+
+// Caller layout [S][k][p][p]: dJ/dGamma_j and dJ/dGamma-hat_j (zero for j = 1), each half of the
+// accumulated symmetric sum, which sits on or above the diagonal.
+__global__ void grad_out_kernel(const double* __restrict__ G, int S, int k, int p, double* __restrict__ og,
+                                double* __restrict__ oh) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t pp = (size_t)p * p;
+  if (idx >= (size_t)S * k * pp) return;
+  const size_t sj = idx / pp;
+  const int e = (int)(idx - sj * pp);
+  const int s = (int)(sj / k), j = (int)(sj - (size_t)s * k);
+  const int r = e / p, q = e - r * p;
+  const size_t up = (size_t)min(r, q) * p + max(r, q);
+  const double* Gs = G + (size_t)s * (2 * k - 1) * pp;
+  og[idx] = 0.5 * Gs[(size_t)j * pp + up];
+  oh[idx] = j >= 1 ? 0.5 * Gs[(size_t)(k + j - 1) * pp + up] : 0.0;
 }
 
 struct Buffers {
@@ -234,33 +324,39 @@ extern "C" sfm_status sfm_adjoint_gradient(sfm_ctx c, int32_t nsteps, double dt,
   const int L = std::min(checkpoint_every, N);
   const size_t state = (size_t)S * k * P;
   const int nck = (N + L - 1) / L;
+  const int nlast = (nck - 1) * L;              // first step of the last segment
   const int nblk = 2 * k - 1;
+  const int K = k * P;
   Buffers B(c);
-  float* ckU = B.get<float>(state * nck);
-  float* ckD = B.get<float>(state * nck);
+  float* ckU = B.get<float>(state * std::max(nck - 1, 1));
+  float* ckD = B.get<float>(state * std::max(nck - 1, 1));
   float* useg = B.get<float>(state * (L + 1));
   float* kxseg = B.get<float>(state * L);
   float* wdz = B.get<float>(state * kGradWindow);
   float* wpsi = B.get<float>(state * kGradWindow);
   float* psi = B.get<float>(state);
   float* F = B.get<float>(state);
-  float* gslot = B.get<float>((size_t)c->n_rs * k * P);
+  float* injw = B.get<float>((size_t)kInjWindow * c->n_rs * K);
   double* G = B.get<double>((size_t)S * nblk * p * p);
-  if (B.e != hipSuccess) return c->fail(SFM_ENOMEM, "adjoint buffers: out of device memory (raise checkpoint_every?)");
+  if (B.e != hipSuccess) return c->fail(SFM_ENOMEM, "adjoint buffers: out of device memory (lower checkpoint_every?)");
   AD_TRY_HIP(hipMemsetAsync(G, 0, (size_t)S * nblk * p * p * sizeof(double), st));
   AD_TRY_HIP(hipMemsetAsync(psi, 0, state * sizeof(float), st));
   AD_TRY_HIP(hipMemsetAsync(F, 0, state * sizeof(float), st));
   AD_TRY_HIP(hipMemsetAsync(kxseg, 0, state * L * sizeof(float), st));   // layer 0 rows stay zero
-  // forward from rest with checkpoints of (U, D) before steps 0, L, 2L, ...
+  // forward from rest with checkpoints of (U, D) before steps 0, L, .., nlast - L; the states of
+  // the last segment are stored as they come
   AD_TRY_HIP(hipMemsetAsync(c->U_d, 0, state * sizeof(float), st));
   AD_TRY_HIP(hipMemsetAsync(c->D_d, 0, state * sizeof(float), st));
   const int nsrc = c->nsrc;
   for (int n = 0; n < N; ++n) {
-    if (n % L == 0) {
+    const bool last = n >= nlast;
+    if (!last && n % L == 0) {
       AD_TRY_HIP(hipMemcpyAsync(ckU + state * (n / L), c->U_d, state * sizeof(float), hipMemcpyDeviceToDevice, st));
       AD_TRY_HIP(hipMemcpyAsync(ckD + state * (n / L), c->D_d, state * sizeof(float), hipMemcpyDeviceToDevice, st));
     }
-    const sfm_status rc = forward_step(c, dt, wavelet_dev ? wavelet_dev + (size_t)n * nsrc : nullptr, nullptr, st);
+    const sfm_status rc = forward_step(c, dt, wavelet_dev ? wavelet_dev + (size_t)n * nsrc : nullptr,
+                                       last ? kxseg + state * (n - nlast) : nullptr,
+                                       last ? useg + state * (n - nlast) : nullptr, st);
     if (rc != SFM_OK) return rc;
   }
   AdjParams ap{};
@@ -269,7 +365,6 @@ extern "C" sfm_status sfm_adjoint_gradient(sfm_ctx c, int32_t nsteps, double dt,
   ap.F = F;
   ap.C = c->C_d;
   ap.exch = c->exch_d;
-  ap.gslot = gslot;
   ap.slot_of = c->hist_slot_d;
   ap.p = p;
   ap.m = t.m;
@@ -278,8 +373,11 @@ extern "C" sfm_status sfm_adjoint_gradient(sfm_ctx c, int32_t nsteps, double dt,
   if (lds > kDefaultLdsBytes)
     AD_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&adj_main_kernel),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  const int K = k * P;
-  const dim3 igrid((K + 255) / 256, c->n_rs);
+  const size_t glds = grad_lds_bytes(kGradWindow, P);
+  if (glds > kDefaultLdsBytes)
+    AD_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&grad_accum_kernel),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds));
+  const dim3 igrid((K + kIE - 1) / kIE, c->n_rs);
   const unsigned fgrid = (unsigned)(((int64_t)S * p + 255) / 256);
   GradParams gp{};
   gp.win_dz = wdz;
@@ -294,11 +392,19 @@ extern "C" sfm_status sfm_adjoint_gradient(sfm_ctx c, int32_t nsteps, double dt,
   gp.state = state;
   gp.dt2 = dt * dt;
   gp.G = G;
+  // injections R^T r^{m-1} for the adjoint steps win_hi down to win_lo (m descends by one)
+  int win_hi = 0, win_lo = N + 1;
   // one adjoint step psi^{m+1} -> psi^m; window slot wslot (or -1: no gradient pair)
   auto adjoint_step = [&](int m, int wslot) -> sfm_status {
-    hipLaunchKernelGGL(adj_inject_kernel, igrid, dim3(256), 0, st, c->rec_rows_d, c->rs_off_d, c->rec_perm_d,
-                       grad_traces_dev, ld, (int64_t)(m - 1), K, gslot);
-    AD_TRY_HIP(hipGetLastError());
+    if (c->n_rs > 0 && m < win_lo) {
+      win_hi = m;
+      win_lo = std::max(1, m - kInjWindow + 1);
+      hipLaunchKernelGGL(adj_inject_window_kernel, igrid, dim3(256), 0, st, c->rec_rows_d, c->rs_off_d,
+                         c->rec_perm_d, grad_traces_dev, ld, (int64_t)(win_hi - 1), win_hi - win_lo + 1, K,
+                         c->n_rs, injw);
+      AD_TRY_HIP(hipGetLastError());
+    }
+    ap.gslot = c->n_rs > 0 ? injw + (size_t)(win_hi - m) * c->n_rs * K : nullptr;
     ap.win_dz = wslot >= 0 ? wdz + state * wslot : nullptr;
     ap.win_psi = wslot >= 0 ? wpsi + state * wslot : nullptr;
     hipLaunchKernelGGL(adj_main_kernel, dim3(S), dim3(kStepThreads), lds, st, ap);
@@ -312,12 +418,14 @@ extern "C" sfm_status sfm_adjoint_gradient(sfm_ctx c, int32_t nsteps, double dt,
   if (rc != SFM_OK) return rc;
   for (int seg = nck - 1; seg >= 0; --seg) {
     const int n0 = seg * L, n1 = std::min(N, n0 + L);
-    AD_TRY_HIP(hipMemcpyAsync(c->U_d, ckU + state * seg, state * sizeof(float), hipMemcpyDeviceToDevice, st));
-    AD_TRY_HIP(hipMemcpyAsync(c->D_d, ckD + state * seg, state * sizeof(float), hipMemcpyDeviceToDevice, st));
-    for (int n = n0; n < n1; ++n) {
-      AD_TRY_HIP(hipMemcpyAsync(useg + state * (n - n0), c->U_d, state * sizeof(float), hipMemcpyDeviceToDevice, st));
-      rc = forward_step(c, dt, wavelet_dev ? wavelet_dev + (size_t)n * nsrc : nullptr, kxseg + state * (n - n0), st);
-      if (rc != SFM_OK) return rc;
+    if (seg < nck - 1) {                        // recompute the segment from its checkpoint
+      AD_TRY_HIP(hipMemcpyAsync(c->U_d, ckU + state * seg, state * sizeof(float), hipMemcpyDeviceToDevice, st));
+      AD_TRY_HIP(hipMemcpyAsync(c->D_d, ckD + state * seg, state * sizeof(float), hipMemcpyDeviceToDevice, st));
+      for (int n = n0; n < n1; ++n) {
+        rc = forward_step(c, dt, wavelet_dev ? wavelet_dev + (size_t)n * nsrc : nullptr, kxseg + state * (n - n0),
+                          useg + state * (n - n0), st);
+        if (rc != SFM_OK) return rc;
+      }
     }
     // adjoint steps m = n1 - 1 .. max(n0, 1), each pairing psi^{m+1} with X^m
     int w = 0, first = 0;
@@ -329,29 +437,22 @@ extern "C" sfm_status sfm_adjoint_gradient(sfm_ctx c, int32_t nsteps, double dt,
       if (w == kGradWindow || m == std::max(n0, 1)) {
         gp.first = first;
         gp.w = w;
-        hipLaunchKernelGGL(grad_accum_kernel, dim3(S, nblk), dim3(256), 0, st, gp);
+        hipLaunchKernelGGL(grad_accum_kernel, dim3(S, nblk), dim3(256), grad_lds_bytes(w, P), st, gp);
         AD_TRY_HIP(hipGetLastError());
         w = 0;
       }
     }
   }
   // gradients to the caller: symmetric parts, Gamma-hat_1 held fixed
-  std::vector<double> h((size_t)S * nblk * p * p);
-  AD_TRY_HIP(hipMemcpyAsync(h.data(), G, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  const size_t nout = (size_t)S * k * p * p;
+  double* og = B.get<double>(nout);
+  double* oh = B.get<double>(nout);
+  if (B.e != hipSuccess) return c->fail(SFM_ENOMEM, "adjoint output: out of device memory");
+  hipLaunchKernelGGL(grad_out_kernel, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, st, G, S, k, p, og, oh);
+  AD_TRY_HIP(hipGetLastError());
+  AD_TRY_HIP(hipMemcpyAsync(grad_gamma, og, nout * sizeof(double), hipMemcpyDeviceToHost, st));
+  AD_TRY_HIP(hipMemcpyAsync(grad_gamma_hat, oh, nout * sizeof(double), hipMemcpyDeviceToHost, st));
   AD_TRY_HIP(hipStreamSynchronize(st));
-  const size_t pp = (size_t)p * p;
-  for (int s = 0; s < S; ++s)
-    for (int j = 0; j < k; ++j) {
-      double* og = grad_gamma + ((size_t)s * k + j) * pp;
-      double* oh = grad_gamma_hat + ((size_t)s * k + j) * pp;
-      const double* g1 = h.data() + ((size_t)s * nblk + j) * pp;
-      const double* g2 = j >= 1 ? h.data() + ((size_t)s * nblk + k + j - 1) * pp : nullptr;
-      for (int r = 0; r < p; ++r)
-        for (int q = 0; q < p; ++q) {
-          og[r * p + q] = 0.5 * (g1[r * p + q] + g1[q * p + r]);
-          oh[r * p + q] = g2 ? 0.5 * (g2[r * p + q] + g2[q * p + r]) : 0.0;
-        }
-    }
   // the single-shot state is left at rest
   AD_TRY_HIP(hipMemsetAsync(c->U_d, 0, state * sizeof(float), st));
   AD_TRY_HIP(hipMemsetAsync(c->D_d, 0, state * sizeof(float), st));

@@ -588,8 +588,10 @@ static hipError_t apply_operator(sfm_ctx c, const float* u, float* a, hipStream_
 }
 
 // One leapfrog step of the single-shot state (no receivers): wavelet_row = this step's source
-// amplitudes [nsrc]; kx_out (optional) receives the interior flux differences of the step.
-sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, hipStream_t st) {
+// amplitudes [nsrc]; kx_out (optional) receives the interior flux differences of the step and
+// u_out (optional) the state the step starts from.
+sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, float* u_out,
+                        hipStream_t st) {
   StepParams prm = make_step_params(c);
   FaceParams f = make_face_params(c);
   prm.mode = 0;
@@ -609,6 +611,7 @@ sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* k
     f.sw_w = c->sw_w_d;
   }
   prm.kx_out = kx_out;
+  prm.u_out = u_out;
   SFM_TRY_HIP(c, launch_step_main(prm, c->cfg.precision, st));
   SFM_TRY_HIP(c, launch_step_face(f, st));
   return SFM_OK;

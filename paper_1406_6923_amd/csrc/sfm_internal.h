@@ -104,6 +104,7 @@ struct StepParams {
   const int32_t* k_of;        // optional [S]: levels of each subdomain's ROM (<= k; null: all k)
   const int32_t* order;       // optional [S]: subdomain of each work-group (longest ROMs first)
   float* kx_out;              // optional [S][k][P16]: the interior flux differences phi_j - phi_{j-1}
+  float* u_out;               // optional [S][k][P16]: a copy of the state U^n the step starts from
                               // (j >= 2) of this step, for the adjoint's recomputed segments
   float* hist;                // receiver-subdomain state history [Tw][n_rs][k][P16] (or null)
   const int32_t* hist_slot;   // [S] history slot of each subdomain, -1 if it holds no receiver
@@ -184,7 +185,8 @@ void release_shots(sfm_ctx c);
 void drop_shot_graph(sfm_ctx c);   // destroys the cached shot-window graph (synchronizes)
 // Zero the levels j >= k_of[s] of a [S][k][P16][cols] state (no-op without a level table).
 hipError_t clear_extra_levels(sfm_ctx c, float* X, int cols, hipStream_t st);
-sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, hipStream_t st);
+sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, float* u_out,
+                        hipStream_t st);
 StepParams step_params(sfm_ctx c);
 void destroy_blas(sfm_ctx c);
 

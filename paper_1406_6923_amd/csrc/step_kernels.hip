@@ -47,10 +47,14 @@ __global__ __launch_bounds__(kStepThreads) void step_main_kernel(StepParams prm)
   // U_{j+1} - U_j with U_{ks+1} = 0
   for (int e = tid; e < ks * P; e += kStepThreads) {
     const int j = e / P;
-    const R u = Uin[sbase + e];
+    const float uf = Uin[sbase + e];
+    const R u = uf;
     const R un = (j + 1 < ks) ? (R)Uin[sbase + e + P] : (R)0;
     xs[e] = un - u;
+    if (prm.u_out) prm.u_out[sbase + e] = uf;
   }
+  if (prm.u_out)
+    for (int e = ks * P + tid; e < k * P; e += kStepThreads) prm.u_out[sbase + e] = Uin[sbase + e];
   __syncthreads();
   run_phase<T, R>(tiles, ks, prm, xs, vstride, part, tid);      // phi_j = Gamma_j dU_j
   __syncthreads();
