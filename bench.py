@@ -393,9 +393,10 @@ def surrogate_probe(torch, sfm, dev, stream, n_samples: int, epochs: int, tol: f
 def adjoint_probe(torch, sfm, dev, stream, nsteps: int, checkpoint_every: int):
     """Misfit gradient on the gradient workload: observed traces from the medium with the Gaussian
     anomaly, ROMs of the background medium, J = 1/2 ||traces - observed||^2, dJ/d(Gamma, Gamma-hat)
-    by the discrete adjoint with checkpoints; timed forward and gradient.  With checkpoint_every =
-    nsteps every forward state and (-K X) of the run stays in HBM (2 x 4001 states of 2.6 MB at
-    4000 steps) and the forward runs once."""
+    by the discrete adjoint with checkpoints; timed forward and gradient.  A checkpoint interval
+    below nsteps is timed beside the run that holds every forward state and (-K X) in HBM (2 x 4001
+    states of 2.6 MB at 4000 steps; the forward then runs once).  Then the sound-speed gradient
+    through a network of the surrogate's architecture."""
     cfg = W.CFG_ADJOINT
     c_bg = cfg.velocity_model()
     c_true = W.gaussian_anomaly(c_bg, **W.ADJOINT_ANOMALY)
@@ -428,6 +429,29 @@ def adjoint_probe(torch, sfm, dev, stream, nsteps: int, checkpoint_every: int):
     t0 = time.perf_counter()
     g_gam, g_hat = sfm.sfm_adjoint_gradient(h.ctx, nsteps, dt, wav, resid, checkpoint_every, stream=stream)
     t_grad = time.perf_counter() - t0
+    t_hbm = None
+    if checkpoint_every < nsteps:       # the same gradient with every forward state held in HBM
+        t0 = time.perf_counter()
+        g2, _ = sfm.sfm_adjoint_gradient(h.ctx, nsteps, dt, wav, resid, nsteps, stream=stream)
+        t_hbm = time.perf_counter() - t0
+        out["all_in_hbm_gradient_seconds"] = t_hbm
+        out["all_in_hbm_vs_checkpointed_rel_l2"] = float(np.linalg.norm(g2 - g_gam) / np.linalg.norm(g_gam))
+        del g2
+    # the sound-speed gradient through a network of the surrogate's architecture (seeded weights:
+    # the cost does not depend on them)
+    ntri = cfg.p * (cfg.p + 1) // 2
+    net = sfm.Cnn(cfg.sub_cells[0] + 1, 32, 2 * cfg.k * ntri, max_batch=64, seed=17)
+    gvel = torch.zeros(c_bg.shape, dtype=torch.float32, device=dev)
+    vel_bg = torch.from_numpy(c_bg.astype(np.float32)).to(dev)
+    sfm.sfm_surrogate_velocity_gradient(h.ctx, net, vel_bg, g_gam, g_hat, gvel, stream=stream)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sfm.sfm_surrogate_velocity_gradient(h.ctx, net, vel_bg, g_gam, g_hat, gvel, stream=stream)
+    t_vel = time.perf_counter() - t0
+    out.update(velocity_gradient_seconds=t_vel, velocity_gradient_finite=bool(torch.isfinite(gvel).all().item()),
+               velocity_gradient_network=f"3D CNN {cfg.sub_cells[0] + 1}^3 -> 4 conv x 32 ch -> "
+                                         f"{2 * cfg.k * ntri} outputs, batches of 64")
+    net.close()
     h.close()
     out.update(dt=dt, misfit=J, forward_seconds=t_fwd, forward_ms_per_step=t_fwd / nsteps * 1e3,
                gradient_seconds=t_grad, gradient_over_forward=t_grad / t_fwd,
@@ -435,7 +459,9 @@ def adjoint_probe(torch, sfm, dev, stream, nsteps: int, checkpoint_every: int):
                gradient_finite=bool(np.isfinite(g_gam).all() and np.isfinite(g_hat).all()),
                fine_equiv_gcell_per_s_gradient=cfg.n_cells * nsteps / t_grad / 1e9)
     log(f"[bench] adjoint ({cfg.name}, {nsteps} steps): forward {t_fwd:.3f} s, gradient {t_grad:.3f} s "
-        f"({t_grad / t_fwd:.2f}x the forward), misfit {J:.4e}")
+        f"({t_grad / t_fwd:.2f}x the forward, checkpoints every {checkpoint_every})"
+        + (f", {t_hbm:.3f} s with every state in HBM" if t_hbm else "")
+        + f", sound-speed gradient through the network {t_vel:.3f} s, misfit {J:.4e}")
     return out
 
 
@@ -463,9 +489,9 @@ def main():
                     help="steps of the many-shot uneven-box workload (0: skip it)")
     ap.add_argument("--adjoint-steps", type=int, default=4000,
                     help="steps of the misfit-gradient probe on the 256^3 gradient workload (0: skip)")
-    ap.add_argument("--adjoint-checkpoint", type=int, default=0,
-                    help="checkpoint interval of the gradient probe (0: every forward state held in HBM, "
-                         "one forward pass)")
+    ap.add_argument("--adjoint-checkpoint", type=int, default=100,
+                    help="checkpoint interval of the gradient probe (0: every forward state held in HBM); "
+                         "a shorter interval is timed beside the all-in-HBM run")
     ap.add_argument("--no-finite-shift", action="store_true",
                     help="skip the finite-shift ROM probe (4^3-subdomain sample of the same ROM shape)")
     args = ap.parse_args()

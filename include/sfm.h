@@ -387,6 +387,12 @@ sfm_status sfm_cnn_forward(sfm_cnn net, const float* x_dev, int32_t batch, float
 /* Parameter gradients of sum(dy * y) for the last forward pass into grad_dev (device float
  * [n_params], flat layout); dy_dev device float [batch][n_out].  Errors: SFM_ESTATE (no forward). */
 sfm_status sfm_cnn_backward(sfm_cnn net, const float* dy_dev, float* grad_dev, void* stream);
+/* Input gradient: dx_dev (device float [batch][n_in^3]) = gradient of sum(dy * y) with respect to
+ * the inputs of the last forward pass, y as sfm_cnn_forward returns it (with the output scale of
+ * sfm_cnn_fit_scale when one is set); dy_dev device float [batch][n_out].  The same bf16 products
+ * as sfm_cnn_backward, the first convolution's data gradient included; no parameter gradients.
+ * Errors: SFM_ESTATE (no forward), SFM_EINVAL (NULL pointers). */
+sfm_status sfm_cnn_input_grad(sfm_cnn net, const float* dy_dev, float* dx_dev, void* stream);
 /* Output scale: per output, the mean and standard deviation (1 for a constant output) of
  * target_dev (device float [n_samples][n_out]); afterwards the net is trained on (target - mean)
  * / sd and sfm_cnn_forward returns mean + sd * (net output).  mean_host / sd_host (host float
@@ -435,6 +441,19 @@ sfm_status sfm_ntd_error(sfm_ctx ctx, const double* coef_dev, double f_peak, dou
 sfm_status sfm_build_roms_surrogate(sfm_ctx ctx, sfm_cnn net, double tol, double f_peak, const float* vel_dev,
                                     int32_t nsrc, const int32_t* src_ijk, int32_t nrec, const int32_t* rec_ijk,
                                     int32_t* accepted, double* ntd_err, double* seconds, void* stream);
+
+/* Velocity gradient through the surrogate (the FWI use of the Introduction): for a misfit J that
+ * depends on the blocks, with block gradients grad_gamma / grad_gamma_hat (host double
+ * [S][k][p][p], as sfm_adjoint_gradient returns them), grad_vel_dev (device float, nodes as
+ * vel_dev) = dJ/dc where the blocks are taken as the network's prediction from c: the chain
+ * through the prediction's upper triangles (an off-diagonal output sets two entries and collects
+ * both gradients; Gamma-hat_1 comes from Lanczos and collects none), the network (input gradient
+ * as sfm_cnn_input_grad), the input log(c / 3000 m/s) (factor 1 / c), and every subdomain box
+ * that holds the node.  Equal cubic subdomains; the network's sizes as in
+ * sfm_build_roms_surrogate.  Runs the network forward again on every subdomain in batches of its
+ * max_batch.  Errors: SFM_EINVAL (sizes, NULL pointers), SFM_ENOMEM, SFM_EHIP.  Synchronizes. */
+sfm_status sfm_surrogate_velocity_gradient(sfm_ctx ctx, sfm_cnn net, const float* vel_dev, const double* grad_gamma,
+                                           const double* grad_gamma_hat, float* grad_vel_dev, void* stream);
 
 #ifdef __cplusplus
 }

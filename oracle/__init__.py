@@ -20,7 +20,11 @@ Modules, in the order of the method:
                   transfer functions (eqs. "NtD", "NtDROM", "NtDtri");
 * ``rom``         Algorithm 1 Stage 1 per subdomain (steps 1.1-1.4, eq. "Uj");
 * ``coupled``     Algorithm 1 Stage 2 (eqs. "mass", "bdrytstep", "intrtstep")
-                  with leapfrog, energy and the CFL bound.
+                  with leapfrog, energy and the CFL bound;
+* ``adjoint``     discrete adjoint of the Stage 2 leapfrog and the misfit gradients
+                  with respect to the S-fraction blocks (the FWI use of the Introduction);
+* ``cnn``         the learned ROM surrogate network, forward and backward;
+* ``surrogate``   the sound-speed gradient through that network (chain rule).
 
 Every function cites the passage it follows.  Pins against closed forms and
 invariants live in ``tests/test_oracle_*.py``.

@@ -122,8 +122,7 @@ def forward(params: Dict[str, np.ndarray], x: np.ndarray, q: Quant = _identity):
     return y, acts
 
 
-def backward(params: Dict[str, np.ndarray], acts, dy: np.ndarray, q: Quant = _identity) -> Dict[str, np.ndarray]:
-    """Parameter gradients of sum(dy * y) for the forward pass that produced ``acts``."""
+def _backward(params: Dict[str, np.ndarray], acts, dy: np.ndarray, q: Quant):
     grads = {}
     a = acts[-1]
     feat = a.reshape(a.shape[0], -1)
@@ -135,7 +134,17 @@ def backward(params: Dict[str, np.ndarray], acts, dy: np.ndarray, q: Quant = _id
         dpre = da * (acts[l] > 0)                       # ReLU: the output is positive where the input was
         dx, grads[f"W{l}"], grads[f"b{l}"] = conv_backward(acts[l - 1], params[f"W{l}"], dpre, q)
         da = dx
-    return grads
+    return grads, da[..., 0]
+
+
+def backward(params: Dict[str, np.ndarray], acts, dy: np.ndarray, q: Quant = _identity) -> Dict[str, np.ndarray]:
+    """Parameter gradients of sum(dy * y) for the forward pass that produced ``acts``."""
+    return _backward(params, acts, dy, q)[0]
+
+
+def input_gradient(params: Dict[str, np.ndarray], acts, dy: np.ndarray, q: Quant = _identity) -> np.ndarray:
+    """Gradient of sum(dy * y) with respect to the input x [B][n][n][n] of that forward pass."""
+    return _backward(params, acts, dy, q)[1]
 
 
 def mse(y: np.ndarray, target: np.ndarray) -> Tuple[float, np.ndarray]:

@@ -328,6 +328,14 @@ __global__ void apply_scale_kernel(float* __restrict__ x, int64_t rows, int64_t 
   }
 }
 
+// out[r][c] = sd[c] dy[r][c]: a gradient with respect to the scaled output, carried to the net's own
+__global__ void scale_grad_kernel(const float* __restrict__ dy, int64_t rows, int64_t cols, const float* __restrict__ sd,
+                                  float* __restrict__ out) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = sd[e % cols] * dy[e];
+}
+
 // rows of x gathered by index: dst[r] = src[idx[r]] (rows of `len` floats)
 __global__ void gather_rows_kernel(const float* __restrict__ src, const int32_t* __restrict__ idx, int rows, int64_t len,
                                    float* __restrict__ dst) {
@@ -462,19 +470,24 @@ sfm_status column_sums(sfm_cnn net, const float* d, const float* act, int64_t ro
 }
 
 // Gradients of sum(dy * y) into g (flat layout), for the last forward pass.
-sfm_status backward_pass(sfm_cnn net, const float* dy, int B, float* g, hipStream_t st) {
+// Gradients of sum(dy * y) for the last forward pass (y the net's own, unscaled output): the
+// parameters into g (flat layout; skipped when g is null) and the input into dx ([B][n_in^3];
+// skipped when dx is null).
+sfm_status backward_pass(sfm_cnn net, const float* dy, int B, float* g, float* dx, hipStream_t st) {
   const int64_t F = net->feat;
   {  // dense layer
-    DenseBwdW w{};
-    w.M = net->n_out;
-    w.N = F;
-    w.K = B;
-    w.dy = dy;
-    w.feat = net->act[kConv];
-    w.dW = g + net->off_Wd;
-    CNN_TRY(launch_gemm(w, w.K, st));
-    sfm_status rc = column_sums(net, dy, nullptr, B, net->n_out, g + net->off_bd, st);
-    if (rc != SFM_OK) return rc;
+    if (g) {
+      DenseBwdW w{};
+      w.M = net->n_out;
+      w.N = F;
+      w.K = B;
+      w.dy = dy;
+      w.feat = net->act[kConv];
+      w.dW = g + net->off_Wd;
+      CNN_TRY(launch_gemm(w, w.K, st));
+      sfm_status rc = column_sums(net, dy, nullptr, B, net->n_out, g + net->off_bd, st);
+      if (rc != SFM_OK) return rc;
+    }
     DenseBwdData d{};
     d.M = B;
     d.N = F;
@@ -493,27 +506,29 @@ sfm_status backward_pass(sfm_cnn net, const float* dy, int B, float* g, hipStrea
   for (int l = kConv - 1; l >= 0; --l) {
     const int ci = l == 0 ? 1 : net->ch, n = net->nodes[l], m = net->nodes[l + 1];
     const int64_t rows = (int64_t)B * m * m * m;
-    ConvBwdW w{};
-    w.M = net->ch;
-    w.N = 27LL * ci;
-    w.K = rows;
-    w.dact = net->dact[l + 1];
-    w.act = net->act[l + 1];
-    w.x = net->act[l];
-    w.part = net->part;
-    w.gi = Grid3{n};
-    w.go = Grid3{m};
-    w.ci = ci;
-    const int64_t kw = split_k(w.M, w.N, w.K);
-    const int slices = (int)((rows + kw - 1) / kw);
-    if ((int64_t)slices * w.M * w.N > net->part_len) return net->fail(SFM_EINVAL, "partial-sum buffer too small");
-    CNN_TRY(launch_gemm(w, kw, st));
-    hipLaunchKernelGGL(sum_slices_kernel, dim3(blocks_for(w.M * w.N)), dim3(256), 0, st, net->part, slices,
-                       w.M * w.N, g + net->off_W[l]);
-    CNN_TRY(hipGetLastError());
-    sfm_status rc = column_sums(net, net->dact[l + 1], net->act[l + 1], rows, net->ch, g + net->off_b[l], st);
-    if (rc != SFM_OK) return rc;
-    if (l > 0) {
+    if (g) {
+      ConvBwdW w{};
+      w.M = net->ch;
+      w.N = 27LL * ci;
+      w.K = rows;
+      w.dact = net->dact[l + 1];
+      w.act = net->act[l + 1];
+      w.x = net->act[l];
+      w.part = net->part;
+      w.gi = Grid3{n};
+      w.go = Grid3{m};
+      w.ci = ci;
+      const int64_t kw = split_k(w.M, w.N, w.K);
+      const int slices = (int)((rows + kw - 1) / kw);
+      if ((int64_t)slices * w.M * w.N > net->part_len) return net->fail(SFM_EINVAL, "partial-sum buffer too small");
+      CNN_TRY(launch_gemm(w, kw, st));
+      hipLaunchKernelGGL(sum_slices_kernel, dim3(blocks_for(w.M * w.N)), dim3(256), 0, st, net->part, slices,
+                         w.M * w.N, g + net->off_W[l]);
+      CNN_TRY(hipGetLastError());
+      sfm_status rc = column_sums(net, net->dact[l + 1], net->act[l + 1], rows, net->ch, g + net->off_b[l], st);
+      if (rc != SFM_OK) return rc;
+    }
+    if (l > 0 || dx) {            // gradient of this layer's input (the net's input for l = 0)
       ConvBwdData d{};
       d.M = (int64_t)B * n * n * n;
       d.N = ci;
@@ -521,7 +536,7 @@ sfm_status backward_pass(sfm_cnn net, const float* dy, int B, float* g, hipStrea
       d.dact = net->dact[l + 1];
       d.act = net->act[l + 1];
       d.W = net->params + net->off_W[l];
-      d.dx = net->dact[l];
+      d.dx = l > 0 ? net->dact[l] : dx;
       d.gi = Grid3{n};
       d.go = Grid3{m};
       d.co = net->ch;
@@ -697,7 +712,24 @@ sfm_status sfm_cnn_backward(sfm_cnn net, const float* dy_dev, float* grad_dev, v
   net->err.clear();
   if (net->last_batch < 1) return net->fail(SFM_ESTATE, "call sfm_cnn_forward first");
   if (!dy_dev || !grad_dev) return net->fail(SFM_EINVAL, "dy_dev and grad_dev are required");
-  return backward_pass(net, dy_dev, net->last_batch, grad_dev, reinterpret_cast<hipStream_t>(stream));
+  return backward_pass(net, dy_dev, net->last_batch, grad_dev, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+sfm_status sfm_cnn_input_grad(sfm_cnn net, const float* dy_dev, float* dx_dev, void* stream) {
+  if (!net) return SFM_EINVAL;
+  net->err.clear();
+  if (net->last_batch < 1) return net->fail(SFM_ESTATE, "call sfm_cnn_forward first");
+  if (!dy_dev || !dx_dev) return net->fail(SFM_EINVAL, "dy_dev and dx_dev are required");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const float* dy = dy_dev;
+  if (net->scaled) {             // y = mean + sd * (net output)
+    const int64_t ny = (int64_t)net->last_batch * net->n_out;
+    hipLaunchKernelGGL(scale_grad_kernel, dim3(blocks_for(ny)), dim3(256), 0, st, dy_dev, (int64_t)net->last_batch,
+                       (int64_t)net->n_out, net->out_sd, net->dy);
+    CNN_TRY(hipGetLastError());
+    dy = net->dy;
+  }
+  return backward_pass(net, dy, net->last_batch, nullptr, dx_dev, st);
 }
 
 sfm_status sfm_cnn_train(sfm_cnn net, const float* x_dev, const float* target_dev, int64_t n_samples,
@@ -736,7 +768,7 @@ sfm_status sfm_cnn_train(sfm_cnn net, const float* x_dev, const float* target_de
       const unsigned lb = blocks_for(ny);
       hipLaunchKernelGGL(mse_kernel, dim3(lb), dim3(256), 0, st, net->y, net->tgt, ny, net->dy, net->loss_part);
       CNN_TRY(hipGetLastError());
-      rc = backward_pass(net, net->dy, batch, net->grads, st);
+      rc = backward_pass(net, net->dy, batch, net->grads, nullptr, st);
       if (rc != SFM_OK) return rc;
       ++net->adam_t;
       const float c1 = 1.f - std::pow(0.9f, (float)net->adam_t), c2 = 1.f - std::pow(0.999f, (float)net->adam_t);

@@ -224,6 +224,58 @@ struct Buf {
   }
 };
 
+// Gradient with respect to the network outputs of subdomains s0 .. s0 + nb - 1 from the block
+// gradients gg / gh ([S][k][p][p], Gamma_j / Gamma-hat_j): an upper-triangle output sets both
+// (i, l) and (l, i) of its block, so it collects both entries' gradients; Gamma-hat_1 (taken from
+// Lanczos, not from the network) collects none.
+__global__ void output_grad_kernel(const double* __restrict__ gg, const double* __restrict__ gh, int s0, int nb, int k,
+                                   int p, const int32_t* __restrict__ ti, const int32_t* __restrict__ tj,
+                                   float* __restrict__ dy) {
+  const int64_t ntri = (int64_t)p * (p + 1) / 2, per = 2LL * k * ntri, total = (int64_t)nb * per;
+  const int64_t pp = (int64_t)p * p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = idx / per, r = idx - b * per;
+    const int64_t blk = r / ntri, e = r - blk * ntri;
+    const bool hat = blk >= k;
+    const int j = (int)(hat ? blk - k : blk);
+    const int i = ti[e], l = tj[e];
+    double v = 0.0;
+    if (!(hat && j == 0)) {
+      const double* G = (hat ? gh : gg) + ((s0 + b) * k + j) * pp;
+      v = i == l ? G[(int64_t)i * p + i] : G[(int64_t)i * p + l] + G[(int64_t)l * p + i];
+    }
+    dy[idx] = (float)v;
+  }
+}
+
+// dJ/dc at every node: the input gradients of all subdomain boxes that hold the node (up to 8 on
+// shared corners), times d log(c / 3000) / dc = 1 / c.  Equal cubic boxes of n cells; box b along
+// an axis holds nodes b n .. (b + 1) n.
+__global__ void velocity_gather_kernel(const float* __restrict__ dx, const float* __restrict__ vel, int ncx, int ncy,
+                                       int ncz, int n, float* __restrict__ out) {
+  const int nbx = ncx / n, nby = ncy / n, nbz = ncz / n, nn = n + 1;
+  const int64_t nx = ncx + 1, ny = ncy + 1, total = nx * ny * (ncz + 1), per = (int64_t)nn * nn * nn;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int ix = (int)(e % nx), iy = (int)((e / nx) % ny), iz = (int)(e / (nx * ny));
+    int bx[2], by[2], bz[2], cx = 0, cy = 0, cz = 0;
+    if (ix / n < nbx) bx[cx++] = ix / n;
+    if (ix % n == 0 && ix > 0) bx[cx++] = ix / n - 1;
+    if (iy / n < nby) by[cy++] = iy / n;
+    if (iy % n == 0 && iy > 0) by[cy++] = iy / n - 1;
+    if (iz / n < nbz) bz[cz++] = iz / n;
+    if (iz % n == 0 && iz > 0) bz[cz++] = iz / n - 1;
+    float acc = 0.f;
+    for (int a = 0; a < cz; ++a)
+      for (int b = 0; b < cy; ++b)
+        for (int c = 0; c < cx; ++c) {
+          const int64_t s = ((int64_t)bz[a] * nby + by[b]) * nbx + bx[c];
+          const int lz = iz - bz[a] * n, ly = iy - by[b] * n, lx = ix - bx[c] * n;
+          acc += dx[s * per + ((int64_t)lz * nn + ly) * nn + lx];
+        }
+    out[e] = acc / vel[e];
+  }
+}
+
 bool uniform_boxes(const Topology& t, int* cells) {
   int w[3];
   t.cells(0, w);
@@ -423,6 +475,64 @@ sfm_status sfm_build_roms_surrogate(sfm_ctx c, sfm_cnn net, double tol, double f
     seconds[2] = secs(t2, t3);   // NtD judge
     seconds[3] = secs(t3, t4);   // accept and repack
   }
+  return SFM_OK;
+}
+
+sfm_status sfm_surrogate_velocity_gradient(sfm_ctx c, sfm_cnn net, const float* vel_dev, const double* grad_gamma,
+                                           const double* grad_gamma_hat, float* grad_vel_dev, void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!net) return c->fail(SFM_EINVAL, "net is NULL");
+  if (!vel_dev || !grad_gamma || !grad_gamma_hat || !grad_vel_dev)
+    return c->fail(SFM_EINVAL, "vel_dev, grad_gamma, grad_gamma_hat and grad_vel_dev are required");
+  const Topology& t = c->topo;
+  int cells = 0;
+  if (!uniform_boxes(t, &cells)) return c->fail(SFM_EINVAL, "the surrogate needs equal cubic subdomains");
+  int32_t dims[4] = {};
+  sfm_cnn_info(net, nullptr, nullptr, nullptr, dims);
+  const int p = t.p, k = t.k;
+  const int64_t ntri = (int64_t)p * (p + 1) / 2, n_out = 2LL * k * ntri;
+  if (dims[0] != cells + 1) return c->fail(SFM_EINVAL, "network input size differs from the subdomain nodes");
+  if (dims[2] != n_out) return c->fail(SFM_EINVAL, "network output size differs from 2k p(p+1)/2");
+  SG_TRY(hipSetDevice(c->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t nin3 = (int64_t)(cells + 1) * (cells + 1) * (cells + 1);
+  const size_t ng = (size_t)t.S * k * p * p;
+  const int32_t maxb = dims[3];
+  std::vector<int32_t> ti, tj;
+  for (int i = 0; i < p; ++i)
+    for (int j = i; j < p; ++j) {
+      ti.push_back(i);
+      tj.push_back(j);
+    }
+  Buf b(c);
+  double* gg = b.get<double>(ng);
+  double* gh = b.get<double>(ng);
+  float* x = b.get<float>((size_t)t.S * nin3);
+  float* dx = b.get<float>((size_t)t.S * nin3);
+  float* dy = b.get<float>((size_t)maxb * n_out);
+  int32_t* ti_d = b.get<int32_t>(ti.size());
+  int32_t* tj_d = b.get<int32_t>(tj.size());
+  if (b.e != hipSuccess) return c->fail(SFM_ENOMEM, "velocity gradient buffers: out of device memory");
+  SG_TRY(hipMemcpyAsync(gg, grad_gamma, ng * sizeof(double), hipMemcpyHostToDevice, st));
+  SG_TRY(hipMemcpyAsync(gh, grad_gamma_hat, ng * sizeof(double), hipMemcpyHostToDevice, st));
+  SG_TRY(hipMemcpyAsync(ti_d, ti.data(), ti.size() * 4, hipMemcpyHostToDevice, st));
+  SG_TRY(hipMemcpyAsync(tj_d, tj.data(), tj.size() * 4, hipMemcpyHostToDevice, st));
+  sfm_status rc = sfm_rom_inputs(c, vel_dev, x, stream);
+  if (rc != SFM_OK) return rc;
+  for (int s0 = 0; s0 < t.S; s0 += maxb) {
+    const int nb = std::min<int>(maxb, t.S - s0);
+    rc = sfm_cnn_forward(net, x + (int64_t)s0 * nin3, nb, nullptr, stream);
+    if (rc != SFM_OK) return c->fail(rc, std::string("surrogate forward: ") + sfm_cnn_last_error(net));
+    hipLaunchKernelGGL(output_grad_kernel, dim3(2048), dim3(256), 0, st, gg, gh, s0, nb, k, p, ti_d, tj_d, dy);
+    SG_TRY(hipGetLastError());
+    rc = sfm_cnn_input_grad(net, dy, dx + (int64_t)s0 * nin3, stream);
+    if (rc != SFM_OK) return c->fail(rc, std::string("surrogate input gradient: ") + sfm_cnn_last_error(net));
+  }
+  hipLaunchKernelGGL(velocity_gather_kernel, dim3(4096), dim3(256), 0, st, dx, vel_dev, t.ncell[0], t.ncell[1],
+                     t.ncell[2], cells, grad_vel_dev);
+  SG_TRY(hipGetLastError());
+  SG_TRY(hipStreamSynchronize(st));
   return SFM_OK;
 }
 

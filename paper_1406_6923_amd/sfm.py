@@ -74,6 +74,8 @@ SIGNATURES = {
     "sfm_cnn_params": (_I32, [_VP, _VP, _VP]),
     "sfm_cnn_forward": (_I32, [_VP, _VP, _I32, _VP, _VP]),
     "sfm_cnn_backward": (_I32, [_VP, _VP, _VP, _VP]),
+    "sfm_cnn_input_grad": (_I32, [_VP, _VP, _VP, _VP]),
+    "sfm_surrogate_velocity_gradient": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "sfm_cnn_fit_scale": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP]),
     "sfm_cnn_train": (_I32, [_VP, _VP, _VP, _I64, _I32, _I32, ctypes.c_float, ctypes.c_uint64, _VP, _VP]),
     "sfm_create_boxes": (_I32, [ctypes.POINTER(sfm_config), _VP, _VP, ctypes.POINTER(_VP)]),
@@ -483,6 +485,10 @@ class Cnn:
     def backward(self, dy, grad, stream=None) -> None:
         _cnn_check(self.net, load_library().sfm_cnn_backward(self.net, _dev(dy), _dev(grad), _stream(stream)))
 
+    def input_grad(self, dy, dx, stream=None) -> None:
+        """dx = gradient of sum(dy * y) with respect to the inputs of the last forward pass."""
+        _cnn_check(self.net, load_library().sfm_cnn_input_grad(self.net, _dev(dy), _dev(dx), _stream(stream)))
+
     def fit_scale(self, target, stream=None):
         mean = np.empty(self.n_out, np.float32)
         sd = np.empty(self.n_out, np.float32)
@@ -510,6 +516,20 @@ def sfm_ntd_error(ctx: int, coef, f_peak: float, stream=None) -> np.ndarray:
     err = np.empty(sfm_query(ctx)["n_subdomains"], np.float64)
     _check(ctx, load_library().sfm_ntd_error(ctx, _dev(coef), float(f_peak), _ptr(err), _stream(stream)))
     return err
+
+
+def sfm_surrogate_velocity_gradient(ctx: int, net: "Cnn", vel, grad_gamma, grad_gamma_hat, grad_vel,
+                                    stream=None) -> None:
+    """grad_vel (device, nodes as vel) = dJ/dc through the network, from the block gradients
+    grad_gamma / grad_gamma_hat (host float64 [S][k][p][p], as sfm_adjoint_gradient returns them)."""
+    gg = _host(grad_gamma, np.float64)
+    gh = _host(grad_gamma_hat, np.float64)
+    info = sfm_query(ctx)
+    need = info["n_subdomains"] * info["k"] * info["p"] ** 2
+    if gg.size != need or gh.size != need:
+        raise ValueError(f"block gradients need {need} entries each")
+    _check(ctx, load_library().sfm_surrogate_velocity_gradient(ctx, net.net, _dev(vel), _ptr(gg), _ptr(gh),
+                                                               _dev(grad_vel), _stream(stream)))
 
 
 def sfm_build_roms_surrogate(ctx: int, net: "Cnn", tol: float, f_peak: float, vel, src_ijk=None, rec_ijk=None,

@@ -126,3 +126,22 @@ def test_cnn_errors():
         net.forward(torch.zeros((3, N_IN, N_IN, N_IN), device="cuda"))
     assert ei.value.status == sfm.SFM_EINVAL
     net.close()
+
+
+def test_cnn_input_gradient_matches_oracle():
+    print("[case] cnn input gradient, scaled outputs", flush=True)
+    net, flat, params, x = _setup(seed=2)
+    rng = np.random.default_rng(11)
+    tgt = (rng.standard_normal((20, N_OUT)) * rng.uniform(0.1, 3.0, N_OUT) + rng.standard_normal(N_OUT))
+    mean, sd = net.fit_scale(torch.from_numpy(tgt.astype(np.float32)).cuda())
+    dy = rng.standard_normal((B, N_OUT)).astype(np.float32)
+    net.forward(torch.from_numpy(x).cuda())
+    dx_d = torch.zeros((B, N_IN, N_IN, N_IN), dtype=torch.float32, device="cuda")
+    net.input_grad(torch.from_numpy(dy).cuda(), dx_d)
+    torch.cuda.synchronize()
+    dye = dy.astype(np.float64) * sd.astype(np.float64)       # gradient carried to the unscaled output
+    _, acts_x = cnn.forward(params, x)
+    _, acts_q = cnn.forward(params, x, q=cnn.bf16)
+    _compare(dx_d.cpu().numpy(), cnn.input_gradient(params, acts_q, dye, q=cnn.bf16),
+             cnn.input_gradient(params, acts_x, dye), "input gradient")
+    net.close()

@@ -9,7 +9,9 @@
 * a trained network on the 32^3 parity grid's split (16^3-cell boxes, m = 4, k = 8): trained on
   the ROMs of 400 subdomains of seeded layered / lognormal / blob media, applied to unseen media;
   every accepted subdomain's NtD error (re-evaluated by the oracle) is within tol, every rejected
-  one keeps the exact Lanczos blocks, and the report states what the network achieved.
+  one keeps the exact Lanczos blocks, and the report states what the network achieved;
+* the sound-speed gradient through the network against the oracle chain (``oracle.surrogate``)
+  with the same bfloat16 operand rounding, on the 32^3 grid's 2 x 2 x 2 boxes in ragged batches.
 """
 import numpy as np
 import pytest
@@ -158,3 +160,39 @@ def test_trained_surrogate_on_unseen_media():
         h.close()
         href.close()
     net.close()
+
+
+def test_velocity_gradient_matches_oracle():
+    from paper_1406_6923_amd import sfm
+    from oracle import cnn, surrogate
+    from tests.cases import rel_l2
+    print("[case] sound-speed gradient through the surrogate, 32^3 grid, batches 3 + 3 + 2", flush=True)
+    cfg = W.CFG_SMALL
+    rng = np.random.default_rng(21)
+    c = (cfg.velocity_model() * (1.0 + 0.05 * rng.standard_normal(tuple(n + 1 for n in cfg.ncell)[::-1])))
+    c = c.astype(np.float32)
+    S, k, p, n = 8, cfg.k, cfg.p, cfg.sub_cells[0]
+    ntri = p * (p + 1) // 2
+    h = _ctx(cfg)
+    net = sfm.Cnn(n + 1, 8, 2 * k * ntri, max_batch=3, seed=5)
+    flat = (rng.standard_normal(net.n_params) * 0.1).astype(np.float32)
+    net.set_params(flat)
+    tgt = rng.standard_normal((16, 2 * k * ntri)) * rng.uniform(0.1, 2.0, 2 * k * ntri)
+    mean, sd = net.fit_scale(torch.from_numpy(tgt.astype(np.float32)).cuda())
+    gg = rng.standard_normal((S, k, p, p))
+    gh = rng.standard_normal((S, k, p, p))
+    gg, gh = gg + np.swapaxes(gg, -1, -2), gh + np.swapaxes(gh, -1, -2)
+    out = torch.zeros(c.shape, dtype=torch.float32, device="cuda")
+    sfm.sfm_surrogate_velocity_gradient(h.ctx, net, torch.from_numpy(c).cuda(), gg, gh, out)
+    got = out.cpu().numpy()
+    params = cnn.unflatten(flat.astype(np.float64), n + 1, 8, 2 * k * ntri)
+    c64, m64, s64 = c.astype(np.float64), mean.astype(np.float64), sd.astype(np.float64)
+    ref_q = surrogate.velocity_gradient(params, c64, n, gg, gh, m64, s64, q=cnn.bf16)
+    ref_x = surrogate.velocity_gradient(params, c64, n, gg, gh, m64, s64)
+    delta = rel_l2(ref_q, ref_x)
+    e_q, e_x = rel_l2(got, ref_q), rel_l2(got, ref_x)
+    print(f"velocity gradient: device vs bf16-operand oracle {e_q:.2e}, vs exact oracle {e_x:.2e}, delta {delta:.2e}")
+    assert np.isfinite(got).all()
+    assert e_q < max(0.1 * delta, 1e-5) and e_x < max(2.0 * delta, 1e-5), (e_q, e_x, delta)
+    net.close()
+    h.close()

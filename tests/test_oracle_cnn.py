@@ -96,3 +96,22 @@ def test_bf16_rounding():
     np.testing.assert_array_equal(cnn.bf16(x), ref)
     assert cnn.bf16(np.array([1.0 + 2 ** -8]))[0] == 1.0               # tie -> even (down)
     assert cnn.bf16(np.array([1.0 + 3 * 2 ** -8]))[0] == 1.0 + 2 ** -6  # tie -> even (up)
+
+
+def test_input_gradient_matches_central_differences():
+    n_in, ch, n_out = 9, 3, 5
+    params = _random_params(n_in, ch, n_out, seed=6)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((2, n_in, n_in, n_in))
+    dy = rng.standard_normal((2, n_out))
+    _, acts = cnn.forward(params, x)
+    g = cnn.input_gradient(params, acts, dy)
+    assert g.shape == x.shape
+    eps = 1e-6
+    for i in rng.choice(x.size, size=12, replace=False):
+        xp, xm = x.copy().reshape(-1), x.copy().reshape(-1)
+        xp[i] += eps
+        xm[i] -= eps
+        fd = (np.sum(dy * cnn.forward(params, xp.reshape(x.shape))[0])
+              - np.sum(dy * cnn.forward(params, xm.reshape(x.shape))[0])) / (2 * eps)
+        assert abs(fd - g.reshape(-1)[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g.reshape(-1)[i])
