@@ -430,6 +430,13 @@ sfm_status sfm_rom_targets(sfm_ctx ctx, float* t_dev, void* stream);
  * Requires 6m <= 64.  Synchronizes. */
 sfm_status sfm_ntd_error(sfm_ctx ctx, const double* coef_dev, double f_peak, double* err_host, void* stream);
 
+/* The network's blocks for every subdomain: coef_dev (device double [S][2][k][p][p], Gamma then
+ * Gamma-hat, symmetric) from the predicted upper triangles of each subdomain's sound speed in
+ * vel_dev (as sfm_build_roms), with Gamma-hat_1 (the face masses) copied from the current ROMs.
+ * Errors: SFM_ESTATE (no ROMs), SFM_EINVAL (sizes as sfm_build_roms_surrogate, NULL pointers),
+ * SFM_ENOMEM, SFM_EHIP.  Synchronizes. */
+sfm_status sfm_surrogate_predict(sfm_ctx ctx, sfm_cnn net, const float* vel_dev, double* coef_dev, void* stream);
+
 /* Learned ROM build: block Lanczos ROMs of every subdomain (as sfm_build_roms without initial
  * conditions; they judge and back up the network), the network's predictions of every
  * subdomain's blocks (Gamma-hat_1, the face masses, always taken from Lanczos), the NtD judge

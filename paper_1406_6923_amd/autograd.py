@@ -8,6 +8,14 @@ blocks (torch.autograd), backed by the library's forward step and its discrete a
 
 Sources, receivers and their projections are held fixed; so are the face masses (Gamma-hat_1:
 its gradient is returned as zero).  Every call runs on the GPU through libsfm.
+
+The blocks can come from the learned surrogate, which makes the sound speed the variable:
+
+    gamma, gamma_hat = surrogate_blocks(vel, net, handle)   # vel: device float32 nodes, requires_grad
+    loss = 0.5 * ((rom_traces(gamma, gamma_hat, model) - observed) ** 2).sum()
+    loss.backward()                                         # vel.grad through the network
+
+(Gamma-hat_1 is taken from the ROMs the handle holds when surrogate_blocks runs.)
 """
 from __future__ import annotations
 
@@ -65,3 +73,34 @@ class _RomTracesFn(torch.autograd.Function):
 def rom_traces(gamma: torch.Tensor, gamma_hat: torch.Tensor, model: RomTraces) -> torch.Tensor:
     """Traces [nrec][nsteps] (device, float32) of the ROMs with the given blocks."""
     return _RomTracesFn.apply(gamma, gamma_hat, model)
+
+
+class _SurrogateBlocksFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, vel, net, handle):
+        info = sfm.sfm_query(handle.ctx)
+        S, k, p = info["n_subdomains"], info["k"], info["p"]
+        v = vel.detach().to(torch.float32).contiguous()
+        coef = torch.empty((S, 2, k, p, p), dtype=torch.float64, device=v.device)
+        sfm.sfm_surrogate_predict(handle.ctx, net, v, coef)
+        ctx.net, ctx.handle = net, handle
+        ctx.save_for_backward(v)
+        blocks = coef.cpu()
+        return blocks[:, 0].contiguous(), blocks[:, 1].contiguous()
+
+    @staticmethod
+    def backward(ctx, g_gam, g_hat):
+        (v,) = ctx.saved_tensors
+        info = sfm.sfm_query(ctx.handle.ctx)
+        shape = (info["n_subdomains"], info["k"], info["p"], info["p"])
+        gg = np.zeros(shape) if g_gam is None else g_gam.detach().cpu().numpy().astype(np.float64)
+        gh = np.zeros(shape) if g_hat is None else g_hat.detach().cpu().numpy().astype(np.float64)
+        grad = torch.zeros_like(v)
+        sfm.sfm_surrogate_velocity_gradient(ctx.handle.ctx, ctx.net, v, gg, gh, grad)
+        return grad, None, None
+
+
+def surrogate_blocks(vel: torch.Tensor, net: sfm.Cnn, handle: sfm.Sfm):
+    """(gamma, gamma_hat), CPU float64 [S][k][p][p], predicted by ``net`` from the sound speed
+    ``vel`` (device float32 nodes), differentiable with respect to ``vel``."""
+    return _SurrogateBlocksFn.apply(vel, net, handle)

@@ -387,6 +387,41 @@ sfm_status sfm_ntd_error(sfm_ctx c, const double* coef_dev, double f_peak, doubl
   return SFM_OK;
 }
 
+sfm_status sfm_surrogate_predict(sfm_ctx c, sfm_cnn net, const float* vel_dev, double* coef_dev, void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (!net) return c->fail(SFM_EINVAL, "net is NULL");
+  if (!vel_dev || !coef_dev) return c->fail(SFM_EINVAL, "vel_dev and coef_dev are required");
+  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs: Gamma-hat_1 comes from the current ROMs");
+  const Topology& t = c->topo;
+  int cells = 0;
+  if (!uniform_boxes(t, &cells)) return c->fail(SFM_EINVAL, "the surrogate needs equal cubic subdomains");
+  int32_t dims[4] = {};
+  sfm_cnn_info(net, nullptr, nullptr, nullptr, dims);
+  const int64_t ntri = (int64_t)t.p * (t.p + 1) / 2, n_out = 2LL * t.k * ntri;
+  if (dims[0] != cells + 1) return c->fail(SFM_EINVAL, "network input size differs from the subdomain nodes");
+  if (dims[2] != n_out) return c->fail(SFM_EINVAL, "network output size differs from 2k p(p+1)/2");
+  SG_TRY(hipSetDevice(c->device));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int64_t nin3 = (int64_t)(cells + 1) * (cells + 1) * (cells + 1);
+  Buf b(c);
+  float* x = b.get<float>((size_t)t.S * nin3);
+  float* y = b.get<float>((size_t)t.S * n_out);
+  if (b.e != hipSuccess) return c->fail(SFM_ENOMEM, "surrogate buffers: out of device memory");
+  sfm_status rc = sfm_rom_inputs(c, vel_dev, x, stream);
+  if (rc != SFM_OK) return rc;
+  const int32_t maxb = dims[3];
+  for (int s0 = 0; s0 < t.S; s0 += maxb) {
+    const int nb = std::min<int>(maxb, t.S - s0);
+    rc = sfm_cnn_forward(net, x + (int64_t)s0 * nin3, nb, y + (int64_t)s0 * n_out, stream);
+    if (rc != SFM_OK) return c->fail(rc, std::string("surrogate forward: ") + sfm_cnn_last_error(net));
+  }
+  hipLaunchKernelGGL(unpack_pred_kernel, dim3(4096), dim3(256), 0, st, y, c->coef64_d, t.S, t.k, t.p, coef_dev);
+  SG_TRY(hipGetLastError());
+  SG_TRY(hipStreamSynchronize(st));
+  return SFM_OK;
+}
+
 sfm_status sfm_build_roms_surrogate(sfm_ctx c, sfm_cnn net, double tol, double f_peak, const float* vel_dev,
                                     int32_t nsrc, const int32_t* src_ijk, int32_t nrec, const int32_t* rec_ijk,
                                     int32_t* accepted, double* ntd_err, double* seconds, void* stream) {
@@ -414,24 +449,12 @@ sfm_status sfm_build_roms_surrogate(sfm_ctx c, sfm_cnn net, double tol, double f
   SG_TRY(hipStreamSynchronize(st));
   auto t1 = now();
   // predictions
-  const int64_t nin3 = (int64_t)(cells + 1) * (cells + 1) * (cells + 1);
   const int64_t pp = (int64_t)t.p * t.p;
   Buf b(c);
-  float* x = b.get<float>((size_t)t.S * nin3);
-  float* y = b.get<float>((size_t)t.S * n_out);
   double* pred = b.get<double>((size_t)t.S * 2 * t.k * pp);
   if (b.e != hipSuccess) return c->fail(SFM_ENOMEM, "surrogate buffers: out of device memory");
-  rc = sfm_rom_inputs(c, vel_dev, x, stream);
+  rc = sfm_surrogate_predict(c, net, vel_dev, pred, stream);
   if (rc != SFM_OK) return rc;
-  const int32_t maxb = dims[3];
-  for (int s0 = 0; s0 < t.S; s0 += maxb) {
-    const int nb = std::min<int>(maxb, t.S - s0);
-    rc = sfm_cnn_forward(net, x + (int64_t)s0 * nin3, nb, y + (int64_t)s0 * n_out, stream);
-    if (rc != SFM_OK) return c->fail(rc, std::string("surrogate forward: ") + sfm_cnn_last_error(net));
-  }
-  hipLaunchKernelGGL(unpack_pred_kernel, dim3(4096), dim3(256), 0, st, y, c->coef64_d, t.S, t.k, t.p, pred);
-  SG_TRY(hipGetLastError());
-  SG_TRY(hipStreamSynchronize(st));
   auto t2 = now();
   std::vector<double> err((size_t)t.S);
   rc = sfm_ntd_error(c, pred, f_peak, err.data(), stream);

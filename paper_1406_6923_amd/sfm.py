@@ -76,6 +76,7 @@ SIGNATURES = {
     "sfm_cnn_backward": (_I32, [_VP, _VP, _VP, _VP]),
     "sfm_cnn_input_grad": (_I32, [_VP, _VP, _VP, _VP]),
     "sfm_surrogate_velocity_gradient": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "sfm_surrogate_predict": (_I32, [_VP, _VP, _VP, _VP, _VP]),
     "sfm_cnn_fit_scale": (_I32, [_VP, _VP, _I64, _VP, _VP, _VP]),
     "sfm_cnn_train": (_I32, [_VP, _VP, _VP, _I64, _I32, _I32, ctypes.c_float, ctypes.c_uint64, _VP, _VP]),
     "sfm_create_boxes": (_I32, [ctypes.POINTER(sfm_config), _VP, _VP, ctypes.POINTER(_VP)]),
@@ -516,6 +517,11 @@ def sfm_ntd_error(ctx: int, coef, f_peak: float, stream=None) -> np.ndarray:
     err = np.empty(sfm_query(ctx)["n_subdomains"], np.float64)
     _check(ctx, load_library().sfm_ntd_error(ctx, _dev(coef), float(f_peak), _ptr(err), _stream(stream)))
     return err
+
+
+def sfm_surrogate_predict(ctx: int, net: "Cnn", vel, coef, stream=None) -> None:
+    """coef (device float64 [S][2][k][p][p]) = the network's blocks, Gamma-hat_1 from the current ROMs."""
+    _check(ctx, load_library().sfm_surrogate_predict(ctx, net.net, _dev(vel), _dev(coef), _stream(stream)))
 
 
 def sfm_surrogate_velocity_gradient(ctx: int, net: "Cnn", vel, grad_gamma, grad_gamma_hat, grad_vel,

@@ -94,6 +94,86 @@ def test_adjoint_autograd_function():
     h.close()
 
 
+def test_velocity_gradient_through_surrogate_autograd():
+    """Sound speed -> network blocks -> traces -> misfit, differentiated by torch.autograd through
+    the library's adjoint and the network's input gradient; reference: the oracle adjoint at the
+    oracle network's blocks, then the oracle chain to the sound speed (bf16 operands as the device)."""
+    from paper_1406_6923_amd import sfm
+    from paper_1406_6923_amd.autograd import RomTraces, rom_traces, surrogate_blocks
+    from oracle import cnn, surrogate
+    print("[case] autograd: sound speed -> surrogate blocks -> traces, small case, 100 steps", flush=True)
+    cfg, c, subs, roms, cs = oracle_case("small")
+    gam, hat, src, rec = rom_arrays(cs)
+    S, k, p, n = len(subs), cfg.k, cfg.p, cfg.sub_cells[0]
+    ntri = p * (p + 1) // 2
+    iu = np.triu_indices(p)
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
+    sfm.sfm_load_roms(h.ctx, gam, hat, cfg.sources(), src, cfg.receivers(), rec)
+    # a network whose prediction is a valid ROM: the subdomain average of the Lanczos blocks (SPD)
+    # plus a small input-dependent part, through the output scale (one mean and sd per output,
+    # shared by all subdomains): mean = the average triangles, sd = 1e-3 of each block's largest entry
+    rng = np.random.default_rng(31)
+    net = sfm.Cnn(n + 1, 8, 2 * k * ntri, max_batch=3, seed=9)
+    flat = (rng.standard_normal(net.n_params) * 0.1).astype(np.float32)
+    net.set_params(flat)
+    gbar, hbar = gam.mean(axis=0), hat.mean(axis=0)
+    t = np.concatenate([b[iu] for b in list(gbar) + list(hbar)])
+    amp = np.concatenate([np.full(ntri, 1e-3 * np.abs(b).max()) for b in list(gbar) + list(hbar)])
+    mean, sd = net.fit_scale(torch.from_numpy(np.stack([t + amp, t - amp]).astype(np.float32)).cuda())
+    params = cnn.unflatten(flat.astype(np.float64), n + 1, 8, 2 * k * ntri)
+    m64, s64 = mean.astype(np.float64), sd.astype(np.float64)
+    y, _ = surrogate.predict(params, surrogate.box_inputs(c, n), m64, s64, q=cnn.bf16)
+    pred = [surrogate.blocks_from_output(y[a], k, p) for a in range(S)]
+    dg = [pg - gam[a] for a, (pg, _) in enumerate(pred)]
+    dh = [ph - hat[a] for a, (_, ph) in enumerate(pred)]
+    cs_p = adjoint.perturbed_system(cs, dg, dh, 1.0)      # Gamma-hat_1 stays the Lanczos one
+    nsteps = 100
+    dt = 0.8 * cs_p.cfl_dt()
+    wav = W.ricker(cfg.f_peak, dt, nsteps)[:, None]
+    traces_ref, _ = adjoint.forward(cs_p, dt, wav)
+    observed = 0.8 * traces_ref
+    model = RomTraces(h, cfg.sources(), src, cfg.receivers(), rec, dt,
+                      torch.tensor(wav, dtype=torch.float32, device="cuda"), nsteps, checkpoint_every=40)
+    vel = torch.tensor(c.astype(np.float32), device="cuda", requires_grad=True)
+    g, gh = surrogate_blocks(vel, net, h)
+    g.retain_grad()
+    gh.retain_grad()
+    loss = 0.5 * ((rom_traces(g, gh, model) - torch.tensor(observed, dtype=torch.float32, device="cuda")) ** 2).sum()
+    loss.backward()
+    got = vel.grad.cpu().numpy()
+    # the network's blocks
+    ref_g = np.stack([pg for pg, _ in pred])
+    ref_h = np.stack([ph for _, ph in pred])
+    ref_h[:, 0] = hat[:, 0]
+    assert rel_l2(g.detach().numpy(), ref_g) < 1e-6 and rel_l2(gh.detach().numpy(), ref_h) < 1e-6
+    # the block gradients: the oracle adjoint at the network's blocks (FP32 adjoint bar)
+    J, r_gam, r_hat = adjoint.gradient(cs_p, dt, wav, observed)
+    d_gam, d_hat = g.grad.numpy(), gh.grad.numpy()
+    e_blk = max(rel_l2(d_gam, r_gam), rel_l2(d_hat[:, 1:], r_hat[:, 1:]))
+    # the chain to the sound speed: the oracle chain fed the device's own block gradients (bf16
+    # operands as the device: within a tenth of the bf16 effect), and end to end from the oracle's
+    # block gradients.  bf16 rounding is discontinuous: block gradients that differ at the FP32
+    # adjoint's 1e-6 level round some small dy entries to the other neighbour, which moves the
+    # bf16 chain by up to a few 1e-3 (the exact chain moves by 1e-5), so the end-to-end bar is the
+    # bf16 effect itself.
+    chain_q = surrogate.velocity_gradient(params, c, n, d_gam, d_hat, m64, s64, q=cnn.bf16)
+    chain_x = surrogate.velocity_gradient(params, c, n, d_gam, d_hat, m64, s64)
+    delta = rel_l2(chain_q, chain_x)
+    e_chain = rel_l2(got, chain_q)
+    ref_x = surrogate.velocity_gradient(params, c, n, r_gam, r_hat, m64, s64)
+    e_end = rel_l2(got, ref_x)
+    print(f"autograd through the surrogate: loss {loss.item():.6e} (oracle {J:.6e}); block gradients rel-L2 "
+          f"{e_blk:.2e}; sound-speed gradient vs the oracle chain on the device's block gradients {e_chain:.2e} "
+          f"(bf16 effect {delta:.2e}), end to end vs the exact oracle {e_end:.2e}")
+    assert abs(loss.item() - J) < 1e-4 * J
+    assert np.isfinite(got).all()
+    assert e_blk < 1e-4
+    assert e_chain < max(0.1 * delta, 1e-5), (e_chain, delta)
+    assert e_end < 2.0 * delta, (e_end, delta)
+    net.close()
+    h.close()
+
+
 def test_adjoint_errors():
     from paper_1406_6923_amd import sfm
     cfg, c, subs, roms, cs = oracle_case("small")
