@@ -6,9 +6,11 @@
 //      each boundary node owned by one face, interface faces first).  Because the patch
 //      functions do not overlap, F^T F = diag(H) and Q_1 = F diag(H)^{-1/2}, B_1 = diag(H^{1/2}).
 //  a2  block Lanczos on (A_+, F) (polynomial Krylov space, the combined steps 1.1 + 1.2 of
-//      Algorithm 1): W = A_+ Q_j, two passes of classical Gram-Schmidt against all blocks
-//      so far (A_j from the projection coefficients), then two passes of Cholesky QR,
-//      W = Q_{j+1} B_{j+1} with B upper triangular, all in FP64.
+//      Algorithm 1): W = A_+ Q_j, the three-term recurrence (W -= Q_j A_j + Q_{j-1} B_j^T),
+//      one pass of classical Gram-Schmidt against all blocks so far (full
+//      reorthogonalisation: after the recurrence only rounding drift is left, so this pass
+//      is the second pass of a CGS2 for the two latest blocks; A_j gets its correction), then
+//      two passes of Cholesky QR, W = Q_{j+1} B_{j+1} with B upper triangular, all in FP64.
 //  a3  S-fraction (eq. "GammaTrans"), FP64, with G_1 = B_1^T and
 //        Gamma-hat_j = G_j G_j^T,  Gamma_j = G_j^{-T} A_j G_j^{-1} - Gamma_{j-1},
 //        G_{j+1} = -Gamma_j^{-1} G_j^{-T} B_{j+1}^T,  G_{j+1}^{-1} = -B_{j+1}^{-T} G_j^T Gamma_j
@@ -835,7 +837,8 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
     B_LAUNCH(init_q1_kernel, (int64_t)nb * N * p, g, Sd, mask_d, Hb, N, kp, nb, Z);
     B_LAUNCH(diag_kernel, (int64_t)nb * pp, Hb, p, nb, Bt, (int64_t)k * pp, 0);   // B_1^T = diag(H^{1/2})
 
-    // a2: block Lanczos with two-pass CGS and two-pass Cholesky QR on a basis Zb of `rows` rows
+    // a2: block Lanczos (three-term recurrence + one full CGS pass) and two-pass Cholesky QR on a
+    // basis Zb of `rows` rows
     // (node-major, ld kp).  apply(jj, W, ldw, sW) writes the operator applied to block jj.
     // Steps jj < nsteps; the step jj = k - 1 only forms A_k.
     auto lanczos = [&](double* Zb, int64_t rows, int nsteps, const double* thrp, auto&& apply) -> sfm_status {
@@ -848,19 +851,30 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
         const sfm_status ra = apply(jj, W, ldw, sW);
         if (ra != SFM_OK) return ra;
         const int nprev = (jj + 1) * p;
-        // C1 = Zb_{1..j}^T W  (column-major p x nprev, C1[r + c p] = (Z^T W)[c][r])
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, nprev, (int)rows, &one, W, ldw, sW, Zb, kp, sZb, &zero,
-                                                 C1, p, (int64_t)kp * p, nb));
+        // Projection coefficients in column-major p x ncols form: C[r + c p] = (Z^T W)[c][r];
+        // W -= Z C is then the product C (p x ncols) Z^T on the node-major W.
+        // Three-term recurrence first: C2 block j = Q_j^T W, W -= Q_j C2_j (and, from the second
+        // block on, W -= Q_{j-1} B_j^T with B_j from the previous step's QR), then one pass of
+        // classical Gram-Schmidt against every block so far (C1), which removes only the rounding
+        // drift left after the recurrence; A_j = sym(C2_j + C1_j).
+        double* C2j = C2 + (int64_t)jj * p * p;
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, p, (int)rows, &one, W, ldw, sW, Zb + (int64_t)jj * p, kp,
+                                                 sZb, &zero, last ? C1 + (int64_t)jj * p * p : C2j, p,
+                                                 (int64_t)kp * p, nb));
         if (last) {
           B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, (const double*)nullptr, p, (int64_t)kp * p, jj * p,
                    A + (int64_t)jj * pp, (int64_t)k * pp, nb);
           break;
         }
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)rows, nprev, &mone, C1, p, (int64_t)kp * p, Zb, kp,
-                                                 sZb, &one, W, ldw, sW, nb));
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)rows, p, &mone, C2j, p, (int64_t)kp * p,
+                                                 Zb + (int64_t)jj * p, kp, sZb, &one, W, ldw, sW, nb));
+        if (jj > 0)   // Q_{j-1}^T A Q_j = B_j^T: in the C form its transpose, B_j (Bt holds B_j^T column-major)
+          B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, (int)rows, p, &mone, Bt + (int64_t)jj * pp, p,
+                                                   (int64_t)k * pp, Zb + (int64_t)(jj - 1) * p, kp, sZb, &one, W, ldw,
+                                                   sW, nb));
         B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, nprev, (int)rows, &one, W, ldw, sW, Zb, kp, sZb, &zero,
-                                                 C2, p, (int64_t)kp * p, nb));
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)rows, nprev, &mone, C2, p, (int64_t)kp * p, Zb, kp,
+                                                 C1, p, (int64_t)kp * p, nb));
+        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)rows, nprev, &mone, C1, p, (int64_t)kp * p, Zb, kp,
                                                  sZb, &one, W, ldw, sW, nb));
         B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, C2, p, (int64_t)kp * p, jj * p, A + (int64_t)jj * pp,
                  (int64_t)k * pp, nb);
