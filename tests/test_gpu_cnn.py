@@ -123,7 +123,14 @@ def test_cnn_errors():
         net.backward(torch.zeros((2, N_OUT), device="cuda"), torch.zeros(net.n_params, device="cuda"))
     assert ei.value.status == sfm.SFM_ESTATE
     with pytest.raises(sfm.SfmError) as ei:
+        net.input_grad(torch.zeros((2, N_OUT), device="cuda"), torch.zeros((2, N_IN, N_IN, N_IN), device="cuda"))
+    assert ei.value.status == sfm.SFM_ESTATE
+    with pytest.raises(sfm.SfmError) as ei:
         net.forward(torch.zeros((3, N_IN, N_IN, N_IN), device="cuda"))
+    assert ei.value.status == sfm.SFM_EINVAL
+    net.forward(torch.zeros((2, N_IN, N_IN, N_IN), device="cuda"))
+    with pytest.raises(sfm.SfmError) as ei:
+        net.input_grad(torch.zeros((2, N_OUT), device="cuda"), None)
     assert ei.value.status == sfm.SFM_EINVAL
     net.close()
 

@@ -196,3 +196,43 @@ def test_velocity_gradient_matches_oracle():
     assert e_q < max(0.1 * delta, 1e-5) and e_x < max(2.0 * delta, 1e-5), (e_q, e_x, delta)
     net.close()
     h.close()
+
+
+def test_velocity_gradient_and_predict_errors():
+    from paper_1406_6923_amd import sfm
+    print("[case] surrogate gradient / prediction argument errors", flush=True)
+    cfg = W.CFG_SMALL
+    S, k, p, n = 8, cfg.k, cfg.p, cfg.sub_cells[0]
+    ntri = p * (p + 1) // 2
+    h = _ctx(cfg)
+    net = sfm.Cnn(n + 1, 4, 2 * k * ntri, max_batch=2, seed=1)
+    vel = torch.full(tuple(c + 1 for c in cfg.ncell[::-1]), 2000.0, dtype=torch.float32, device="cuda")
+    coef = torch.zeros((S, 2, k, p, p), dtype=torch.float64, device="cuda")
+    with pytest.raises(sfm.SfmError) as ei:                 # Gamma-hat_1 needs ROMs
+        sfm.sfm_surrogate_predict(h.ctx, net, vel, coef)
+    assert ei.value.status == sfm.SFM_ESTATE
+    g = np.zeros((S, k, p, p))
+    out = torch.zeros_like(vel)
+    with pytest.raises(ValueError):                         # block gradients of the wrong size
+        sfm.sfm_surrogate_velocity_gradient(h.ctx, net, vel, g[:, :1], g, out)
+    bad = sfm.Cnn(n + 3, 4, 2 * k * ntri, max_batch=2, seed=1)
+    with pytest.raises(sfm.SfmError) as ei:                 # network input size
+        sfm.sfm_surrogate_velocity_gradient(h.ctx, bad, vel, g, g, out)
+    assert ei.value.status == sfm.SFM_EINVAL
+    bad.close()
+    bad = sfm.Cnn(n + 1, 4, 2 * k * ntri + 1, max_batch=2, seed=1)
+    with pytest.raises(sfm.SfmError) as ei:                 # network output size
+        sfm.sfm_surrogate_velocity_gradient(h.ctx, bad, vel, g, g, out)
+    assert ei.value.status == sfm.SFM_EINVAL
+    bad.close()
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_surrogate_velocity_gradient(h.ctx, net, vel, g, g, None)
+    assert ei.value.status == sfm.SFM_EINVAL
+    h.close()
+    hu = _ctx(cfg, sub=((16, 16), (8, 24), (16, 16)))        # boxes that are not equal cubes
+    gu = np.zeros((sfm.sfm_query(hu.ctx)["n_subdomains"], k, p, p))
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_surrogate_velocity_gradient(hu.ctx, net, vel, gu, gu, out)
+    assert ei.value.status == sfm.SFM_EINVAL
+    hu.close()
+    net.close()
