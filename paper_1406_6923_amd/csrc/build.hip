@@ -18,7 +18,7 @@
 //  a4  projections (eq. "Uj"): s = G Z^T M^{-1/2} e_s, r = e_r^T M^{-1/2} Z G^{-1}, and
 //      U(0) = G Z^T M^{1/2} u0.
 // The reductions run in FP64 on the device; the large dense products (Z^T W, Z C, W^T W and the
-// triangular solves with N right-hand sides) are plain rocBLAS strided-batched DGEMM/DTRSM calls.
+// products with the inverse Cholesky factors) are plain rocBLAS strided-batched DGEMM calls.
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
@@ -443,6 +443,16 @@ __global__ __launch_bounds__(256) void cholesky_kernel(double* __restrict__ A, i
     if (i < j) a[e] = 0.0;
   }
   if (tid == 0 && bad) flag[blockIdx.x] = 1;
+}
+
+// Strict upper triangle of column-major p x p blocks set to zero.
+__global__ void zero_upper_kernel(double* __restrict__ A, int p, int64_t stride, int nb) {
+  const int64_t total = (int64_t)nb * p * p;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / ((int64_t)p * p));
+    const int e = (int)(idx - (int64_t)b * p * p);
+    if (e % p < e / p) A[b * stride + e] = 0.0;
+  }
 }
 
 // out_j = sym(C1 block j + C2 block j) (projection coefficients of W on Q_j) -> A_j.
@@ -878,17 +888,28 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
                                                  sZb, &one, W, ldw, sW, nb));
         B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, C2, p, (int64_t)kp * p, jj * p, A + (int64_t)jj * pp,
                  (int64_t)k * pp, nb);
-        // Cholesky QR, twice: W = Q (L1 L2)^T
+        // Cholesky QR, twice: W = Q (L1 L2)^T.  Each pass multiplies by the inverse of its
+        // Cholesky factor (a batched triangular inverse and one batched DGEMM; a batched
+        // triangular solve with `rows` right-hand sides runs as many small products), out of
+        // place through Wl: pass 1 W -> Wl, pass 2 Wl -> W.
         double* Ls[2] = {L1, L2};
         for (int pass = 0; pass < 2; ++pass) {
-          B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, p, (int)rows, &one, W, ldw, sW, W, ldw, sW, &zero,
-                                                   Ls[pass], p, pp, nb));
+          const double* src = pass == 0 ? W : Wl;
+          const int lsrc = pass == 0 ? ldw : p;
+          const int64_t ssrc = pass == 0 ? sW : rows * p;
+          double* dst = pass == 0 ? Wl : W;
+          const int ldst = pass == 0 ? p : ldw;
+          const int64_t sdst = pass == 0 ? rows * p : sW;
+          B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, p, (int)rows, &one, src, lsrc, ssrc, src, lsrc, ssrc,
+                                                   &zero, Ls[pass], p, pp, nb));
           hipLaunchKernelGGL(cholesky_kernel, dim3(nb), dim3(256), 0, st, Ls[pass], p, pp,
                              pass == 0 ? thrp : (const double*)nullptr, kGramRelTol, flags);
           B_TRY_HIP(hipGetLastError());
-          B_TRY_BLAS(rocblas_dtrsm_strided_batched(h, rocblas_side_left, rocblas_fill_lower, NN,
-                                                   rocblas_diagonal_non_unit, p, (int)rows, &one, Ls[pass], p, pp, W,
-                                                   ldw, sW, nb));
+          B_TRY_BLAS(rocblas_dtrtri_strided_batched(h, rocblas_fill_lower, rocblas_diagonal_non_unit, p, Ls[pass], p, pp,
+                                                    T1, p, pp, nb));
+          B_LAUNCH(zero_upper_kernel, (int64_t)nb * pp, T1, p, pp, nb);
+          B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)rows, p, &one, T1, p, pp, src, lsrc, ssrc, &zero,
+                                                   dst, ldst, sdst, nb));   // dst^T = L^{-1} src^T
         }
         // B_{j+1}^T = L1 L2
         B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, p, p, &one, L1, p, pp, L2, p, pp, &zero,
