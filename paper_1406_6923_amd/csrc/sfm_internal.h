@@ -242,7 +242,7 @@ struct sfm_ctx_s {
   float* Ds_d = nullptr;
   float* exch_s_d = nullptr;
   int32_t* src_shot_d = nullptr;    // [nsrc] shot driven by each source, -1 if none
-  float* rec_stage_d = nullptr;     // receiver samples of the current window [32][nrec][64]
+  float* rec_stage_d = nullptr;     // receiver partial samples of the current window [32][4][nrec][64]
   int64_t shots_n = 0;
   int64_t shots_timed = 0;
   double shots_ms[3] = {0, 0, 0};   // main, face, record

@@ -361,7 +361,8 @@ struct ShotRecParams {
   const int32_t* perm;         // sorted receivers: caller index
   const float* U;              // [S][k][P][64]
   const int32_t* k_of;         // [S] levels of each subdomain's ROM (null: all k)
-  float* stage;                // [kShotWindow][nrec][64] samples of the current window (sorted order)
+  float* stage;                // [kShotWindow][nsplit][nrec][64] partial samples of the window (sorted order)
+  int nsplit;                  // reduction segments of the receiver product (1 .. kRecSplit)
   float* out;                  // [nshot][nrec][ld]
   int k, P, nrec, nshot;
   int64_t ld;
@@ -371,8 +372,15 @@ struct ShotRecParams {
   int w;                       // flush: filled slots
 };
 
-// stage[slot][r][n] = rows[r] . U[s(r)][:][:][n]: per receiver subdomain a (receivers x kP) (kP x 64)
-// product on the matrix cores, 64 receivers x 64 shots per work-group (one wave per 16 receivers).
+constexpr int kRecSplit = 4;   // most reduction segments of the receiver product
+
+// stage[slot][z][r][n] = rows[r][K_z] . U[s(r)][K_z][n], K_z the z-th of nsplit segments of the
+// k P words of a row (multiples of 64; the segments past the subdomain's k_s P sum nothing):
+// per receiver subdomain a (receivers x kP) (kP x 64) product on the matrix cores, 64 receivers x
+// 64 shots per work-group (one wave per 16 receivers).  With ROM sizes that differ, the work-groups
+// of the deepest ROMs set the kernel's length, so the reduction is split over kRecSplit
+// work-groups (nsplit = 1 otherwise: the split only adds partial traffic).  The flush adds the
+// segments in order.
 // The reduction runs in chunks of 64 staged through LDS (rows as [r][e], U as [e][n]); the next
 // chunk is loaded into registers (16-byte loads) while the current one is multiplied.  The 64
 // shots of a receiver are one 256-byte row of the window.
@@ -387,6 +395,9 @@ __global__ __launch_bounds__(256) void shots_record_kernel(ShotRecParams prm) {
   const int K = prm.k * prm.P;            // row length and level stride; a multiple of 16 (P = P16)
   const int sub = prm.rec_sub[r0];
   const int Kr = (prm.k_of ? prm.k_of[sub] : prm.k) * prm.P;   // levels past k_s are zero: skipped
+  const int seg = ((K + prm.nsplit - 1) / prm.nsplit + kK - 1) / kK * kK;
+  const int z = blockIdx.z;
+  const int kb = z * seg, ke = min(kb + seg, Kr);               // this work-group's words of the rows
   const float* Ub = prm.U + (size_t)sub * K * kShotCols;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63, g = lane >> 4, li = lane & 15;
   // loader layout: 4 passes of 16 rows x 16 quads
@@ -397,16 +408,16 @@ __global__ __launch_bounds__(256) void shots_record_kernel(ShotRecParams prm) {
     for (int pass = 0; pass < 4; ++pass) {
       const int rr = lr + 16 * pass;
       const int r = r0 + rr, e = k0 + 4 * lq;
-      rbuf[pass] = (r < r1 && e < Kr) ? *reinterpret_cast<const f4*>(prm.rows + (size_t)r * K + e) : f4{0.f, 0.f, 0.f, 0.f};
+      rbuf[pass] = (r < r1 && e < ke) ? *reinterpret_cast<const f4*>(prm.rows + (size_t)r * K + e) : f4{0.f, 0.f, 0.f, 0.f};
       const int e2 = k0 + rr;
-      ubuf[pass] = e2 < Kr ? *reinterpret_cast<const f4*>(Ub + (size_t)e2 * kShotCols + 4 * lq) : f4{0.f, 0.f, 0.f, 0.f};
+      ubuf[pass] = e2 < ke ? *reinterpret_cast<const f4*>(Ub + (size_t)e2 * kShotCols + 4 * lq) : f4{0.f, 0.f, 0.f, 0.f};
     }
   };
   f4 acc[4];
 #pragma unroll
   for (int h = 0; h < 4; ++h) acc[h] = f4{0.f, 0.f, 0.f, 0.f};
-  load(0);
-  for (int k0 = 0; k0 < Kr; k0 += kK) {
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += kK) {
     __syncthreads();
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
@@ -414,7 +425,7 @@ __global__ __launch_bounds__(256) void shots_record_kernel(ShotRecParams prm) {
       *reinterpret_cast<f4*>(&Us[lr + 16 * pass][4 * lq]) = ubuf[pass];
     }
     __syncthreads();
-    if (k0 + kK < Kr) load(k0 + kK);
+    if (k0 + kK < ke) load(k0 + kK);
 #pragma unroll
     for (int kk = 0; kk < kK; kk += 16) {
       const f4 a = *reinterpret_cast<const f4*>(&Rs[16 * wv + li][kk + 4 * g]);
@@ -434,20 +445,22 @@ __global__ __launch_bounds__(256) void shots_record_kernel(ShotRecParams prm) {
   for (int v = 0; v < 4; ++v) {
     const int r = r0 + 16 * wv + 4 * g + v;
     if (r >= r1) continue;
-    float* row = prm.stage + ((size_t)prm.slot * prm.nrec + r) * kShotCols;
+    float* row = prm.stage + (((size_t)prm.slot * prm.nsplit + z) * prm.nrec + r) * kShotCols;
 #pragma unroll
     for (int h = 0; h < 4; ++h) row[16 * h + li] = acc[h][v];
   }
 }
 
-// out[n][perm[r]][col0 + t] = stage[t][r][n] for t < w: one work-group per receiver, transposed
+// out[n][perm[r]][col0 + t] = sum over z of stage[t][z][r][n] for t < w: one work-group per receiver, transposed
 // through LDS so that both the window rows (64 shots) and the trace runs (w samples) are contiguous.
 __global__ __launch_bounds__(256) void shots_flush_kernel(ShotRecParams prm) {
   __shared__ float tile[kShotWindow][kShotCols + 1];
   const int r = blockIdx.x;
   for (int e = threadIdx.x; e < prm.w * kShotCols; e += 256) {
     const int t = e / kShotCols, n = e - t * kShotCols;
-    tile[t][n] = prm.stage[((size_t)t * prm.nrec + r) * kShotCols + n];
+    float v = 0.f;
+    for (int z = 0; z < prm.nsplit; ++z) v += prm.stage[(((size_t)t * prm.nsplit + z) * prm.nrec + r) * kShotCols + n];
+    tile[t][n] = v;
   }
   __syncthreads();
   const size_t orow = (size_t)prm.perm[r];
@@ -561,7 +574,8 @@ sfm_status sfm_shots_init(sfm_ctx c, int32_t nshot, const int32_t* shot_src, voi
   c->src_shot_d = static_cast<int32_t*>(c->dalloc(src_shot.size() * sizeof(int32_t), &e));
   c->shot_base_d = static_cast<int64_t*>(c->dalloc(sizeof(int64_t), &e));
   if (c->nrec > 0)
-    c->rec_stage_d = static_cast<float*>(c->dalloc((size_t)kShotWindow * c->nrec * kShotCols * sizeof(float), &e));
+    c->rec_stage_d =
+        static_cast<float*>(c->dalloc((size_t)kShotWindow * kRecSplit * c->nrec * kShotCols * sizeof(float), &e));
   if (e != hipSuccess) {
     release_shots(c);
     return c->fail(SFM_ENOMEM, "shot state: out of device memory");
@@ -717,7 +731,10 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
   rp.ld = ld;
   const int64_t nface = (int64_t)t.S * t.p * (kShotCols / 4);
   const bool record = traces_dev && c->nrec > 0;
-  const dim3 rgrid((c->rs_max + 63) / 64, c->n_rs);
+  bool mixed = false;                    // ROM sizes that differ: split the receiver product
+  for (size_t q = 1; q < c->k_of.size(); ++q) mixed = mixed || c->k_of[q] != c->k_of[0];
+  rp.nsplit = mixed ? kRecSplit : 1;
+  const dim3 rgrid((c->rs_max + 63) / 64, c->n_rs, rp.nsplit);
   // one step at relative index n (absolute with base == null); closes the window with a flush
   auto launch_step = [&](int n, int64_t col0, bool close, const int64_t* base, hipStream_t s,
                          bool set_attr) -> hipError_t {
