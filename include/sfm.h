@@ -316,6 +316,8 @@ sfm_status sfm_adjoint_gradient(sfm_ctx ctx, int32_t nsteps, double dt, const fl
  * the fastest (see sfm_shots_tuning).
  *   shot_src  host, int32 [nshot]: source index driving each shot (-1: no source), or NULL
  *             for shot n <- source n (then nshot <= nsrc).  A source drives at most one shot.
+ * Device memory: U and D of S k P16 x 64 floats each, the boundary exchange, and a receiver
+ * staging window of 32 steps x 4 partial sums x nrec x 64 floats.
  * Synchronizes.  Errors: SFM_ESTATE (no ROMs), SFM_EINVAL, SFM_ENOMEM. */
 sfm_status sfm_shots_init(sfm_ctx ctx, int32_t nshot, const int32_t* shot_src, void* stream);
 
