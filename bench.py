@@ -496,8 +496,9 @@ def main():
                     help="skip the finite-shift ROM probe (4^3-subdomain sample of the same ROM shape)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU split of this "
-              f"method is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); splitting the subdomains over "
+              f"several GPUs (one boundary exchange per cut face per step) is designed but not built",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
