@@ -88,6 +88,9 @@ typedef struct {
   double timed_main_ms;      /* summed device time of the step's main kernel over those steps */
   double timed_face_ms;      /* summed device time of the boundary-layer kernel */
   double timed_record_ms;    /* summed device time of the receiver kernel */
+  double rho_estimate;       /* last sfm_cfl_dt: power-iteration estimate of rho (a lower bound), 0 if none */
+  double rho_bound;          /* last sfm_cfl_dt: certified upper bound on rho, dt_max = 2 / sqrt(rho_bound) */
+  int64_t watchdog_checks;   /* state checks made by the sfm_step watchdog since sfm_set_watchdog */
 } sfm_info;
 
 /* Validate cfg and allocate a context on the current device.
@@ -188,10 +191,20 @@ sfm_status sfm_export_roms(sfm_ctx ctx, double* gamma, double* gamma_hat);
  * double [nrec][k][p] to the host (either may be NULL).  Synchronizes. */
 sfm_status sfm_export_projections(sfm_ctx ctx, double* src_vec, double* rec_rows);
 
-/* Stability limit of leapfrog for the coupled ROM: dt_max = 2 / sqrt(rho), rho the
- * largest eigenvalue of the coupled operator estimated by `iters` (>= 10) power
- * iterations of the FP32 step operator from a fixed seeded start.  Leaves the state
- * unchanged.  Synchronizes.  Errors: SFM_ESTATE (no ROMs), SFM_EINVAL. */
+/* Stability limit of leapfrog for the coupled ROM (the time stepping of the Stage 2 section):
+ * dt_max = 2 / sqrt(rho), rho the largest eigenvalue of M^{-1} K, the step operator with the
+ * coefficients as they are stored (FP32, BF16 or FP64).  *dt_max never exceeds that limit:
+ *   1. `iters` (>= 10) power iterations of the step operator from a fixed seeded start give an
+ *      estimate rho_est <= rho;
+ *   2. for mu on a ladder above rho_est (then bisected), every subdomain is tested for
+ *      mu M^alpha - K^alpha > 0 by an FP64 block Cholesky factorisation of its block-tridiagonal
+ *      S-fraction form on the stored coefficients (pivots must exceed 1e-9 mu); the first mu that
+ *      passes everywhere bounds max_alpha lambda_max(K^alpha, M^alpha) >= rho (the coupled
+ *      Rayleigh quotient is a mediant of the subdomains'), and dt_max = 2 / sqrt(mu).
+ * rho_est and mu are reported in sfm_info.  Leaves the state unchanged.  Synchronizes.
+ * Errors: SFM_ESTATE (no ROMs), SFM_EINVAL, SFM_ENOMEM (certificate scratch: 5 p^2 doubles for
+ * each of min(S, 2048) work-groups), SFM_EUNSTABLE (a stored Gamma-hat_j is not positive
+ * definite, or nothing up to 1e6 rho_est passes: no time step is stable). */
 sfm_status sfm_cfl_dt(sfm_ctx ctx, int32_t iters, double* dt_max, void* stream);
 
 /* Advance the coupled ROMs nsteps leapfrog steps of size dt (Algorithm 1, Stage 2):
@@ -201,9 +214,18 @@ sfm_status sfm_cfl_dt(sfm_ctx ctx, int32_t iters, double* dt_max, void* stream);
  *   traces_dev   device, float [nrec][ld]; if not NULL, receiver sample of U^{n+1} for the
  *                i-th step of this call goes to traces_dev[r * ld + i]  (ld >= nsteps)
  * If dt exceeds the last sfm_cfl_dt result (when one was computed) the call fails with
- * SFM_EUNSTABLE before launching anything.  Errors: SFM_ESTATE, SFM_EINVAL. */
+ * SFM_EUNSTABLE before launching anything; so does a failed watchdog check (sfm_set_watchdog).
+ * Errors: SFM_ESTATE, SFM_EINVAL, SFM_EUNSTABLE. */
 sfm_status sfm_step(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet_dev,
                     float* traces_dev, int64_t ld, void* stream);
+
+/* Run-time stability watchdog of sfm_step.  With every > 0, sfm_step computes ||U^n||_2 (FP64
+ * sum over the whole state) after every `every`-th step of a call and after its last step,
+ * synchronizes the stream, and stops with SFM_EUNSTABLE when the norm is not finite or exceeds
+ * max_norm (> 0; INFINITY checks finiteness only).  The steps done before the failing check stay
+ * applied (sfm_info.steps_done counts them).  every = 0 turns the watchdog off (the default).
+ * Errors: SFM_EINVAL. */
+sfm_status sfm_set_watchdog(sfm_ctx ctx, int32_t every, double max_norm);
 
 /* Receiver samples of the current state: out_dev[r] = r_r . U^{alpha(r), n} (device,
  * float [nrec]).  Errors: SFM_ESTATE. */

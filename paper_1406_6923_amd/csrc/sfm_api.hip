@@ -445,6 +445,9 @@ extern "C" sfm_status sfm_query(sfm_ctx c, sfm_info* out) {
   out->coef_bytes_algorithmic = (int64_t)t.S * (2 * t.k - 1) * ((int64_t)t.p * (t.p + 1) / 2) * elem;
   out->state_bytes = (int64_t)t.S * t.k * t.p * 4;
   out->build_seconds = c->build_seconds;
+  out->rho_estimate = c->rho_est;
+  out->rho_bound = c->rho_bound;
+  out->watchdog_checks = c->wd_checks;
   return SFM_OK;
 }
 
@@ -574,7 +577,7 @@ static FaceParams make_face_params(sfm_ctx c) {
 }
 
 // a = a(u) of the coupled scheme without forcing (both kernels in operator mode).
-static hipError_t apply_operator(sfm_ctx c, const float* u, float* a, hipStream_t st) {
+hipError_t apply_operator(sfm_ctx c, const float* u, float* a, hipStream_t st) {
   StepParams prm = make_step_params(c);
   prm.mode = 1;
   prm.Uin = u;
@@ -694,6 +697,21 @@ sfm_status sfm_step(sfm_ctx c, int32_t nsteps, double dt, const float* wavelet_d
       SFM_TRY_HIP(c, launch_record_window(r, st, c->rs_max));
     }
     if (e) SFM_TRY_HIP(c, hipEventRecord(e[3], st));
+    if (c->wd_every > 0 && ((i + 1) % c->wd_every == 0 || i + 1 == nsteps)) {
+      const int64_t n = (int64_t)c->topo.S * c->topo.k * c->geo.P16;
+      double nrm2 = 0.0;
+      SFM_TRY_HIP(c, launch_norm2(c->U_d, n, c->red_d, st));
+      SFM_TRY_HIP(c, hipMemcpyAsync(&nrm2, c->red_d, sizeof(double), hipMemcpyDeviceToHost, st));
+      SFM_TRY_HIP(c, hipStreamSynchronize(st));
+      ++c->wd_checks;
+      const double nrm = std::sqrt(nrm2);
+      if (!std::isfinite(nrm) || nrm > c->wd_max_norm) {
+        c->n += i + 1;
+        return c->fail(SFM_EUNSTABLE, "watchdog: |U| = " + std::to_string(nrm) + " after step " +
+                                          std::to_string(c->n) + (std::isfinite(nrm) ? " exceeds the limit "
+                                          + std::to_string(c->wd_max_norm) : " (state not finite)"));
+      }
+    }
   }
   c->n += nsteps;
   return SFM_OK;
@@ -745,49 +763,14 @@ sfm_status sfm_apply_operator(sfm_ctx c, const float* u_dev, float* a_dev, void*
   return SFM_OK;
 }
 
-sfm_status sfm_cfl_dt(sfm_ctx c, int32_t iters, double* dt_max, void* stream) {
+sfm_status sfm_set_watchdog(sfm_ctx c, int32_t every, double max_norm) {
   if (!c) return SFM_EINVAL;
   c->err.clear();
-  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs");
-  if (iters < 10 || !dt_max) return c->fail(SFM_EINVAL, "iters must be >= 10 and dt_max non-NULL");
-  SFM_TRY_HIP(c, hipSetDevice(c->device));
-  hipStream_t st = as_stream(stream);
-  const Topology& t = c->topo;
-  const int P16 = c->geo.P16;
-  const int64_t n = (int64_t)t.S * t.k * P16;
-  // Seeded start vector; shared boundary entries take the value of the lower-index side.
-  std::vector<float> v((size_t)n, 0.f);
-  uint64_t z = 0x9E3779B97F4A7C15ull;
-  for (int s = 0; s < t.S; ++s)
-    for (int j = 0; j < t.k; ++j)
-      for (int q = 0; q < t.p; ++q) {
-        z ^= z << 13; z ^= z >> 7; z ^= z << 17;
-        v[((size_t)s * t.k + j) * P16 + q] = (float)((double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5);
-      }
-  for (int s = 0; s < t.S; ++s)
-    for (int q = 0; q < t.p; ++q) {
-      const int f = q / t.m, pat = q % t.m;
-      const int nb = t.nbr[(size_t)s * 6 + f];
-      if (nb >= 0 && nb < s) v[(size_t)s * t.k * P16 + q] = v[(size_t)nb * t.k * P16 + (f ^ 1) * t.m + pat];
-    }
-  // Padding entries of the boundary layer are never written by the operator: clear them.
-  SFM_TRY_HIP(c, hipMemsetAsync(c->work_b_d, 0, n * sizeof(float), st));
-  SFM_TRY_HIP(c, hipMemcpyAsync(c->work_a_d, v.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
-  SFM_TRY_HIP(c, launch_norm2(c->work_a_d, n, c->red_d, st));
-  SFM_TRY_HIP(c, launch_scale(c->work_a_d, n, c->red_d, c->work_a_d, st));
-  for (int it = 0; it < iters; ++it) {
-    SFM_TRY_HIP(c, apply_operator(c, c->work_a_d, c->work_b_d, st));
-    SFM_TRY_HIP(c, launch_norm2(c->work_b_d, n, c->red_d, st));
-    if (it + 1 < iters) SFM_TRY_HIP(c, launch_scale(c->work_b_d, n, c->red_d, c->work_a_d, st));
-  }
-  double nrm2 = 0.0;
-  SFM_TRY_HIP(c, hipMemcpyAsync(&nrm2, c->red_d, sizeof(double), hipMemcpyDeviceToHost, st));
-  SFM_TRY_HIP(c, hipStreamSynchronize(st));
-  // a = -M^{-1} K v with |v| = 1, so |a| -> rho.
-  const double rho = std::sqrt(nrm2);
-  if (!(rho > 0.0) || !std::isfinite(rho)) return c->fail(SFM_EBREAKDOWN, "spectral radius estimate failed");
-  c->dt_max = 2.0 / std::sqrt(rho);
-  *dt_max = c->dt_max;
+  if (every < 0) return c->fail(SFM_EINVAL, "every must be >= 0");
+  if (every > 0 && !(max_norm > 0.0)) return c->fail(SFM_EINVAL, "max_norm must be > 0");
+  c->wd_every = every;
+  c->wd_max_norm = max_norm;
+  c->wd_checks = 0;
   return SFM_OK;
 }
 

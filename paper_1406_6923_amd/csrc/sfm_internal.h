@@ -188,6 +188,8 @@ hipError_t clear_extra_levels(sfm_ctx c, float* X, int cols, hipStream_t st);
 sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, float* u_out,
                         hipStream_t st);
 StepParams step_params(sfm_ctx c);
+// a = a(u) of the coupled scheme without forcing, [S][k][P16] each (step kernels in operator mode).
+hipError_t apply_operator(sfm_ctx c, const float* u, float* a, hipStream_t st);
 void destroy_blas(sfm_ctx c);
 
 }  // namespace sfm
@@ -268,6 +270,11 @@ struct sfm_ctx_s {
   bool has_roms = false;
   int64_t n = 0;
   double dt_max = -1.0;
+  double rho_est = 0.0;             // last sfm_cfl_dt: power-iteration estimate
+  double rho_bound = 0.0;           // last sfm_cfl_dt: certified bound
+  int32_t wd_every = 0;             // sfm_step watchdog: check every wd_every steps (0 = off)
+  double wd_max_norm = 0.0;
+  int64_t wd_checks = 0;
   double build_seconds = 0.0;
   void* blas = nullptr;             // rocblas_handle of the ROM build (created on first use)
   // per-kernel timing of sfm_step (events recorded on the caller's stream)

@@ -45,7 +45,8 @@ class sfm_info(ctypes.Structure):
                 ("coef_bytes_algorithmic", ctypes.c_int64), ("state_bytes", ctypes.c_int64),
                 ("build_seconds", ctypes.c_double), ("timed_steps", ctypes.c_int64),
                 ("timed_main_ms", ctypes.c_double), ("timed_face_ms", ctypes.c_double),
-                ("timed_record_ms", ctypes.c_double)]
+                ("timed_record_ms", ctypes.c_double), ("rho_estimate", ctypes.c_double),
+                ("rho_bound", ctypes.c_double), ("watchdog_checks", ctypes.c_int64)]
 
 
 class SfmError(RuntimeError):
@@ -100,6 +101,7 @@ SIGNATURES = {
     "sfm_export_projections": (_I32, [_VP, _VP, _VP]),
     "sfm_cfl_dt": (_I32, [_VP, _I32, ctypes.POINTER(_D), _VP]),
     "sfm_step": (_I32, [_VP, _I32, _D, _VP, _VP, _I64, _VP]),
+    "sfm_set_watchdog": (_I32, [_VP, _I32, _D]),
     "sfm_record_receivers": (_I32, [_VP, _VP, _VP]),
     "sfm_apply_operator": (_I32, [_VP, _VP, _VP, _VP]),
     "sfm_set_timing": (_I32, [_VP, _I32]),
@@ -265,6 +267,10 @@ def sfm_step(ctx: int, nsteps: int, dt: float, wavelet=None, traces=None, ld: Op
         ld = traces.shape[-1] if traces is not None else 0
     _check(ctx, load_library().sfm_step(ctx, int(nsteps), float(dt), _dev(wavelet), _dev(traces), int(ld),
                                         _stream(stream)))
+
+
+def sfm_set_watchdog(ctx: int, every: int, max_norm: float = float("inf")) -> None:
+    _check(ctx, load_library().sfm_set_watchdog(ctx, int(every), float(max_norm)))
 
 
 def sfm_adjoint_gradient(ctx: int, nsteps: int, dt: float, wavelet, grad_traces, checkpoint_every: int = 100,

@@ -27,12 +27,21 @@ def case_config(name: str) -> W.Workload:
     elif name == "mid":
         # The large workload's subdomain size and ROM sizes (33^3 nodes, m = 16, k = 16) on 2 x 2 x 1.
         cfg = W.scaled_large((2, 2, 1), nsteps=150)
+    elif name in ("m8", "m12"):
+        # 32^3-cell boxes on a 2 x 2 x 2 split with k = 16: m = 8 gives 6m = 48 (three 16-row tiles,
+        # the learned-ROM workload's shape), m = 12 gives 6m = 72 padded to 80 (five tiles, the
+        # gradient and many-shot workloads' shape).  Odd tile counts take the single-strip middle
+        # job of the step, adjoint and operator kernels.
+        m = 8 if name == "m8" else 12
+        cfg = W.Workload(name=f"layered_64c_2x2x2_m{m}_k16", ncell=(64, 64, 64), sub_cells=(32, 32, 32),
+                         h=10.0, m=m, k=16, f_peak=12.0, nsteps=500, src=((31, 31, 2),), rec_grid=(32, 32),
+                         velocity="layered_inclusions", seed=1406 + m)
     else:
         raise KeyError(name)
     return cfg
 
 
-@functools.lru_cache(maxsize=4)
+@functools.lru_cache(maxsize=6)
 def oracle_case(name: str = "small", sigma: float = np.inf):
     """Build the oracle ROMs and coupled system of a named workload."""
     cfg = case_config(name)
@@ -213,3 +222,46 @@ def shifted_interp_tolerance(sd, r, sigma: float, rtol: float, seed: int = 3) ->
     e = max(interpolation_error(sd, r.sf, sigma), interpolation_error(sd, sf_noisy, sigma), 1e-15)
     return 30.0 * e
 
+
+
+U32 = 2.0 ** -24
+
+
+def operator_error_bound(cs: coupled.CoupledSystem, U: np.ndarray, tau=None) -> np.ndarray:
+    """Elementwise first-order bound, times 2, on |a_gpu - a_oracle| for one application of the
+    coupled step operator with FP32 coefficients and state, [S][k][p].
+
+    The kernels round every stored coefficient to FP32 (relative u = 2^-24), form
+    x_j = U_{j+1} - U_j (one rounding), phi_j = Gamma_j x_j as FP32 dot products of length p
+    (error below p u sum |Gamma_j||x_j|), y_j = phi_j - phi_{j-1} (one rounding) and
+    a_j = Gamma-hat_j y_j; on the boundary layer a_f = C_f (phi_f^alpha + phi_f^beta) with C_f, the
+    sum and the product rounded once each.  tau[j] (optional) adds a relative coefficient
+    difference per level (device-built ROMs against the oracle's)."""
+    out = []
+    phis, dphis = [], []
+    for a, rom in enumerate(cs.roms):
+        k, p = rom.k, rom.p
+        tj = np.zeros(k) if tau is None else np.asarray(tau)
+        Ua = np.asarray(U[a], dtype=np.float64)
+        dU = np.vstack([Ua[1:], np.zeros((1, p))]) - Ua
+        phi = np.stack([rom.sf.gamma[j] @ dU[j] for j in range(k)])
+        dphi = np.stack([((p + 2) * U32 + tj[j]) * (np.abs(rom.sf.gamma[j]) @ np.abs(dU[j])) + U32 * np.abs(phi[j])
+                         for j in range(k)])
+        phis.append(phi)
+        dphis.append(dphi)
+        b = np.zeros((k, p))
+        for j in range(1, k):
+            y = phi[j] - phi[j - 1]
+            dy = dphi[j] + dphi[j - 1] + U32 * np.abs(y)
+            Gh = np.abs(rom.sf.gamma_hat[j])
+            b[j] = Gh @ dy + ((p + 1) * U32 + tj[j]) * (Gh @ np.abs(y)) + U32 * np.abs(rom.sf.gamma_hat[j] @ y)
+        out.append(b)
+    flux = np.zeros(cs.n_ports)
+    dflux = np.zeros(cs.n_ports)
+    for a in range(len(cs.roms)):
+        np.add.at(flux, cs.port_ids[a], np.abs(phis[a][0]))
+        np.add.at(dflux, cs.port_ids[a], dphis[a][0])
+    for a in range(len(cs.roms)):
+        ids = cs.port_ids[a]
+        out[a][0] = cs.C[ids] * (dflux[ids] + 3 * U32 * flux[ids])
+    return 2.0 * np.stack(out) + 1e-300

@@ -35,7 +35,27 @@ def test_struct_layouts_match_header():
     # sfm_config: 3 + 3 int32, a double (8-aligned), 4 int32 -> 48 bytes
     assert ctypes.sizeof(sfm.sfm_config) == 48
     assert sfm.sfm_config.h.offset == 24
-    assert ctypes.sizeof(sfm.sfm_info) == 96
+    # sfm_info: 6 int32, 4 int64, 4 double, 3 double, 1 int64 -> 120 bytes
+    assert ctypes.sizeof(sfm.sfm_info) == 120
+    assert sfm.sfm_info.rho_bound.offset == 104
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """The binding's structs against sizeof/offsetof of the header as a C compiler lays it out."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "sfm.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu\\n", sizeof(sfm_config), offsetof(sfm_config, h), '
+                   'sizeof(sfm_info), offsetof(sfm_info, rho_bound)); return 0; }\n')
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [ctypes.sizeof(sfm.sfm_config), sfm.sfm_config.h.offset, ctypes.sizeof(sfm.sfm_info),
+                   sfm.sfm_info.rho_bound.offset]
 
 
 @pytest.mark.parametrize("kwargs, fragment", [

@@ -73,8 +73,8 @@ def test_levels_traces_and_cfl_match_oracle(name, nsteps):
     h, cfg, cs_ks, ks = _loaded(name)
     dt_ref = cs_ks.cfl_dt()
     dt_gpu = sfm.sfm_cfl_dt(h.ctx, iters=400)
-    assert dt_gpu == pytest.approx(dt_ref, rel=0.02)
-    assert dt_gpu >= dt_ref * (1 - 1e-6)
+    print(f"{name}: dt_max device {dt_gpu:.8e}, oracle {dt_ref:.8e} (ratio {dt_gpu / dt_ref:.6f})")
+    assert dt_ref * (1 - 1e-3) <= dt_gpu <= dt_ref * (1 + 1e-6)     # certified: never above the limit
     dt = 0.9 * dt_ref
     wav = W.ricker(cfg.f_peak, dt, nsteps)[:, None]
     ref = cs_ks.run(dt, wav)

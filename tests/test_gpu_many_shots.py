@@ -3,7 +3,8 @@ cells as 936 boxes of 24, 32 or 48 cells per axis, ROMs built on the device with
 subdomain from {8, 12, 16, 24, 32} (k_s Lanczos steps each) and FP64 coefficient storage, 64 shots
 through the FP64 shot kernel, 36864 receivers.
 
-The oracle builds one sampled subdomain (a 24 x 24 x 32 box at its own k_s) and checks:
+The oracle builds sampled subdomains (24 x 24 x 32 boxes at their own k_s: one of 8 or 12 levels,
+one of 24 and one of 32) and checks:
   * the device's k_s-level coefficients, per level within 30x the oracle's own FP64 response to a
     1e-15 perturbation of the subdomain operator, and zero past k_s;
   * one application of the shot operator to a random state of all 64 shots, on every entry that
@@ -70,20 +71,23 @@ def _oracle_sub(cfg, c, s, k):
     return sd, rom.build_rom(sd, k), nb
 
 
-def _sample(cfg, ks):
-    """The first subdomain of the smallest box shape whose ROM size is 8 or 12."""
+def _sample(cfg, ks, levels):
+    """The first subdomain of the smallest box shape (a 24 x 24 x 32 box) whose ROM size is in levels."""
     for s in range(len(ks)):
         b = _box_index(cfg, s)
         w = [cfg.box_cells(d)[b[d]] for d in range(3)]
-        if w == [24, 24, 32] and ks[s] in (8, 12):
+        if sorted(w) == [24, 24, 32] and ks[s] in levels:
             return s
-    pytest.skip("no 24 x 24 x 32 box with k_s <= 12 in this draw")
+    pytest.skip(f"no 24 x 24 x 32 box with k_s in {levels} in this draw")
 
 
-def test_many_shots_sampled_subdomain_matches_oracle(many):
+# k_s = 24 and 32 are the deep ROMs whose blocks do not survive FP32 storage, the reason the
+# workload streams FP64 coefficients through the FP64 shot kernel.
+@pytest.mark.parametrize("levels", [(8, 12), (24,), (32,)])
+def test_many_shots_sampled_subdomain_matches_oracle(many, levels):
     from paper_1406_6923_amd import sfm
     cfg, c, h, ks = many
-    s = _sample(cfg, ks)
+    s = _sample(cfg, ks, levels)
     k = int(ks[s])
     print(f"[case] many-shot sampled subdomain {s}, k_s = {k}: oracle build", flush=True)
     sd, r, nb = _oracle_sub(cfg, c, s, k)
@@ -128,10 +132,14 @@ def test_many_shots_sampled_subdomain_matches_oracle(many):
     H = np.diag(r.sf.gamma_hat[0])
     outer = [q for q in range(p) if nb[q // m] < 0]
     if outer:
+        # an outer-face entry is C_f phi_1 with C_f = H stored in FP32, phi_1 exchanged in FP32 and
+        # the product rounded: three FP32 roundings on top of the coefficient tolerance
         ref0 = H[outer, None] * phi[0][outer]
-        b0 = H[outer, None] * (tau[0] * (np.abs(r.sf.gamma[0]) @ np.abs(dU[0]))[outer]) + U32 * np.abs(ref0)
-        assert np.all(np.abs(got[0][outer] - ref0) <= 2 * b0 + 1e-300)
-    print(f"subdomain {s} (k_s = {k}, {len(outer)} outer-face entries): worst interior error / bound {worst:.3f}")
+        b0 = H[outer, None] * (tau[0] * (np.abs(r.sf.gamma[0]) @ np.abs(dU[0]))[outer]) + 3 * U32 * np.abs(ref0)
+        r0 = float(np.max(np.abs(got[0][outer] - ref0) / (2 * b0 + 1e-300)))
+        assert r0 <= 1.0, r0
+    print(f"subdomain {s} (k_s = {k}, {len(outer)} outer-face entries): worst interior error / bound {worst:.3f}"
+          + (f", outer-face entries {r0:.3f}" if outer else ""))
 
 
 def test_many_shots_run_is_finite_and_reproducible(many):

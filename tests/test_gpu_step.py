@@ -2,16 +2,16 @@
 
 The ROMs come from the oracle through sfm_load_roms, so these tests isolate the step
 kernels (layer fluxes, exchange, interior and boundary updates, receivers) from the
-device ROM build.  Tolerances: one application of the step operator 1e-5 rel-L2 in
-FP32 (6e-2 with BF16 coefficient storage: relative rounding 2^-9 per word, amplified by
-the differences U_{j+1} - U_j and phi_j - phi_{j-1} on random states), and
-receiver traces 1e-3 rel-L2 (FP32).
+device ROM build.  Tolerances: one application of the step operator within the elementwise
+forward error bound of FP32 storage and dot products, and 1e-5 rel-L2 where 6m <= 24 (6e-2 with
+BF16 coefficient storage: relative rounding 2^-9 per word, amplified by the differences
+U_{j+1} - U_j and phi_j - phi_{j-1} on random states); receiver traces 1e-5 rel-L2 in FP32.
 """
 import numpy as np
 import pytest
 
 import workloads as W
-from tests.cases import oracle_case, random_consistent_state, rel_l2, rom_arrays
+from tests.cases import operator_error_bound, oracle_case, random_consistent_state, rel_l2, rom_arrays
 
 pytestmark = pytest.mark.gpu
 
@@ -32,26 +32,34 @@ def _loaded(name, precision=0):
     return h, cfg, cs
 
 
-# Random states excite the stiffest ROM modes, where the deep S-fraction levels
-# (condition numbers up to 1e10 for Gamma-hat_k at k = 16) amplify FP32 rounding of
-# the stored coefficients; the 6m = 96, k = 16 case is therefore held to 5e-5 on
-# random states and to 1e-5 on a physical (wavefield) state below.
+# One application of the step operator in FP32 is held elementwise to the first-order forward
+# error bound of FP32 coefficient storage and FP32 dot products (tests.cases.operator_error_bound).
+# Random states excite the stiffest ROM modes, where the deep S-fraction levels (condition numbers
+# up to 1e10 for Gamma-hat_k at k = 16) amplify that rounding: at 6m = 96, k = 16 the rel-L2 of one
+# application is ~1.6e-5 while every entry sits far inside its bound, so the 1e-5 relative bar is
+# kept where the arithmetic allows it (6m <= 24) and the bound decides at 6m = 96.  BF16 storage
+# (relative rounding 2^-9 per word) is reported against 6e-2.
 @pytest.mark.parametrize("name, precision, tol", [("small", 0, 1e-5), ("ragged", 0, 1e-5), ("small", 1, 6e-2),
-                                                   ("mid", 0, 5e-5)])
+                                                   ("mid", 0, None)])
 def test_step_operator_matches_oracle(name, precision, tol):
     from paper_1406_6923_amd import sfm
     h, cfg, cs = _loaded(name, precision)
-    U = random_consistent_state(cs, seed=11)
+    U = random_consistent_state(cs, seed=11).astype(np.float32).astype(np.float64)
     ref = np.stack(cs.accel(list(U)))
     u_d = torch.tensor(U, dtype=torch.float32, device="cuda")
     a_d = torch.empty_like(u_d)
     sfm.sfm_apply_operator(h.ctx, u_d, a_d)
     torch.cuda.synchronize()
-    got = a_d.cpu().numpy()
-    assert rel_l2(got, ref) < tol
-    # boundary layer (eq. "bdrytstep") and interior layers separately
-    assert rel_l2(got[:, 0], ref[:, 0]) < tol
-    assert rel_l2(got[:, 1:], ref[:, 1:]) < tol
+    got = a_d.cpu().numpy().astype(np.float64)
+    errs = (rel_l2(got, ref), rel_l2(got[:, 0], ref[:, 0]), rel_l2(got[:, 1:], ref[:, 1:]))
+    msg = f"{name} prec {precision}: operator rel-L2 all {errs[0]:.2e}, boundary {errs[1]:.2e}, interior {errs[2]:.2e}"
+    if precision == 0:
+        ratio = float(np.max(np.abs(got - ref) / operator_error_bound(cs, U)))
+        msg += f"; max error / bound {ratio:.3f}"
+        assert ratio < 1.0
+    print(msg)
+    if tol is not None:
+        assert max(errs) < tol
     h.close()
 
 
@@ -89,7 +97,7 @@ def test_traces_match_oracle(name, nsteps):
     got = tr_d.cpu().numpy()
     err = rel_l2(got, ref)
     print(f"{name}: traces rel-L2 = {err:.3e}")
-    assert err < 1e-3
+    assert err < 1e-5
     # the last sample (windowed product) equals an explicit record of the final state (dot
     # products in another order)
     out = torch.empty(len(cs.receivers), dtype=torch.float32, device="cuda")
@@ -101,23 +109,27 @@ def test_traces_match_oracle(name, nsteps):
 
 @pytest.mark.parametrize("name", ["small", "mid"])
 def test_step_operator_on_wavefield_state(name):
-    """One application of the step operator to the oracle's wavefield after 100 steps."""
+    """One application of the step operator to the oracle's wavefield after 100 steps: within the
+    forward error bound everywhere, and 1e-5 rel-L2 at 6m = 24 (at 6m = 96, k = 16 the FP32-stored
+    deep levels give ~1.1e-5 on one application; traces over many steps stay at ~2e-6)."""
     from paper_1406_6923_amd import sfm
     h, cfg, cs = _loaded(name)
     dt = 0.9 * cs.cfl_dt()
     wav = W.ricker(cfg.f_peak, dt, 100)[:, None]
     _, U, _ = cs.run(dt, wav, return_state=True)
-    U = np.stack(U)
+    U = np.stack(U).astype(np.float32).astype(np.float64)
     ref = np.stack(cs.accel(list(U)))
     u_d = torch.tensor(U, dtype=torch.float32, device="cuda")
     a_d = torch.empty_like(u_d)
     sfm.sfm_apply_operator(h.ctx, u_d, a_d)
     torch.cuda.synchronize()
-    err = rel_l2(a_d.cpu().numpy(), ref)
-    print(f"{name}: wavefield operator rel-L2 = {err:.3e}")
-    # 6m = 96, k = 16: the FP32-stored deep levels give ~1.1e-5 on one application (measured);
-    # the traces over many steps stay at ~2e-6 (test_mid_traces_match_oracle).
-    assert err < (1e-5 if name == "small" else 2e-5)
+    got = a_d.cpu().numpy().astype(np.float64)
+    err = rel_l2(got, ref)
+    ratio = float(np.max(np.abs(got - ref) / operator_error_bound(cs, U)))
+    print(f"{name}: wavefield operator rel-L2 = {err:.3e}, max error / bound {ratio:.3f}")
+    assert ratio < 1.0
+    if name == "small":
+        assert err < 1e-5
     h.close()
 
 
@@ -138,16 +150,68 @@ def test_mid_traces_match_oracle():
     h.close()
 
 
-def test_cfl_estimate_matches_oracle():
+def _bf16(a):
+    t = torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64)
+    return t.numpy()
+
+
+@pytest.mark.parametrize("name, precision", [("small", 0), ("ragged", 0), ("small", 1)])
+def test_cfl_limit_is_certified(name, precision):
+    """sfm_cfl_dt never exceeds the true limit 2 / sqrt(rho) of the operator it steps (the
+    coefficients as stored), and sits within 1e-3 of it (the per-subdomain bound the certificate
+    tests is within 3e-4 of the coupled rho on these cases, the bisection stops at 2e-5)."""
+    from oracle import adjoint
+    from oracle.coupled import subdomain_bound
+    from paper_1406_6923_amd import sfm
+    h, cfg, cs = _loaded(name, precision)
+    if precision == 1:      # the exact limit of the BF16-rounded operator
+        dg = [_bf16(r.sf.gamma) - r.sf.gamma for r in cs.roms]
+        dh = [_bf16(r.sf.gamma_hat) - r.sf.gamma_hat for r in cs.roms]
+        ref_sys = adjoint.perturbed_system(cs, dg, dh, 1.0)
+    else:
+        ref_sys = cs
+    rho = ref_sys.max_eig()
+    dt_ref = 2.0 / np.sqrt(rho)
+    dt_gpu = sfm.sfm_cfl_dt(h.ctx, iters=400)
+    info = h.info()
+    print(f"{name} prec {precision}: dt_max device {dt_gpu:.8e}, exact {dt_ref:.8e} (ratio {dt_gpu / dt_ref:.6f}); "
+          f"rho estimate {info['rho_estimate']:.6e}, bound {info['rho_bound']:.6e}, exact {rho:.6e}, "
+          f"subdomain bound {subdomain_bound(ref_sys.roms):.6e}")
+    assert dt_gpu <= dt_ref * (1 + 1e-6)
+    assert dt_gpu >= dt_ref * (1 - 1e-3)
+    assert info["rho_estimate"] <= rho * (1 + 1e-5) <= info["rho_bound"] * (1 + 1e-5)
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_step(h.ctx, 1, 1.0001 * dt_gpu, torch.zeros((1, 1), device="cuda"))
+    assert ei.value.status == sfm.SFM_EUNSTABLE
+    h.close()
+
+
+def test_watchdog_stops_unstable_runs():
+    """The run-time watchdog: a state that is not finite, or whose norm exceeds the limit, stops
+    sfm_step with SFM_EUNSTABLE (both forced from the host); a normal run passes its checks."""
     from paper_1406_6923_amd import sfm
     h, cfg, cs = _loaded("small")
-    dt_gpu = sfm.sfm_cfl_dt(h.ctx, iters=400)
-    dt_ref = cs.cfl_dt()
-    assert dt_gpu == pytest.approx(dt_ref, rel=0.02)
-    assert dt_gpu >= dt_ref * (1 - 1e-6)       # power iteration bounds rho from below
+    dt = 0.9 * cs.cfl_dt()
+    wav = torch.tensor(W.ricker(cfg.f_peak, dt, 100)[:, None], dtype=torch.float32, device="cuda")
+    sfm.sfm_set_watchdog(h.ctx, 25)
+    sfm.sfm_step(h.ctx, 100, dt, wav)
+    assert h.info()["watchdog_checks"] == 4
+    u, d, n = sfm.sfm_get_state(h.ctx)
+    sfm.sfm_set_watchdog(h.ctx, 10, 1e-3 * float(np.linalg.norm(u)))
     with pytest.raises(sfm.SfmError) as ei:
-        sfm.sfm_step(h.ctx, 1, 1.01 * dt_gpu, torch.zeros((1, 1), device="cuda"))
-    assert ei.value.status == sfm.SFM_EUNSTABLE
+        sfm.sfm_step(h.ctx, 30, dt, wav[:30].contiguous())
+    assert ei.value.status == sfm.SFM_EUNSTABLE and h.info()["steps_done"] == 110
+    bad = u.copy()
+    bad[3, 2, 5] = np.nan
+    sfm.sfm_set_state(h.ctx, bad, d, 0)
+    sfm.sfm_set_watchdog(h.ctx, 50)
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_step(h.ctx, 20, dt, wav[:20].contiguous())
+    assert ei.value.status == sfm.SFM_EUNSTABLE and "not finite" in sfm.sfm_last_error(h.ctx)
+    sfm.sfm_set_watchdog(h.ctx, 0)
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_set_watchdog(h.ctx, 5, 0.0)
+    assert ei.value.status == sfm.SFM_EINVAL
     h.close()
 
 
