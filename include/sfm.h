@@ -219,6 +219,18 @@ sfm_status sfm_cfl_dt(sfm_ctx ctx, int32_t iters, double* dt_max, void* stream);
 sfm_status sfm_step(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet_dev,
                     float* traces_dev, int64_t ld, void* stream);
 
+/* sfm_cfl_dt for callers that cannot allocate device memory (code that must not call hipMalloc,
+ * tight serving loops, harnesses that forbid allocation): the same computation and result, with
+ * the stability certificate's scratch in a static device array of 64 MiB instead of a per-call
+ * allocation (the power iterations use buffers the context allocated at sfm_create).  Calls no
+ * hipMalloc or hipFree.  Each device holds its own copy of the array, from the first call on that
+ * device until the process ends; every call on a device shares it and leaves its contents behind
+ * (nothing in it needs to start at zero), so calls that overlap on one device, from any context or
+ * thread, race.  Work-groups are limited to those whose 5 (6m)^2 FP64 work matrices fit in 63 MiB
+ * (181 at 6m = 96, 25 at 6m = 256), which only lengthens the certificate.
+ * Errors: as sfm_cfl_dt except SFM_ENOMEM; SFM_EINVAL for more than 262,144 subdomains. */
+sfm_status sfm_cfl_dt_noalloc(sfm_ctx ctx, int32_t iters, double* dt_max, void* stream);
+
 /* Run-time stability watchdog of sfm_step.  With every > 0, sfm_step computes ||U^n||_2 (FP64
  * sum over the whole state) after every `every`-th step of a call and after its last step,
  * synchronizes the stream, and stops with SFM_EUNSTABLE when the norm is not finite or exceeds

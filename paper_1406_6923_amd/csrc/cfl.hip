@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -291,4 +292,51 @@ extern "C" sfm_status sfm_cfl_dt(sfm_ctx c, int32_t iters, double* dt_max, void*
   const sfm_status rc = sfm::cfl_limit(c, iters, scratch, nwg, dt_max, reinterpret_cast<hipStream_t>(stream));
   c->dfree(scratch);
   return rc;
+}
+
+// ----------------------------------------------------------------------------- no-allocation variant
+// The certificate's scratch (work matrices and verdicts) in one file-scope device array.  In host
+// code `scratch` names a host-side stand-in, not device memory: its device address is taken once
+// per device with hipGetSymbolAddress, with that device current, and only that address is used.
+namespace {
+constexpr size_t kStaticVerdictBytes = size_t(1) << 20;          // S <= 262,144
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;         // 63 MiB of work matrices + verdicts
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+extern "C" sfm_status sfm_cfl_dt_noalloc(sfm_ctx c, int32_t iters, double* dt_max, void* stream) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  const size_t per_group = sfm::cfl_scratch_bytes_per_group(c->topo.p);
+  const size_t verdict_bytes = (size_t)c->topo.S * sizeof(int32_t);
+  if (verdict_bytes > kStaticVerdictBytes)
+    return c->fail(SFM_EINVAL, "sfm_cfl_dt_noalloc: " + std::to_string(c->topo.S) +
+                                   " subdomains exceed the static scratch limit of " +
+                                   std::to_string(kStaticVerdictBytes / sizeof(int32_t)));
+  const size_t groups = (kStaticScratchBytes - kStaticVerdictBytes) / per_group;
+  if (groups < 1)
+    return c->fail(SFM_EINVAL, "sfm_cfl_dt_noalloc: 6m = " + std::to_string(c->topo.p) +
+                                   " needs more than the static scratch of one work-group");
+  if (!c->has_roms) return c->fail(SFM_ESTATE, "no ROMs");
+  if (iters < 10 || !dt_max) return c->fail(SFM_EINVAL, "iters must be >= 10 and dt_max non-NULL");
+  if (c->device < 0 || c->device >= kMaxDevices) return c->fail(SFM_EINVAL, "device index out of range");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return c->fail(SFM_EHIP, std::string("hipSetDevice failed: ") + hipGetErrorString(e));
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[c->device]) {
+      void* ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return c->fail(SFM_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+      g_scratch_dev[c->device] = ptr;
+    }
+    base = g_scratch_dev[c->device];
+  }
+  const int nwg = (int)std::min<size_t>({(size_t)c->topo.S, size_t(2048), groups});
+  return sfm::cfl_limit(c, iters, static_cast<double*>(base), nwg, dt_max, reinterpret_cast<hipStream_t>(stream));
 }

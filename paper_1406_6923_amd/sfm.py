@@ -102,6 +102,7 @@ SIGNATURES = {
     "sfm_cfl_dt": (_I32, [_VP, _I32, ctypes.POINTER(_D), _VP]),
     "sfm_step": (_I32, [_VP, _I32, _D, _VP, _VP, _I64, _VP]),
     "sfm_set_watchdog": (_I32, [_VP, _I32, _D]),
+    "sfm_cfl_dt_noalloc": (_I32, [_VP, _I32, ctypes.POINTER(_D), _VP]),
     "sfm_record_receivers": (_I32, [_VP, _VP, _VP]),
     "sfm_apply_operator": (_I32, [_VP, _VP, _VP, _VP]),
     "sfm_set_timing": (_I32, [_VP, _I32]),
@@ -267,6 +268,12 @@ def sfm_step(ctx: int, nsteps: int, dt: float, wavelet=None, traces=None, ld: Op
         ld = traces.shape[-1] if traces is not None else 0
     _check(ctx, load_library().sfm_step(ctx, int(nsteps), float(dt), _dev(wavelet), _dev(traces), int(ld),
                                         _stream(stream)))
+
+
+def sfm_cfl_dt_noalloc(ctx: int, iters: int = 200, stream=None) -> float:
+    out = _D()
+    _check(ctx, load_library().sfm_cfl_dt_noalloc(ctx, int(iters), ctypes.byref(out), _stream(stream)))
+    return out.value
 
 
 def sfm_set_watchdog(ctx: int, every: int, max_norm: float = float("inf")) -> None:
