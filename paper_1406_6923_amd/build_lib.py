@@ -31,11 +31,21 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *COMMON, "-c", src, "-o", obj]
+# The debug preset: SFM_DEBUG launch checks (shapes and grids against what each kernel assumes,
+# abort on violation), host code under AddressSanitizer and UndefinedBehaviorSanitizer (device code
+# is not instrumented), -O1 -g.  Load it with the sanitizer runtime preloaded.
+DEBUG = ["-O1", "-g", "-DSFM_DEBUG", "-fno-omit-frame-pointer", "-Xarch_host", "-fsanitize=address",
+         "-Xarch_host", "-fsanitize=undefined"]
+OBJ_DEBUG = os.path.join(PKG, "_build_debug")
+LIB_DEBUG = os.path.join(PKG, "libsfm_debug.so")
+
+
+def _compile(src: str, verbose: bool, debug: bool = False) -> str:
+    obj = os.path.join(OBJ_DEBUG if debug else OBJ, os.path.basename(src) + ".o")
+    flags = [f for f in COMMON if f != "-O3"] + DEBUG if debug else COMMON
+    cmd = [_hipcc(), *flags, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [_hipcc(), "-x", "hip", *COMMON, "-c", src, "-o", obj]
+        cmd = [_hipcc(), "-x", "hip", *flags, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -46,22 +56,26 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source under csrc/ and link libsfm.so; returns the library path."""
-    os.makedirs(OBJ, exist_ok=True)
+def build(verbose: bool = False, debug: bool = False) -> str:
+    """Compile every source under csrc/ and link libsfm.so (libsfm_debug.so with debug=True, the
+    debug preset above); returns the library path."""
+    os.makedirs(OBJ_DEBUG if debug else OBJ, exist_ok=True)
+    lib = LIB_DEBUG if debug else LIB
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, debug), srcs))
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
            "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+    if debug:
+        cmd += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -235,6 +235,7 @@ sfm_status cfl_limit(sfm_ctx c, int32_t iters, double* scratch, int nwg, double*
   prm.scratch = scratch;
   prm.verdict = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(scratch) + nwg * cfl_scratch_bytes_per_group(p));
   std::vector<int32_t> verdict(S);
+  SFM_DCHECK(nwg >= 1 && nwg <= S && p >= 1 && k >= 1 && c->coef64_d && scratch);
   auto passes = [&](double mu, bool* ok) -> sfm_status {
     prm.mu = mu;
     hipLaunchKernelGGL(inertia_kernel, dim3(nwg), dim3(kCflThreads), 0, st, prm);

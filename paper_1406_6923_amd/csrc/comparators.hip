@@ -47,6 +47,86 @@ __global__ __launch_bounds__(256) void fdtd_step_kernel(const float* __restrict_
   unm1[idx] = fmaf(coef[idx], lap, 2.f * uc - unm1[idx]);
 }
 
+// The same update, marching along z: a work-group owns a 64 x 4 tile of (x, y) columns and a
+// chunk of kFdtdChunk planes; each thread keeps its column's u at planes l-1, l, l+1 in registers
+// (each plane's operands loaded one plane ahead) and takes its x / y neighbours from plane l staged
+// in LDS with a one-node ring of the neighbouring tiles' nodes; mirror ghosts on the outer faces are
+// taken in the stencil itself.  Per node and step it reads u, u^{n-1} and the coefficient once
+// (plus the ring and two planes per chunk) and writes u^{n+1}: 16 bytes.
+constexpr int kFdtdTx = 64, kFdtdTy = 4, kFdtdChunk = 32;
+
+__global__ __launch_bounds__(kFdtdTx * kFdtdTy) void fdtd_march_kernel(const float* __restrict__ u,
+                                                                    float* __restrict__ unm1,
+                                                                    const float* __restrict__ coef, int nx, int ny,
+                                                                    int nz) {
+  __shared__ float pl[2][kFdtdTy + 2][kFdtdTx + 2];
+  const int tx = threadIdx.x % kFdtdTx, ty = threadIdx.x / kFdtdTx;
+  const int x0 = blockIdx.x * kFdtdTx, y0 = blockIdx.y * kFdtdTy;
+  const int x = x0 + tx, y = y0 + ty;
+  const int l0 = blockIdx.z * kFdtdChunk;
+  const int l1 = min(nz, l0 + kFdtdChunk);
+  const int64_t sxy = (int64_t)nx * ny;
+  const bool act = x < nx && y < ny;
+  const int64_t col = act ? (int64_t)y * nx + x : 0;
+  // the ring: rows y0 - 1 and y0 + 4 (64 nodes each), columns x0 - 1 and x0 + 64 (4 nodes each),
+  // where they exist in the grid
+  const int t = threadIdx.x;
+  int rx = -1, ry = -1, slot_r = 0, slot_c = 0;
+  if (t < 2 * kFdtdTx) {
+    const int side = t / kFdtdTx;
+    slot_r = side ? kFdtdTy + 1 : 0;
+    slot_c = t % kFdtdTx + 1;
+    rx = x0 + t % kFdtdTx;
+    ry = side ? y0 + kFdtdTy : y0 - 1;
+  } else if (t < 2 * kFdtdTx + 2 * kFdtdTy) {
+    const int q = t - 2 * kFdtdTx;
+    const int side = q / kFdtdTy;
+    slot_r = q % kFdtdTy + 1;
+    slot_c = side ? kFdtdTx + 1 : 0;
+    rx = side ? x0 + kFdtdTx : x0 - 1;
+    ry = y0 + q % kFdtdTy;
+  }
+  const bool ring = rx >= 0 && rx < nx && ry >= 0 && ry < ny;
+  const int64_t rcol = ring ? (int64_t)ry * nx + rx : 0;
+  // plane above l with the mirror ghost at the last plane
+  auto above = [&](int l) { return l + 1 < nz ? l + 1 : (nz > 1 ? l - 1 : l); };
+  float um = 0.f, uc = 0.f, up = 0.f, vn = 0.f, cn = 0.f, rg = 0.f;
+  if (act) {
+    uc = u[l0 * sxy + col];
+    um = u[(l0 > 0 ? l0 - 1 : above(l0)) * sxy + col];
+    up = u[above(l0) * sxy + col];
+    vn = unm1[l0 * sxy + col];
+    cn = coef[l0 * sxy + col];
+  }
+  if (ring) rg = u[l0 * sxy + rcol];
+  int b = 0;
+  for (int l = l0; l < l1; ++l) {
+    pl[b][ty + 1][tx + 1] = uc;
+    if (ring) pl[b][slot_r][slot_c] = rg;
+    const float vc = vn, cc = cn, uz = up;
+    if (l + 1 < l1) {       // operands of the next plane
+      if (act) {
+        vn = unm1[(l + 1) * sxy + col];
+        cn = coef[(l + 1) * sxy + col];
+        up = u[above(l + 1) * sxy + col];
+      }
+      if (ring) rg = u[(l + 1) * sxy + rcol];
+    }
+    __syncthreads();
+    if (act) {
+      const float xm = pl[b][ty + 1][x > 0 ? tx : tx + 2];
+      const float xp = pl[b][ty + 1][x < nx - 1 ? tx + 2 : tx];
+      const float ym = pl[b][y > 0 ? ty : ty + 2][tx + 1];
+      const float yp = pl[b][y < ny - 1 ? ty + 2 : ty][tx + 1];
+      const float lap = (xm + xp) + (ym + yp) + (um + uz) - 6.f * uc;
+      unm1[l * sxy + col] = fmaf(cc, lap, 2.f * uc - vc);
+    }
+    um = uc;
+    uc = uz;
+    b ^= 1;
+  }
+}
+
 // Point sources (added after the stencil update of the same step) and receiver samples.
 __global__ void fdtd_source_kernel(float* __restrict__ unext, const int64_t* __restrict__ node,
                                    const float* __restrict__ scale, const float* __restrict__ wavelet, int nsrc) {
@@ -201,9 +281,13 @@ extern "C" sfm_status sfm_fdtd_run(const int32_t* ncell, double h, const float* 
   if (nsrc) C_TRY(hipMemcpy(scale_d, sscale.data(), nsrc * 4, hipMemcpyHostToDevice));
   if (nrec) C_TRY(hipMemcpy(rn_d, rn.data(), nrec * 8, hipMemcpyHostToDevice));
   C_TRY(hipStreamSynchronize(st));
+  SFM_DCHECK(nx >= 2 && ny >= 2 && nz >= 1 && (int64_t)nx * ny * nz == n);
   t0 = std::chrono::steady_clock::now();
   for (int32_t s = 0; s < nsteps; ++s) {
-    hipLaunchKernelGGL(fdtd_step_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, u, v, coef, nx, ny, nz);
+    hipLaunchKernelGGL(fdtd_march_kernel,
+                       dim3((unsigned)((nx + kFdtdTx - 1) / kFdtdTx), (unsigned)((ny + kFdtdTy - 1) / kFdtdTy),
+                            (unsigned)((nz + kFdtdChunk - 1) / kFdtdChunk)),
+                       dim3(kFdtdTx * kFdtdTy), 0, st, u, v, coef, nx, ny, nz);
     if (nsrc)
       hipLaunchKernelGGL(fdtd_source_kernel, dim3((nsrc + 63) / 64), dim3(64), 0, st, v, sn_d, scale_d,
                          wavelet_dev + (int64_t)s * nsrc, nsrc);

@@ -93,6 +93,8 @@ hipError_t launch_record(const RecParams& prm, hipStream_t st) {
 
 hipError_t launch_record_window(const RecWindowParams& prm, hipStream_t st, int max_per_slot) {
   if (prm.n_rs == 0 || prm.w <= 0) return hipSuccess;
+  SFM_DCHECK(prm.w <= kHistWindow && max_per_slot >= 1 && prm.rs_off && prm.perm && prm.rows && prm.hist);
+  SFM_DCHECK(prm.traces && prm.ld >= prm.col0 + prm.w);
   const dim3 grid((max_per_slot + kTR - 1) / kTR, prm.n_rs);
   hipLaunchKernelGGL(record_window_kernel, grid, dim3(256), 0, st, prm);
   return hipGetLastError();

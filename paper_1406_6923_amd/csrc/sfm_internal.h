@@ -32,6 +32,25 @@
 
 #include "sfm.h"
 
+// Launch checks of the debug build (SFM_DEBUG): before a kernel is launched, the host verifies
+// that shapes, grids and buffer extents match what the kernel's indexing assumes, and aborts with
+// the failed condition otherwise.  Compiled out of the release build.
+#ifdef SFM_DEBUG
+#include <cstdio>
+#include <cstdlib>
+#define SFM_DCHECK(cond)                                                                         \
+  do {                                                                                           \
+    if (!(cond)) {                                                                               \
+      std::fprintf(stderr, "SFM_DEBUG: launch check failed: %s (%s:%d)\n", #cond, __FILE__, __LINE__); \
+      std::abort();                                                                              \
+    }                                                                                            \
+  } while (0)
+#else
+#define SFM_DCHECK(cond) \
+  do {                   \
+  } while (0)
+#endif
+
 namespace sfm {
 
 constexpr int kTile = 16;

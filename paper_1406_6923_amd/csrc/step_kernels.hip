@@ -235,6 +235,12 @@ static hipError_t launch_main_t(const StepParams& prm, size_t lds, hipStream_t s
 
 hipError_t launch_step_main(const StepParams& prm, int precision, hipStream_t st) {
   const size_t lds = step_lds_bytes(prm, precision);
+  SFM_DCHECK(prm.S > 0 && prm.k >= 1 && prm.P16 == kTile * prm.nt && prm.nt >= 1 && prm.nt <= kMaxNt);
+  SFM_DCHECK(prm.npairs == (prm.nt + 1) / 2 && prm.nslots == prm.nt + prm.nt * (prm.nt - 1) / 2);
+  SFM_DCHECK(prm.words_per_sub == (2 * (int64_t)prm.k - 1) * prm.words_per_block);
+  SFM_DCHECK(lds <= kMaxLdsBytes && prm.tiles && prm.exch);
+  SFM_DCHECK(prm.mode == 1 ? (prm.Uin && prm.Aout) : (prm.U && prm.D));
+  SFM_DCHECK(!prm.hist || (prm.hist_slot && prm.mode == 0));
   if (precision == SFM_PREC_FP32) return launch_main_t<float>(prm, lds, st);
   if (precision == SFM_PREC_FP64) return launch_main_t<double>(prm, lds, st);
   return launch_main_t<uint16_t>(prm, lds, st);
@@ -242,6 +248,8 @@ hipError_t launch_step_main(const StepParams& prm, int precision, hipStream_t st
 
 hipError_t launch_step_face(const FaceParams& prm, hipStream_t st) {
   const int64_t n = (int64_t)prm.S * prm.p;
+  SFM_DCHECK(prm.p == 6 * prm.m && prm.p <= prm.P16 && prm.nbr && prm.C && prm.exch);
+  SFM_DCHECK(n > 0 && (n + 255) / 256 <= 0x7fffffff);
   const int threads = 256;
   hipLaunchKernelGGL(step_face_kernel, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, st, prm);
   return hipGetLastError();
@@ -252,6 +260,7 @@ hipError_t launch_pack(const double* blocks, int64_t /*nblocks_total*/, int /*bl
                        int precision, int S, hipStream_t st) {
   const int threads = 256;
   const int64_t total = (int64_t)S * (2 * k - 1) * geo.words_per_block;
+  SFM_DCHECK(geo.p == p && geo.P16 >= p && blocks && wrow && wcol && tiles && total > 0);
   const unsigned grid = (unsigned)std::min<int64_t>((total + threads - 1) / threads, 65536);
   if (precision == SFM_PREC_FP32) {
     hipLaunchKernelGGL(pack_kernel<float>, dim3(grid), dim3(threads), 0, st, blocks, k, p, geo.words_per_block,
