@@ -231,6 +231,19 @@ sfm_status sfm_step(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet
  * Errors: as sfm_cfl_dt except SFM_ENOMEM; SFM_EINVAL for more than 262,144 subdomains. */
 sfm_status sfm_cfl_dt_noalloc(sfm_ctx ctx, int32_t iters, double* dt_max, void* stream);
 
+/* The batched FP64 matrix product the ROM build runs on the FP64 matrix cores (block Lanczos
+ * projections and re-orthogonalisation, Cholesky QR, S-fraction products of Stage 1), column-major
+ * like BLAS:  C_b = alpha op(A_b) op(B_b) + beta C_b for b < batch, op(X) = X^T when trans_x != 0,
+ * op(A) M x K, op(B) K x N, C M x N; X_b starts at X + b stride_x.  All pointers are device memory;
+ * C must not overlap A or B.  work (device, work_bytes, may be NULL) holds partial tiles when a long
+ * reduction (K in the thousands against a small C) is split over work-groups; the splits are summed
+ * in a fixed order, so results are reproducible.  Asynchronous on stream.
+ * Errors: SFM_EINVAL (sizes, leading dimensions, missing pointers), SFM_EHIP (launch). */
+sfm_status sfm_dgemm_batched(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K, double alpha,
+                             const double* A, int64_t lda, int64_t stride_a, const double* B, int64_t ldb,
+                             int64_t stride_b, double beta, double* C, int64_t ldc, int64_t stride_c, int32_t batch,
+                             double* work, int64_t work_bytes, void* stream);
+
 /* Run-time stability watchdog of sfm_step.  With every > 0, sfm_step computes ||U^n||_2 (FP64
  * sum over the whole state) after every `every`-th step of a call and after its last step,
  * synchronizes the stream, and stops with SFM_EUNSTABLE when the norm is not finite or exceeds

@@ -1,8 +1,8 @@
 """Compile libsfm.so (HIP C++ for gfx950) in-tree.
 
 Usage: python -m paper_1406_6923_amd.build_lib  (or build() from Python).
-Every HIP source is compiled with packed-FP32 instructions disabled and the
-objects are linked against rocBLAS (plain FP64 GEMM/TRSM of the ROM build).
+Every HIP source is compiled with packed-FP32 instructions disabled; the library links
+only the HIP runtime (every kernel, the ROM build's FP64 products included, is in csrc/).
 """
 from __future__ import annotations
 
@@ -66,7 +66,7 @@ def build(verbose: bool = False, debug: bool = False) -> str:
         objs = list(ex.map(lambda s: _compile(s, verbose, debug), srcs))
     tmp = lib + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp,
-           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+           "-Wl,-rpath,/opt/rocm/lib"]
     if debug:
         cmd += ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
     if verbose:

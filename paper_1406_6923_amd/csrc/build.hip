@@ -19,7 +19,6 @@
 //      U(0) = G Z^T M^{1/2} u0.
 // The reductions run in FP64 on the device; the large dense products (Z^T W, Z C, W^T W and the
 // products with the inverse Cholesky factors) are plain rocBLAS strided-batched DGEMM calls.
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -608,13 +607,6 @@ unsigned grid_for(int64_t n, int threads = 256) {
 
 }  // namespace
 
-void destroy_blas(sfm_ctx c) {
-  if (c->blas) {
-    rocblas_destroy_handle(static_cast<rocblas_handle>(c->blas));
-    c->blas = nullptr;
-  }
-}
-
 }  // namespace sfm
 
 using namespace sfm;
@@ -623,13 +615,6 @@ using namespace sfm;
   do {                                                                                       \
     hipError_t e_ = (call);                                                                  \
     if (e_ != hipSuccess) return c->fail(SFM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-#define B_TRY_BLAS(call)                                                                      \
-  do {                                                                                        \
-    rocblas_status s_ = (call);                                                               \
-    if (s_ != rocblas_status_success)                                                         \
-      return c->fail(SFM_EHIP, std::string(#call) + ": " + rocblas_status_to_string(s_));     \
   } while (0)
 
 #define B_LAUNCH(kernel, n, ...)                                                              \
@@ -686,15 +671,6 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
   sfm_status rc = locate_points(c, nsrc, src_ijk, nrec, rec_ijk, src_sub, src_local, rec_sub, rec_local);
   if (rc != SFM_OK) return rc;
 
-  if (!c->blas) {
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success) return c->fail(SFM_EHIP, "rocblas_create_handle failed");
-    c->blas = h;
-  }
-  rocblas_handle h = static_cast<rocblas_handle>(c->blas);
-  B_TRY_BLAS(rocblas_set_stream(h, st));
-  B_TRY_BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
-
   release_roms(c);
   hipError_t e = hipSuccess;
   c->coef64_d = static_cast<double*>(c->dalloc((size_t)S * 2 * k * pp * sizeof(double), &e));
@@ -749,6 +725,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
   int32_t* flags = sc.get<int32_t>((size_t)nbmax + 1);
   int32_t* meta = sc.get<int32_t>((size_t)nbmax * 5);
   int32_t* pts = sc.get<int32_t>((size_t)(std::max(nsrc, nrec) + 1) * 3);
+  double* gw = sc.get(kGemmWorkBytes / sizeof(double));      // split-reduction partial tiles
   // finite shift: PCG vectors, reduced operator and reduced-space basis
   double *Dinv = nullptr, *Rv = nullptr, *Pv = nullptr, *Qv = nullptr, *part = nullptr, *cgs = nullptr;
   double *At = nullptr, *Zh = nullptr;
@@ -768,7 +745,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
   if (sc.e != hipSuccess) return c->fail(SFM_ENOMEM, "ROM build scratch: out of device memory (lower build_batch)");
   std::vector<double> Hall((size_t)S * p);
   const double one = 1.0, zero = 0.0, mone = -1.0;
-  const rocblas_operation NN = rocblas_operation_none, TT = rocblas_operation_transpose;
+  const bool NN = false, TT = true;   // operand not transposed / transposed
 
   const char* vb = std::getenv("SFM_VERBOSE");
   const bool verbose = vb && vb[0] && vb[0] != '0';
@@ -868,24 +845,17 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
         // classical Gram-Schmidt against every block so far (C1), which removes only the rounding
         // drift left after the recurrence; A_j = sym(C2_j + C1_j).
         double* C2j = C2 + (int64_t)jj * p * p;
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, p, (int)rows, &one, W, ldw, sW, Zb + (int64_t)jj * p, kp,
-                                                 sZb, &zero, last ? C1 + (int64_t)jj * p * p : C2j, p,
-                                                 (int64_t)kp * p, nb));
+        B_TRY_HIP(dgemm_batched(NN, TT, p, p, (int)rows, one, W, ldw, sW, Zb + (int64_t)jj * p, kp, sZb, zero, last ? C1 + (int64_t)jj * p * p : C2j, p, (int64_t)kp * p, nb, st, gw, kGemmWorkBytes));
         if (last) {
           B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, (const double*)nullptr, p, (int64_t)kp * p, jj * p,
                    A + (int64_t)jj * pp, (int64_t)k * pp, nb);
           break;
         }
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)rows, p, &mone, C2j, p, (int64_t)kp * p,
-                                                 Zb + (int64_t)jj * p, kp, sZb, &one, W, ldw, sW, nb));
+        B_TRY_HIP(dgemm_batched(NN, NN, p, (int)rows, p, mone, C2j, p, (int64_t)kp * p, Zb + (int64_t)jj * p, kp, sZb, one, W, ldw, sW, nb, st, gw, kGemmWorkBytes));
         if (jj > 0)   // Q_{j-1}^T A Q_j = B_j^T: in the C form its transpose, B_j (Bt holds B_j^T column-major)
-          B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, (int)rows, p, &mone, Bt + (int64_t)jj * pp, p,
-                                                   (int64_t)k * pp, Zb + (int64_t)(jj - 1) * p, kp, sZb, &one, W, ldw,
-                                                   sW, nb));
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, nprev, (int)rows, &one, W, ldw, sW, Zb, kp, sZb, &zero,
-                                                 C1, p, (int64_t)kp * p, nb));
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)rows, nprev, &mone, C1, p, (int64_t)kp * p, Zb, kp,
-                                                 sZb, &one, W, ldw, sW, nb));
+          B_TRY_HIP(dgemm_batched(TT, NN, p, (int)rows, p, mone, Bt + (int64_t)jj * pp, p, (int64_t)k * pp, Zb + (int64_t)(jj - 1) * p, kp, sZb, one, W, ldw, sW, nb, st, gw, kGemmWorkBytes));
+        B_TRY_HIP(dgemm_batched(NN, TT, p, nprev, (int)rows, one, W, ldw, sW, Zb, kp, sZb, zero, C1, p, (int64_t)kp * p, nb, st, gw, kGemmWorkBytes));
+        B_TRY_HIP(dgemm_batched(NN, NN, p, (int)rows, nprev, mone, C1, p, (int64_t)kp * p, Zb, kp, sZb, one, W, ldw, sW, nb, st, gw, kGemmWorkBytes));
         B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, C2, p, (int64_t)kp * p, jj * p, A + (int64_t)jj * pp,
                  (int64_t)k * pp, nb);
         // Cholesky QR, twice: W = Q (L1 L2)^T.  Each pass multiplies by the inverse of its
@@ -900,20 +870,16 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
           double* dst = pass == 0 ? Wl : W;
           const int ldst = pass == 0 ? p : ldw;
           const int64_t sdst = pass == 0 ? rows * p : sW;
-          B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, p, (int)rows, &one, src, lsrc, ssrc, src, lsrc, ssrc,
-                                                   &zero, Ls[pass], p, pp, nb));
+          B_TRY_HIP(dgemm_batched(NN, TT, p, p, (int)rows, one, src, lsrc, ssrc, src, lsrc, ssrc, zero, Ls[pass], p, pp, nb, st, gw, kGemmWorkBytes));
           hipLaunchKernelGGL(cholesky_kernel, dim3(nb), dim3(256), 0, st, Ls[pass], p, pp,
                              pass == 0 ? thrp : (const double*)nullptr, kGramRelTol, flags);
           B_TRY_HIP(hipGetLastError());
-          B_TRY_BLAS(rocblas_dtrtri_strided_batched(h, rocblas_fill_lower, rocblas_diagonal_non_unit, p, Ls[pass], p, pp,
-                                                    T1, p, pp, nb));
+          B_TRY_HIP(trtri_lower_batched(Ls[pass], pp, T1, pp, p, nb, st));
           B_LAUNCH(zero_upper_kernel, (int64_t)nb * pp, T1, p, pp, nb);
-          B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, (int)rows, p, &one, T1, p, pp, src, lsrc, ssrc, &zero,
-                                                   dst, ldst, sdst, nb));   // dst^T = L^{-1} src^T
+          B_TRY_HIP(dgemm_batched(NN, NN, p, (int)rows, p, one, T1, p, pp, src, lsrc, ssrc, zero, dst, ldst, sdst, nb, st, gw, kGemmWorkBytes));   // dst^T = L^{-1} src^T
         }
         // B_{j+1}^T = L1 L2
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, p, p, &one, L1, p, pp, L2, p, pp, &zero,
-                                                 Bt + (int64_t)(jj + 1) * pp, p, (int64_t)k * pp, nb));
+        B_TRY_HIP(dgemm_batched(NN, NN, p, p, p, one, L1, p, pp, L2, p, pp, zero, Bt + (int64_t)(jj + 1) * pp, p, (int64_t)k * pp, nb, st, gw, kGemmWorkBytes));
       }
       return SFM_OK;
     };
@@ -981,16 +947,14 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
       // A~ = V^T A_+ V, one block row at a time (symmetric: rows jj*p.. of the column-major kp x kp)
       for (int jj = 0; jj < k; ++jj) {
         B_LAUNCH(stencil_kernel, (int64_t)nb * N * p, g, Sd, N, nb, Z + (int64_t)jj * p, kp, sZ, Wl, p, N * p, 0.0);
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, kp, (int)N, &one, Wl, p, N * p, Z, kp, sZ, &zero,
-                                                 At + (int64_t)jj * p, kp, kpkp, nb));
+        B_TRY_HIP(dgemm_batched(NN, TT, p, kp, (int)N, one, Wl, p, N * p, Z, kp, sZ, zero, At + (int64_t)jj * p, kp, kpkp, nb, st, gw, kGemmWorkBytes));
       }
       B_LAUNCH(symmetrize_kernel, (int64_t)nb * kpkp, At, kp, kpkp, nb);
       // block Lanczos on (A~, E_1 B_1): Q~_1 = E_1, same B_1^T = diag(H^{1/2})
       B_LAUNCH(eye_block_kernel, (int64_t)nb * kp * p, kp, p, nb, Zh, kpkp);
       rc = lanczos(Zh, kp, k, thr, [&](int jj, double* W, int ldw, int64_t sW) -> sfm_status {
         // W^T = Q~_j^T A~ (column-major p x kp)
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, kp, kp, &one, Zh + (int64_t)jj * p, kp, kpkp, At, kp,
-                                                 kpkp, &zero, W, ldw, sW, nb));
+        B_TRY_HIP(dgemm_batched(NN, NN, p, kp, kp, one, Zh + (int64_t)jj * p, kp, kpkp, At, kp, kpkp, zero, W, ldw, sW, nb, st, gw, kGemmWorkBytes));
         return SFM_OK;
       });
       if (rc != SFM_OK) return rc;
@@ -999,8 +963,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
       for (int64_t n0 = 0; n0 < N; n0 += nc) {
         const int64_t nn = std::min(nc, N - n0);
         B_LAUNCH(copy_blocks_kernel, (int64_t)nb * nn * kp, Z + n0 * kp, sZ, Wl, N * p, nn * kp, nb, 1.0);
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, kp, (int)nn, kp, &one, Zh, kp, kpkp, Wl, kp, N * p, &zero,
-                                                 Z + n0 * kp, kp, sZ, nb));
+        B_TRY_HIP(dgemm_batched(NN, NN, kp, (int)nn, kp, one, Zh, kp, kpkp, Wl, kp, N * p, zero, Z + n0 * kp, kp, sZ, nb, st, gw, kGemmWorkBytes));
       }
     }
     // a3: S-fraction
@@ -1011,16 +974,14 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
       double* Gj = G + jj * pp;
       double* Gij = Gi + jj * pp;
       double* Gamj = Gam + jj * pp;
-      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, TT, p, p, p, &one, Gj, p, sk, Gj, p, sk, &zero, Gh + jj * pp, p, sk,
-                                               nb));
+      B_TRY_HIP(dgemm_batched(NN, TT, p, p, p, one, Gj, p, sk, Gj, p, sk, zero, Gh + jj * pp, p, sk, nb, st, gw, kGemmWorkBytes));
       B_LAUNCH(symmetrize_kernel, (int64_t)nb * pp, Gh + jj * pp, p, sk, nb);
-      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, NN, NN, p, p, p, &one, A + jj * pp, p, sk, Gij, p, sk, &zero, T1, p, pp,
-                                               nb));
+      B_TRY_HIP(dgemm_batched(NN, NN, p, p, p, one, A + jj * pp, p, sk, Gij, p, sk, zero, T1, p, pp, nb, st, gw, kGemmWorkBytes));
       if (jj == 0) {
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, p, p, &one, Gij, p, sk, T1, p, pp, &zero, Gamj, p, sk, nb));
+        B_TRY_HIP(dgemm_batched(TT, NN, p, p, p, one, Gij, p, sk, T1, p, pp, zero, Gamj, p, sk, nb, st, gw, kGemmWorkBytes));
       } else {
         B_LAUNCH(copy_blocks_kernel, (int64_t)nb * pp, Gam + (jj - 1) * pp, sk, Gamj, sk, pp, nb, 1.0);
-        B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, p, p, &one, Gij, p, sk, T1, p, pp, &mone, Gamj, p, sk, nb));
+        B_TRY_HIP(dgemm_batched(TT, NN, p, p, p, one, Gij, p, sk, T1, p, pp, mone, Gamj, p, sk, nb, st, gw, kGemmWorkBytes));
       }
       B_LAUNCH(symmetrize_kernel, (int64_t)nb * pp, Gamj, p, sk, nb);
       if (jj + 1 == kb) break;
@@ -1032,15 +993,12 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
       double* Gin = Gi + (jj + 1) * pp;
       double* Btn = Bt + (jj + 1) * pp;
       // G_{j+1} = -Gamma_j^{-1} G_j^{-T} B_{j+1}^T
-      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, p, p, &one, Gij, p, sk, Btn, p, sk, &zero, Gn, p, sk, nb));
-      B_TRY_BLAS(rocblas_dtrsm_strided_batched(h, rocblas_side_left, rocblas_fill_lower, NN, rocblas_diagonal_non_unit,
-                                               p, p, &mone, L1, p, pp, Gn, p, sk, nb));
-      B_TRY_BLAS(rocblas_dtrsm_strided_batched(h, rocblas_side_left, rocblas_fill_lower, TT, rocblas_diagonal_non_unit,
-                                               p, p, &one, L1, p, pp, Gn, p, sk, nb));
+      B_TRY_HIP(dgemm_batched(TT, NN, p, p, p, one, Gij, p, sk, Btn, p, sk, zero, Gn, p, sk, nb, st, gw, kGemmWorkBytes));
+      B_TRY_HIP(trsm_lower_batched(false, -1.0, L1, pp, Gn, sk, p, nb, st));
+      B_TRY_HIP(trsm_lower_batched(true, 1.0, L1, pp, Gn, sk, p, nb, st));
       // G_{j+1}^{-1} = -B_{j+1}^{-T} G_j^T Gamma_j
-      B_TRY_BLAS(rocblas_dgemm_strided_batched(h, TT, NN, p, p, p, &one, Gj, p, sk, Gamj, p, sk, &zero, Gin, p, sk, nb));
-      B_TRY_BLAS(rocblas_dtrsm_strided_batched(h, rocblas_side_left, rocblas_fill_lower, NN, rocblas_diagonal_non_unit,
-                                               p, p, &mone, Btn, p, sk, Gin, p, sk, nb));
+      B_TRY_HIP(dgemm_batched(TT, NN, p, p, p, one, Gj, p, sk, Gamj, p, sk, zero, Gin, p, sk, nb, st, gw, kGemmWorkBytes));
+      B_TRY_HIP(trsm_lower_batched(false, -1.0, Btn, sk, Gin, sk, p, nb, st));
     }
     // coefficients to the FP64 store [S][2][k][p][p] (symmetric: column-major = row-major)
     B_LAUNCH(scatter_blocks_kernel, (int64_t)nb * kb * pp, Gam, sk, c->coef64_d, 2 * sk, (int64_t)kb * pp, nb, ids_d);

@@ -379,7 +379,6 @@ void sfm_destroy(sfm_ctx c) {
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   sfm::drop_shot_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  destroy_blas(c);
   c->dfree_all();
   (void)hipSetDevice(cur);
   delete c;

@@ -207,9 +207,22 @@ hipError_t clear_extra_levels(sfm_ctx c, float* X, int cols, hipStream_t st);
 sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, float* u_out,
                         hipStream_t st);
 StepParams step_params(sfm_ctx c);
+// Batched FP64 kernels of the ROM build (dgemm.hip), column-major like BLAS:
+//   C_b = alpha op(A_b) op(B_b) + beta C_b, op(X) = X^T when tX.  work (work_bytes) holds the partial
+//   tiles of split reductions (a split is only used when they fit; kMaxGemmSplit splits at most).
+constexpr int kMaxGemmSplit = 16;
+constexpr size_t kGemmWorkBytes = (size_t)8 * 4096 * 96 * 96;   // 4096 partial tiles of 96 x 96
+hipError_t dgemm_batched(bool tA, bool tB, int M, int N, int K, double alpha, const double* A, int64_t lda,
+                         int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc,
+                         int64_t sC, int batch, hipStream_t st, double* work, size_t work_bytes);
+//   X_b = L_b^{-1}, L lower triangular non-unit p x p (ld p); X's strict upper triangle is zeroed.
+hipError_t trtri_lower_batched(const double* L, int64_t sL, double* X, int64_t sX, int p, int batch, hipStream_t st);
+//   B_b <- alpha op(L_b)^{-1} B_b, L lower triangular non-unit, B p x p (ld p each).
+hipError_t trsm_lower_batched(bool trans, double alpha, const double* L, int64_t sL, double* B, int64_t sB, int p,
+                              int batch, hipStream_t st);
+
 // a = a(u) of the coupled scheme without forcing, [S][k][P16] each (step kernels in operator mode).
 hipError_t apply_operator(sfm_ctx c, const float* u, float* a, hipStream_t st);
-void destroy_blas(sfm_ctx c);
 
 }  // namespace sfm
 
@@ -295,7 +308,6 @@ struct sfm_ctx_s {
   double wd_max_norm = 0.0;
   int64_t wd_checks = 0;
   double build_seconds = 0.0;
-  void* blas = nullptr;             // rocblas_handle of the ROM build (created on first use)
   // per-kernel timing of sfm_step (events recorded on the caller's stream)
   bool timing = false;
   std::vector<hipEvent_t> ev;       // 4 events per timed step: main start, face start, record start, end

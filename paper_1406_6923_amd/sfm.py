@@ -102,6 +102,8 @@ SIGNATURES = {
     "sfm_cfl_dt": (_I32, [_VP, _I32, ctypes.POINTER(_D), _VP]),
     "sfm_step": (_I32, [_VP, _I32, _D, _VP, _VP, _I64, _VP]),
     "sfm_set_watchdog": (_I32, [_VP, _I32, _D]),
+    "sfm_dgemm_batched": (_I32, [_I32, _I32, _I32, _I32, _I32, _D, _VP, _I64, _I64, _VP, _I64, _I64, _D, _VP, _I64,
+                                 _I64, _I32, _VP, _I64, _VP]),
     "sfm_cfl_dt_noalloc": (_I32, [_VP, _I32, ctypes.POINTER(_D), _VP]),
     "sfm_record_receivers": (_I32, [_VP, _VP, _VP]),
     "sfm_apply_operator": (_I32, [_VP, _VP, _VP, _VP]),
@@ -274,6 +276,19 @@ def sfm_cfl_dt_noalloc(ctx: int, iters: int = 200, stream=None) -> float:
     out = _D()
     _check(ctx, load_library().sfm_cfl_dt_noalloc(ctx, int(iters), ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def sfm_dgemm_batched(trans_a: bool, trans_b: bool, M: int, N: int, K: int, alpha: float, A, lda: int, stride_a: int,
+                      B, ldb: int, stride_b: int, beta: float, C, ldc: int, stride_c: int, batch: int, work=None,
+                      stream=None) -> None:
+    """Column-major batched FP64 product on device tensors (see include/sfm.h)."""
+    wb = work.numel() * work.element_size() if work is not None else 0
+    st = load_library().sfm_dgemm_batched(int(bool(trans_a)), int(bool(trans_b)), int(M), int(N), int(K), float(alpha),
+                                          _dev(A), int(lda), int(stride_a), _dev(B), int(ldb), int(stride_b),
+                                          float(beta), _dev(C), int(ldc), int(stride_c), int(batch), _dev(work),
+                                          int(wb), _stream(stream))
+    if st != SFM_OK:
+        raise SfmError(st, "sfm_dgemm_batched failed")
 
 
 def sfm_set_watchdog(ctx: int, every: int, max_norm: float = float("inf")) -> None:
