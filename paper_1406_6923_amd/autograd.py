@@ -2,7 +2,7 @@
 blocks (torch.autograd), backed by the library's forward step and its discrete adjoint.
 
     model = RomTraces(handle, src_ijk, src_vec, rec_ijk, rec_rows, dt, wavelet, nsteps)
-    traces = rom_traces(gamma, gamma_hat, model)        # gamma, gamma_hat: float64 [S][k][p][p]
+    traces = rom_traces(gamma, gamma_hat, model)        # gamma, gamma_hat: [S][k][p][p], any device
     loss = 0.5 * ((traces - observed) ** 2).sum()
     loss.backward()                                       # gamma.grad, gamma_hat.grad
 
@@ -62,12 +62,15 @@ class _RomTracesFn(torch.autograd.Function):
         gh = gamma_hat.detach().cpu().numpy().astype(np.float64)
         ctx.model = model
         ctx.blocks = (g, gh)
+        # each gradient goes back on its input's device and in its dtype
+        ctx.like = ((gamma.device, gamma.dtype), (gamma_hat.device, gamma_hat.dtype))
         return model.forward(g, gh)
 
     @staticmethod
     def backward(ctx, grad_traces):
         g_gam, g_hat = ctx.model.backward(*ctx.blocks, grad_traces)
-        return torch.from_numpy(g_gam), torch.from_numpy(g_hat), None
+        (dg, tg), (dh, th) = ctx.like
+        return torch.from_numpy(g_gam).to(dg, tg), torch.from_numpy(g_hat).to(dh, th), None
 
 
 def rom_traces(gamma: torch.Tensor, gamma_hat: torch.Tensor, model: RomTraces) -> torch.Tensor:

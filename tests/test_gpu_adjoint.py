@@ -81,16 +81,19 @@ def test_adjoint_autograd_function():
                       torch.tensor(wav, dtype=torch.float32, device="cuda"), nsteps, checkpoint_every=50)
     traces_ref, _ = adjoint.forward(cs, dt, wav)
     observed = torch.tensor(0.8 * traces_ref, dtype=torch.float32, device="cuda")
-    g = torch.tensor(gam, requires_grad=True)
-    gh = torch.tensor(hat, requires_grad=True)
-    tr = rom_traces(g, gh, model)
-    loss = 0.5 * ((tr - observed) ** 2).sum()
-    loss.backward()
     J, r_gam, r_hat = adjoint.gradient(cs, dt, wav, 0.8 * traces_ref)
-    e = max(rel_l2(g.grad.numpy(), r_gam), rel_l2(gh.grad.numpy()[:, 1:], r_hat[:, 1:]))
-    print(f"autograd: loss {loss.item():.6e} (oracle {J:.6e}), gradient rel-L2 {e:.2e}")
-    assert abs(loss.item() - J) < 1e-4 * J
-    assert e < 1e-4
+    # blocks on the host, then on the device (gradients come back where the blocks live)
+    for dev in ("cpu", "cuda"):
+        g = torch.tensor(gam, requires_grad=True, device=dev)
+        gh = torch.tensor(hat, requires_grad=True, device=dev)
+        tr = rom_traces(g, gh, model)
+        loss = 0.5 * ((tr - observed) ** 2).sum()
+        loss.backward()
+        assert g.grad.device == g.device and gh.grad.dtype == gh.dtype
+        e = max(rel_l2(g.grad.cpu().numpy(), r_gam), rel_l2(gh.grad.cpu().numpy()[:, 1:], r_hat[:, 1:]))
+        print(f"autograd ({dev} blocks): loss {loss.item():.6e} (oracle {J:.6e}), gradient rel-L2 {e:.2e}")
+        assert abs(loss.item() - J) < 1e-4 * J
+        assert e < 1e-4
     h.close()
 
 
