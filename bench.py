@@ -103,15 +103,22 @@ def cpu_baseline(cfg: W.Workload, c_full: np.ndarray, dt_ratio: float, nsub=(1, 
     t0 = time.perf_counter()
     fg.fdtd(dtf, W.ricker(cfg.f_peak, dtf, nf)[:, None], src, np.array([[1, 1, 0]]))
     fdtd_rate = cells * nf / (time.perf_counter() - t0) / 1e9
+    value = cells * nsteps * dt_ratio / t_step / 1e9
+    # The step loop's per-subdomain products are small: if one BLAS thread runs it as fast as the
+    # whole pool, the oracle effectively used one core.
+    used = 1 if (one_thread is not None and one_thread >= 0.85 * value) else int(threads)
     return {
-        "value": cells * nsteps * dt_ratio / t_step / 1e9,
+        "value": value,
         "unit": "Gcell-updates/s (fine-grid-equivalent)",
-        "cores": int(threads),
+        "cores": used,
+        "blas_threads": int(threads),
         "kind": "oracle",
         "sample": (f"{nsub[0]}x{nsub[1]}x{nsub[2]} subdomains ({cells} cells) cut from the same velocity model, "
                    f"same subdomain size and ROM sizes; oracle ROM build of those subdomains "
                    f"({len(subs) / t_build:.3f} builds/s, not in value) then {nsteps} FP64 leapfrog steps "
-                   f"of the coupled ROMs timed; dt ratio taken from the GPU run"),
+                   f"of the coupled ROMs timed; dt ratio taken from the GPU run; cores = 1 when the "
+                   f"one-thread rate matches the {int(threads)}-thread rate (the products are too small to "
+                   f"parallelise)"),
         "builds_per_s": len(subs) / t_build,
         "step_seconds": t_step,
         "value_one_thread": one_thread,
@@ -161,6 +168,37 @@ def finite_shift_probe(torch, sfm, dev, stream, n: int = 4, steps: int = 200, si
     log(f"[bench] finite shift sigma = {sigma:.3g}: {out['builds_per_s']:.1f} builds/s "
         f"(sigma = inf {out['sigma_inf_builds_per_s']:.1f}), at most {iters} CG iterations, "
         f"dt x{out['dt_ratio_vs_sigma_inf']:.3f}, FP64 step kernel {main_ms:.4f} ms ({out['fp64_main_gbs']:.0f} GB/s)")
+    return out
+
+
+def fp64_stream_probe(torch, sfm, h, cfg: W.Workload, dt: float, dt_ratio: float, finite_dt_gain, steps: int = 100):
+    """The FP64 coefficient stream (the finite-shift path's step) at the full workload's scale: the
+    run's own ROMs loaded into an FP64-storage context, the step kernel timed over `steps` steps.
+    Combined with the finite-shift probe's dt gain this is the finite-shift stepping rate at scale."""
+    gam, hat = sfm.sfm_export_roms(h.ctx)
+    h64 = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k, precision=sfm.SFM_PREC_FP64)
+    sfm.sfm_load_roms(h64.ctx, gam, hat)
+    del gam, hat
+    sfm.sfm_set_state(h64.ctx, None, None, 0)      # zero state, no sources: the stream is the same
+    sfm.sfm_step(h64.ctx, 10, dt, None, None)
+    sfm.sfm_set_timing(h64.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sfm.sfm_step(h64.ctx, steps, dt, None, None)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = h64.info()
+    h64.close()
+    S, k, p = info["n_subdomains"], info["k"], info["p"]
+    main_ms = info["timed_main_ms"] / max(info["timed_steps"], 1)
+    launch_bytes = S * ((2 * k - 1) * p * (p + 1) // 2 * 8 + 3 * k * p * 4)
+    out = {"subdomains": S, "main_ms": main_ms, "main_gbs": launch_bytes / (main_ms * 1e-3) / 1e9,
+           "ms_per_step": wall / steps * 1e3,
+           "gcell_per_s_at_sigma_inf_dt": cfg.n_cells * steps * dt_ratio / wall / 1e9}
+    if finite_dt_gain:
+        out["finite_shift_gcell_per_s_estimate"] = out["gcell_per_s_at_sigma_inf_dt"] * finite_dt_gain
+    log(f"[bench] FP64 coefficient stream at {S} subdomains: main kernel {main_ms:.4f} ms "
+        f"({out['main_gbs']:.0f} GB/s), {out['ms_per_step']:.4f} ms/step")
     return out
 
 
@@ -676,6 +714,9 @@ def main():
         out["learned_roms"] = surrogate_probe(torch, sfm, dev, stream, args.surrogate_samples, args.surrogate_epochs)
     if not args.no_finite_shift:
         out["finite_shift"] = finite_shift_probe(torch, sfm, dev, stream)
+        if prec == sfm.SFM_PREC_FP32:
+            out["finite_shift"]["fp64_stream_at_scale"] = fp64_stream_probe(
+                torch, sfm, h, cfg, dt, ratio, out["finite_shift"]["dt_ratio_vs_sigma_inf"])
     if args.adjoint_steps:
         out["adjoint"] = adjoint_probe(torch, sfm, dev, stream, args.adjoint_steps,
                                        args.adjoint_checkpoint or args.adjoint_steps)

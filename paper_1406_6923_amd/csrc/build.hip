@@ -36,6 +36,13 @@ namespace {
 // Relative Gram pivot below which a Lanczos block counts as rank deficient: the independent
 // part of a column is below ~3e-7 of its norm, where Cholesky QR can no longer orthogonalise it.
 constexpr double kGramRelTol = 1e-13;
+// Gamma_j (j < k) and Gamma-hat_j = G_j G_j^T (j >= 2) must be positive definite: a Cholesky pivot
+// at or below 1e-13 of its diagonal entry is rounding-level in FP64, so such a level is reported as
+// a breakdown rather than left to the sign of a rounding error.  Gamma-hat_j squares the
+// conditioning of G_j, so a near-singular level falls to ~1e-16 whatever the rounding order.  The
+// S-fraction levels of the workloads here keep every pivot above 1.6e-11 of its diagonal (the
+// k = 32 polynomial ROMs of the many-shot workload; 2e-10 and up for finite shifts).
+constexpr double kGammaRelTol = 1e-13;
 
 struct BoxGeo {
   int sub[3];        // cells per edge
@@ -601,6 +608,19 @@ __global__ void unify_ports_kernel(const int32_t* __restrict__ nbr, int S, int k
   if (nb >= 0 && nb < s) U[(int64_t)s * k * P16 + q] = U[(int64_t)nb * k * P16 + (f ^ 1) * m + pat];
 }
 
+// A_b = [B_j | C2_j] (p x 2p, column-major, ld p): B_j from its stored transpose (column-major
+// B_j^T at Bt), then the recurrence's projection C2_j, so that W -= Q_{j-1} B_j^T + Q_j A_j is one
+// product with the adjacent basis blocks [Q_{j-1} Q_j].
+__global__ void recurrence_coef_kernel(const double* __restrict__ Bt, int64_t sBt, const double* __restrict__ C2,
+                                       int64_t sC2, int p, int nb, double* __restrict__ Af) {
+  const int64_t per = 2 * (int64_t)p * p;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < per * nb; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / per, q = e - b * per;
+    const int c = (int)(q / p), r = (int)(q - (int64_t)c * p);
+    Af[e] = c < p ? Bt[b * sBt + c + (int64_t)r * p] : C2[b * sC2 + r + (int64_t)(c - p) * p];
+  }
+}
+
 unsigned grid_for(int64_t n, int threads = 256) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + threads - 1) / threads, 1 << 20));
 }
@@ -726,6 +746,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
   int32_t* meta = sc.get<int32_t>((size_t)nbmax * 5);
   int32_t* pts = sc.get<int32_t>((size_t)(std::max(nsrc, nrec) + 1) * 3);
   double* gw = sc.get(kGemmWorkBytes / sizeof(double));      // split-reduction partial tiles
+  double* Af = sc.get((size_t)nbmax * 2 * pp);                // [B_j | C2_j] of the fused recurrence update
   // finite shift: PCG vectors, reduced operator and reduced-space basis
   double *Dinv = nullptr, *Rv = nullptr, *Pv = nullptr, *Qv = nullptr, *part = nullptr, *cgs = nullptr;
   double *At = nullptr, *Zh = nullptr;
@@ -851,9 +872,17 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
                    A + (int64_t)jj * pp, (int64_t)k * pp, nb);
           break;
         }
-        B_TRY_HIP(dgemm_batched(NN, NN, p, (int)rows, p, mone, C2j, p, (int64_t)kp * p, Zb + (int64_t)jj * p, kp, sZb, one, W, ldw, sW, nb, st, gw, kGemmWorkBytes));
-        if (jj > 0)   // Q_{j-1}^T A Q_j = B_j^T: in the C form its transpose, B_j (Bt holds B_j^T column-major)
-          B_TRY_HIP(dgemm_batched(TT, NN, p, (int)rows, p, mone, Bt + (int64_t)jj * pp, p, (int64_t)k * pp, Zb + (int64_t)(jj - 1) * p, kp, sZb, one, W, ldw, sW, nb, st, gw, kGemmWorkBytes));
+        if (jj == 0) {
+          B_TRY_HIP(dgemm_batched(NN, NN, p, (int)rows, p, mone, C2j, p, (int64_t)kp * p, Zb, kp, sZb, one, W, ldw, sW,
+                                  nb, st, gw, kGemmWorkBytes));
+        } else {
+          // W -= Q_{j-1} B_j^T + Q_j A_j as one product over the adjacent blocks (Q_{j-1}^T A Q_j = B_j^T: in
+          // the C form its transpose, B_j; Bt holds B_j^T column-major)
+          B_LAUNCH(recurrence_coef_kernel, (int64_t)nb * 2 * pp, Bt + (int64_t)jj * pp, (int64_t)k * pp, C2j,
+                   (int64_t)kp * p, p, nb, Af);
+          B_TRY_HIP(dgemm_batched(NN, NN, p, (int)rows, 2 * p, mone, Af, p, 2 * pp, Zb + (int64_t)(jj - 1) * p, kp, sZb,
+                                  one, W, ldw, sW, nb, st, gw, kGemmWorkBytes));
+        }
         B_TRY_HIP(dgemm_batched(NN, TT, p, nprev, (int)rows, one, W, ldw, sW, Zb, kp, sZb, zero, C1, p, (int64_t)kp * p, nb, st, gw, kGemmWorkBytes));
         B_TRY_HIP(dgemm_batched(NN, NN, p, (int)rows, nprev, mone, C1, p, (int64_t)kp * p, Zb, kp, sZb, one, W, ldw, sW, nb, st, gw, kGemmWorkBytes));
         B_LAUNCH(accum_a_kernel, (int64_t)nb * pp, C1, C2, p, (int64_t)kp * p, jj * p, A + (int64_t)jj * pp,
@@ -976,6 +1005,12 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
       double* Gamj = Gam + jj * pp;
       B_TRY_HIP(dgemm_batched(NN, TT, p, p, p, one, Gj, p, sk, Gj, p, sk, zero, Gh + jj * pp, p, sk, nb, st, gw, kGemmWorkBytes));
       B_LAUNCH(symmetrize_kernel, (int64_t)nb * pp, Gh + jj * pp, p, sk, nb);
+      if (jj > 0) {   // Gamma-hat_j = G_j G_j^T must be positive definite at the FP64 level (kGammaRelTol)
+        B_LAUNCH(copy_blocks_kernel, (int64_t)nb * pp, Gh + jj * pp, sk, L2, pp, pp, nb, 1.0);
+        hipLaunchKernelGGL(cholesky_kernel, dim3(nb), dim3(256), 0, st, L2, p, pp, (const double*)nullptr,
+                           kGammaRelTol, flags);
+        B_TRY_HIP(hipGetLastError());
+      }
       B_TRY_HIP(dgemm_batched(NN, NN, p, p, p, one, A + jj * pp, p, sk, Gij, p, sk, zero, T1, p, pp, nb, st, gw, kGemmWorkBytes));
       if (jj == 0) {
         B_TRY_HIP(dgemm_batched(TT, NN, p, p, p, one, Gij, p, sk, T1, p, pp, zero, Gamj, p, sk, nb, st, gw, kGemmWorkBytes));
@@ -987,7 +1022,8 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
       if (jj + 1 == kb) break;
       // Cholesky of Gamma_j (must be SPD for j < k)
       B_LAUNCH(copy_blocks_kernel, (int64_t)nb * pp, Gamj, sk, L1, pp, pp, nb, 1.0);
-      hipLaunchKernelGGL(cholesky_kernel, dim3(nb), dim3(256), 0, st, L1, p, pp, (const double*)nullptr, 0.0, flags);
+      hipLaunchKernelGGL(cholesky_kernel, dim3(nb), dim3(256), 0, st, L1, p, pp, (const double*)nullptr, kGammaRelTol,
+                         flags);
       B_TRY_HIP(hipGetLastError());
       double* Gn = G + (jj + 1) * pp;
       double* Gin = Gi + (jj + 1) * pp;
@@ -1051,7 +1087,8 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
     for (int b = 0; b < nb && status == SFM_OK; ++b)
       if (fl[b])
         status = c->fail(SFM_EBREAKDOWN, "subdomain " + std::to_string(ids[b]) +
-                                             ": block Lanczos breakdown or non-SPD Gamma_j");
+                                             ": block Lanczos breakdown, or an S-fraction level that is not positive definite "
+                                             "at the FP64 level");
   }
   if (status != SFM_OK) {
     release_roms(c);

@@ -27,7 +27,10 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBK = 16;            // K per LDS stage
+#ifndef SFM_GEMM_BK
+#define SFM_GEMM_BK 16
+#endif
+constexpr int kBK = SFM_GEMM_BK;   // K per LDS stage
 constexpr int kGemmThreads = 256;  // four waves
 constexpr int kPad = 2;            // LDS row padding (doubles)
 
