@@ -573,7 +573,10 @@ def main():
     t_build = time.perf_counter() - t0
     log(f"[bench] build {t_build:.2f} s ({S / t_build:.1f} builds/s)")
 
+    t0 = time.perf_counter()
     dt_max = sfm.sfm_cfl_dt(h.ctx, args.cfl_iters, stream=stream)
+    t_cfl = time.perf_counter() - t0
+    log(f"[bench] certified stability limit {dt_max:.6e} s in {t_cfl:.2f} s")
     dt = 0.9 * dt_max
     dt_fine = 0.9 * cfg.h / (math.sqrt(3.0) * c_max)
     ratio = dt / dt_fine
@@ -690,6 +693,7 @@ def main():
             "traffic_note": traffic_note,
         },
         "rom_builds_per_s": S / t_build,
+        "stability_certificate_seconds": t_cfl,
         "build_seconds": t_build,
         "dt_rom": dt,
         "dt_fine": dt_fine,

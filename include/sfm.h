@@ -202,9 +202,10 @@ sfm_status sfm_export_projections(sfm_ctx ctx, double* src_vec, double* rec_rows
  *      passes everywhere bounds max_alpha lambda_max(K^alpha, M^alpha) >= rho (the coupled
  *      Rayleigh quotient is a mediant of the subdomains'), and dt_max = 2 / sqrt(mu).
  * rho_est and mu are reported in sfm_info.  Leaves the state unchanged.  Synchronizes.
- * Errors: SFM_ESTATE (no ROMs), SFM_EINVAL, SFM_ENOMEM (certificate scratch: 5 p^2 doubles for
- * each of min(S, 2048) work-groups), SFM_EUNSTABLE (a stored Gamma-hat_j is not positive
- * definite, or nothing up to 1e6 rho_est passes: no time step is stable). */
+ * Errors: SFM_ESTATE (no ROMs), SFM_EINVAL, SFM_ENOMEM (certificate scratch: 7 p^2 doubles for
+ * each of min(S, 2048) subdomains processed together, plus 8 S bytes), SFM_EUNSTABLE (a stored
+ * Gamma-hat_j is not positive definite, or nothing up to 1e6 rho_est passes: no time step is
+ * stable). */
 sfm_status sfm_cfl_dt(sfm_ctx ctx, int32_t iters, double* dt_max, void* stream);
 
 /* Advance the coupled ROMs nsteps leapfrog steps of size dt (Algorithm 1, Stage 2):
@@ -226,8 +227,9 @@ sfm_status sfm_step(sfm_ctx ctx, int32_t nsteps, double dt, const float* wavelet
  * hipMalloc or hipFree.  Each device holds its own copy of the array, from the first call on that
  * device until the process ends; every call on a device shares it and leaves its contents behind
  * (nothing in it needs to start at zero), so calls that overlap on one device, from any context or
- * thread, race.  Work-groups are limited to those whose 5 (6m)^2 FP64 work matrices fit in 63 MiB
- * (181 at 6m = 96, 25 at 6m = 256), which only lengthens the certificate.
+ * thread, race.  The subdomains processed together are limited to those whose 7 (6m)^2 FP64 work
+ * matrices fit in 62 MiB (125 at 6m = 96, 17 at 6m = 256), which only lengthens the certificate:
+ * every subdomain's arithmetic is the same in any batch, so the result equals sfm_cfl_dt's.
  * Errors: as sfm_cfl_dt except SFM_ENOMEM; SFM_EINVAL for more than 262,144 subdomains. */
 sfm_status sfm_cfl_dt_noalloc(sfm_ctx ctx, int32_t iters, double* dt_max, void* stream);
 

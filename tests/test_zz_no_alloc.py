@@ -1,8 +1,9 @@
 """sfm_cfl_dt_noalloc (the stability limit with its certificate scratch in a static device array)
-against sfm_cfl_dt through the C ABI: the same kernels in the same order, so the limits, estimates
-and bounds agree exactly; two calls in a row on different contexts, the second on a smaller
-system; no device memory is allocated by a call once the array is resident; sizes beyond the
-static limit are rejected."""
+against sfm_cfl_dt through the C ABI: the same kernels, with each subdomain's arithmetic the same in
+any batch of subdomains, so the limits, estimates and bounds agree exactly; two calls in a row on
+different contexts, the second on a smaller system; a system of more subdomains than the static
+array holds at once (smaller batches than the allocating call's); no device memory is allocated by
+a call once the array is resident; sizes beyond the static limit are rejected."""
 import pytest
 
 import workloads as W
@@ -49,6 +50,21 @@ def test_noalloc_limit_equals_the_allocating_call():
     assert ei.value.status == sfm.SFM_EUNSTABLE
     ha.close()
     hb.close()
+
+
+def test_noalloc_limit_with_more_subdomains_than_one_batch():
+    from paper_1406_6923_amd import sfm
+    cfg = W.scaled_large((8, 8, 4))
+    print(f"[case] no-alloc CFL: {cfg.name}, 256 subdomains at 6m = 96 (125 per static batch)", flush=True)
+    c = torch.from_numpy(cfg.velocity_model().astype("float32")).cuda()
+    h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
+    sfm.sfm_build_roms(h.ctx, c, cfg.sources(), cfg.receivers())
+    ref = sfm.sfm_cfl_dt(h.ctx, 50)
+    info = h.info()
+    got = sfm.sfm_cfl_dt_noalloc(h.ctx, 50)
+    print(f"{got:.12e} vs {ref:.12e}; rho bound {h.info()['rho_bound']:.12e} vs {info['rho_bound']:.12e}")
+    assert got == ref and h.info()["rho_bound"] == info["rho_bound"]
+    h.close()
 
 
 def test_noalloc_rejects_sizes_beyond_the_static_scratch():
