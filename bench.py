@@ -635,6 +635,13 @@ def main():
     copy_gbs = 2 * 4 * n * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
     log(f"[bench] device copy {copy_gbs:.0f} GB/s")
+    # Sustained FP64 matrix-core rate on register operands: the practical ceiling of the build's
+    # products and of the FP64 many-shot kernel, beside the published peak.
+    pbuf = torch.empty(4096 * 256, dtype=torch.float64, device=dev)
+    sfm.sfm_probe_fp64_matrix_rate(pbuf, 4096, 200, stream=stream)
+    fp64_mfma = sfm.sfm_probe_fp64_matrix_rate(pbuf, 4096, 2000, stream=stream)
+    del pbuf
+    log(f"[bench] FP64 matrix cores sustain {fp64_mfma:.1f} TFLOP/s (published peak {FP64_MFMA_PEAK_TFLOPS})")
 
     comparators = {}
     if not args.no_comparators:
@@ -704,6 +711,7 @@ def main():
         "traces_finite": finite,
         "copy_gbs": copy_gbs,
         "frac_of_copy": achieved / copy_gbs,
+        "fp64_matrix_probe_tflops": fp64_mfma,
     }
     if comparators:
         comparators["speedup_vs_fine_fdtd"] = value / comparators["fine_fdtd_gcell_per_s"]
@@ -714,6 +722,9 @@ def main():
                                    args.shot_steps, nrec, ms_per_step)
     if args.uneven_steps:
         out["many_shots_uneven"] = uneven_shots_probe(torch, sfm, dev, stream, args.uneven_steps)
+        rf = out["many_shots_uneven"]["roofline"]
+        rf["measured_fp64_matrix_tflops"] = fp64_mfma
+        rf["frac_of_measured"] = rf["achieved"] / fp64_mfma
     if args.surrogate_samples:
         out["learned_roms"] = surrogate_probe(torch, sfm, dev, stream, args.surrogate_samples, args.surrogate_epochs)
     if not args.no_finite_shift:

@@ -246,6 +246,14 @@ sfm_status sfm_dgemm_batched(int32_t trans_a, int32_t trans_b, int32_t M, int32_
                              int64_t stride_b, double beta, double* C, int64_t ldc, int64_t stride_c, int32_t batch,
                              double* work, int64_t work_bytes, void* stream);
 
+/* Sustained rate of the FP64 matrix cores that sfm_dgemm_batched runs on, for reading its roofline:
+ * `blocks` work-groups of four waves each run `iters` rounds of eight independent 16 x 16 x 4
+ * FP64 matrix products on register operands, timed with events on stream.  out: device,
+ * double [blocks * 256], written (one value per lane, to keep the products live).
+ * *tflops = 2 * 16 * 16 * 4 * 8 * 4 * blocks * iters / seconds / 1e12.  Synchronizes.
+ * Errors: SFM_EINVAL, SFM_EHIP. */
+sfm_status sfm_probe_fp64_matrix_rate(int32_t blocks, int32_t iters, double* out, double* tflops, void* stream);
+
 /* Run-time stability watchdog of sfm_step.  With every > 0, sfm_step computes ||U^n||_2 (FP64
  * sum over the whole state) after every `every`-th step of a call and after its last step,
  * synchronizes the stream, and stops with SFM_EUNSTABLE when the norm is not finite or exceeds

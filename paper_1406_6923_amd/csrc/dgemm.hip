@@ -231,6 +231,23 @@ hipError_t launch_trans(GemmArgs& g, int tm, int tn, hipStream_t st) {
   return launch_tile<TA, TB, 1, 1>(g, st);
 }
 
+// Sustained FP64 matrix-core rate: every wave runs `iters` rounds of eight independent
+// 16 x 16 x 4 MFMA accumulation chains on register operands (no memory traffic in the loop).
+__global__ __launch_bounds__(256) void mfma_rate_kernel(double* out, int iters) {
+  d4 acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+  const double a = 1.0 + threadIdx.x * 1e-9, b = 1.0 - threadIdx.x * 1e-9;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) s += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace
 
 size_t dgemm_workspace_bytes(int M, int N, int K, int batch) {
@@ -248,8 +265,10 @@ hipError_t dgemm_batched(bool tA, bool tB, int M, int N, int K, double alpha, co
   g.A = A; g.lda = lda; g.sA = sA;
   g.B = B; g.ldb = ldb; g.sB = sB;
   g.C = C; g.ldc = ldc; g.sC = sC;
-  // tiles of 96 (3 MFMA tiles per wave) along a dimension above 32, else 32
-  const int tm = M > 32 ? 3 : 1, tn = N > 32 ? 3 : 1;
+  // tiles of 96 (3 MFMA tiles per wave) along a dimension above 32, else 32; a short reduction
+  // that also reads C back (beta != 0) is bound by the C traffic, and narrower column tiles
+  // (twice the work-groups per CU) move it faster
+  const int tm = M > 32 ? 3 : 1, tn = (N > 32 && (K > 256 || beta == 0.0)) ? 3 : 1;
   const int64_t tiles = (int64_t)((M + 32 * tm - 1) / (32 * tm)) * ((N + 32 * tn - 1) / (32 * tn)) * batch;
   // split long reductions until the grid holds about 2048 work-groups, each at least 1024 deep
   int ksplit = 1;
@@ -301,4 +320,31 @@ extern "C" sfm_status sfm_dgemm_batched(int32_t trans_a, int32_t trans_b, int32_
                                           stride_b, beta, C, ldc, stride_c, batch,
                                           reinterpret_cast<hipStream_t>(stream), work, (size_t)work_bytes);
   return e == hipSuccess ? SFM_OK : SFM_EHIP;
+}
+
+extern "C" sfm_status sfm_probe_fp64_matrix_rate(int32_t blocks, int32_t iters, double* out, double* tflops,
+                                                 void* stream) {
+  if (blocks < 1 || iters < 1 || !out || !tflops) return SFM_EINVAL;
+  const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return SFM_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return SFM_EHIP;
+  }
+  float ms = 0.0f;
+  hipError_t e = hipEventRecord(e0, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(sfm::mfma_rate_kernel, dim3(blocks), dim3(256), 0, st, out, iters);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess || !(ms > 0.0f)) return SFM_EHIP;
+  // four waves per work-group, eight 16 x 16 x 4 products (2 * 1024 flops) per wave and round
+  *tflops = (double)blocks * 4 * 8 * (double)iters * 2048.0 / (ms * 1e-3) / 1e12;
+  return SFM_OK;
 }

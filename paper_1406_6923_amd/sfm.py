@@ -105,6 +105,7 @@ SIGNATURES = {
     "sfm_dgemm_batched": (_I32, [_I32, _I32, _I32, _I32, _I32, _D, _VP, _I64, _I64, _VP, _I64, _I64, _D, _VP, _I64,
                                  _I64, _I32, _VP, _I64, _VP]),
     "sfm_cfl_dt_noalloc": (_I32, [_VP, _I32, ctypes.POINTER(_D), _VP]),
+    "sfm_probe_fp64_matrix_rate": (_I32, [_I32, _I32, _VP, ctypes.POINTER(_D), _VP]),
     "sfm_record_receivers": (_I32, [_VP, _VP, _VP]),
     "sfm_apply_operator": (_I32, [_VP, _VP, _VP, _VP]),
     "sfm_set_timing": (_I32, [_VP, _I32]),
@@ -289,6 +290,18 @@ def sfm_dgemm_batched(trans_a: bool, trans_b: bool, M: int, N: int, K: int, alph
                                           int(wb), _stream(stream))
     if st != SFM_OK:
         raise SfmError(st, "sfm_dgemm_batched failed")
+
+
+def sfm_probe_fp64_matrix_rate(out, blocks: int = 4096, iters: int = 2000, stream=None) -> float:
+    """Sustained FP64 matrix-core TFLOP/s (out: device float64 tensor of >= blocks * 256)."""
+    if out.numel() < blocks * 256:
+        raise ValueError("out holds fewer than blocks * 256 doubles")
+    tf = _D(0.0)
+    st = load_library().sfm_probe_fp64_matrix_rate(int(blocks), int(iters), _dev(out), ctypes.byref(tf),
+                                                   _stream(stream))
+    if st != SFM_OK:
+        raise SfmError(st, "sfm_probe_fp64_matrix_rate failed")
+    return tf.value
 
 
 def sfm_set_watchdog(ctx: int, every: int, max_norm: float = float("inf")) -> None:

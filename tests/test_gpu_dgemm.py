@@ -59,3 +59,16 @@ def test_dgemm_matches_numpy(ta, tb, M, N, K, batch):
     print(f"dgemm ta={ta} tb={tb} {M}x{N}x{K} x{batch}: max error / bound {ratio:.3f}")
     assert ratio < 1.0
     assert np.array_equal(got[:, :, M:], C0[:, :, M:])       # padding rows untouched
+
+
+def test_fp64_matrix_rate_probe():
+    """The sustained-rate probe returns a rate between 1 TFLOP/s and the published 78.6 TFLOP/s."""
+    from paper_1406_6923_amd import sfm
+    out = torch.empty(1024 * 256, dtype=torch.float64, device="cuda")
+    print("[case] FP64 matrix-rate probe, 1024 work-groups", flush=True)
+    rate = sfm.sfm_probe_fp64_matrix_rate(out, 1024, 500)
+    print(f"FP64 matrix cores: {rate:.1f} TFLOP/s")
+    assert 1.0 < rate < 78.6 * 1.05
+    assert torch.isfinite(out).all()
+    with pytest.raises(ValueError):
+        sfm.sfm_probe_fp64_matrix_rate(out, 2048, 10)
