@@ -158,34 +158,53 @@ __global__ void init_q1_kernel(BoxGeo g, const double* __restrict__ S, const int
 
 // W = (A_+ + shift I) X = S K S X + shift X for the p columns of X (ld ldx) into W (ld ldw).
 // K is the geometric stiffness: coefficient h per edge, halved for every box plane holding the edge.
+// One thread per (subdomain, node column (i, j), column of X) marches along z with the scale and
+// value of the planes l - 1, l, l + 1 in registers, so a z-neighbour (a whole plane of rows away)
+// is loaded once; the x- and y-neighbours lie in the plane the neighbouring threads load.  Every
+// term is formed as y_n - S_nb X_nb with y_n = S_n X_n, in the order x-, x+, y-, y+, z-, z+.
 __global__ void stencil_kernel(BoxGeo g, const double* __restrict__ S, int64_t N, int nb, const double* __restrict__ X,
                                int ldx, int64_t sx, double* __restrict__ W, int ldw, int64_t sw, double shift) {
-  const int64_t total = (int64_t)nb * N * g.p;
+  const int nx = g.n[0], nz = g.n[2];
+  const int64_t plane = (int64_t)nx * g.n[1];
+  const int64_t total = (int64_t)nb * plane * g.p;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     const int col = (int)(idx % g.p);
-    const int64_t bn = idx / g.p;
-    const int b = (int)(bn / N);
-    const int64_t n = bn - (int64_t)b * N;
-    int i, j, l;
-    local_ijk(g, n, i, j, l);
+    const int64_t bq = idx / g.p;
+    const int b = (int)(bq / plane);
+    const int64_t q = bq - (int64_t)b * plane;
+    const int i = (int)(q % nx), j = (int)(q / nx);
     const double* Sb = S + (int64_t)b * N;
     const double* Xb = X + (int64_t)b * sx + col;
-    const double sn = Sb[n];
-    const double yn = sn * Xb[n * ldx];
+    double* Wb = W + (int64_t)b * sw + col;
     const double wi = half_if(i == 0 || i == g.sub[0]);
     const double wj = half_if(j == 0 || j == g.sub[1]);
-    const double wl = half_if(l == 0 || l == g.sub[2]);
-    double acc = 0.0;
-    const int64_t sxn = 1, syn = g.n[0], szn = (int64_t)g.n[0] * g.n[1];
-    // x-edges lie in the planes normal to y and z that hold them
-    const double cx = g.h * wj * wl, cy = g.h * wi * wl, cz = g.h * wi * wj;
-    if (i > 0) acc += cx * (yn - Sb[n - sxn] * Xb[(n - sxn) * ldx]);
-    if (i < g.sub[0]) acc += cx * (yn - Sb[n + sxn] * Xb[(n + sxn) * ldx]);
-    if (j > 0) acc += cy * (yn - Sb[n - syn] * Xb[(n - syn) * ldx]);
-    if (j < g.sub[1]) acc += cy * (yn - Sb[n + syn] * Xb[(n + syn) * ldx]);
-    if (l > 0) acc += cz * (yn - Sb[n - szn] * Xb[(n - szn) * ldx]);
-    if (l < g.sub[2]) acc += cz * (yn - Sb[n + szn] * Xb[(n + szn) * ldx]);
-    W[(int64_t)b * sw + n * ldw + col] = sn * acc + shift * Xb[n * ldx];
+    const double cz = g.h * wi * wj;     // z-edges lie in the planes normal to x and y that hold them
+    int64_t n = q;
+    double sm = 0.0, xm = 0.0;                               // plane l - 1
+    double sn = Sb[n], xn = Xb[n * ldx];                     // plane l
+    double sp = Sb[n + plane], xp = Xb[(n + plane) * ldx];   // plane l + 1 (nz >= 2)
+    for (int l = 0; l < nz; ++l) {
+      const double wl = half_if(l == 0 || l == g.sub[2]);
+      const double cx = g.h * wj * wl, cy = g.h * wi * wl;
+      const double yn = sn * xn;
+      double acc = 0.0;
+      if (i > 0) acc += cx * (yn - Sb[n - 1] * Xb[(n - 1) * ldx]);
+      if (i < g.sub[0]) acc += cx * (yn - Sb[n + 1] * Xb[(n + 1) * ldx]);
+      if (j > 0) acc += cy * (yn - Sb[n - nx] * Xb[(n - nx) * ldx]);
+      if (j < g.sub[1]) acc += cy * (yn - Sb[n + nx] * Xb[(n + nx) * ldx]);
+      if (l > 0) acc += cz * (yn - sm * xm);
+      if (l < g.sub[2]) acc += cz * (yn - sp * xp);
+      Wb[n * ldw] = sn * acc + shift * xn;
+      sm = sn;
+      xm = xn;
+      sn = sp;
+      xn = xp;
+      n += plane;
+      if (l + 2 < nz) {
+        sp = Sb[n + plane];
+        xp = Xb[(n + plane) * ldx];
+      }
+    }
   }
 }
 
@@ -916,7 +935,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
     if (!finite) {
       // polynomial space: block Lanczos on (A_+, F)
       rc = lanczos(Z, N, kb, thr, [&](int jj, double* W, int ldw, int64_t sW) -> sfm_status {
-        B_LAUNCH(stencil_kernel, (int64_t)nb * N * p, g, Sd, N, nb, Z + (int64_t)jj * p, kp, sZ, W, ldw, sW, 0.0);
+        B_LAUNCH(stencil_kernel, (int64_t)nb * (N / g.n[2]) * p, g, Sd, N, nb, Z + (int64_t)jj * p, kp, sZ, W, ldw, sW, 0.0);
         return SFM_OK;
       });
       if (rc != SFM_OK) return rc;
@@ -940,7 +959,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
         int it = 0;
         for (;;) {
           for (int q = 0; q < kCgCheck; ++q, ++it) {
-            B_LAUNCH(stencil_kernel, (int64_t)nb * N * p, g, Sd, N, nb, Pv, p, sN, Qv, p, sN, shift.sigma);
+            B_LAUNCH(stencil_kernel, (int64_t)nb * (N / g.n[2]) * p, g, Sd, N, nb, Pv, p, sN, Qv, p, sN, shift.sigma);
             hipLaunchKernelGGL(cg_dot_kernel, cgrid, dim3(256), 0, st, cv, Pv, Qv, part);
             B_TRY_HIP(hipGetLastError());
             hipLaunchKernelGGL(cg_alpha_kernel, dim3(sgrid), dim3(256), 0, st, cv, part, cgs, active);
@@ -975,7 +994,7 @@ sfm_status build_roms(sfm_ctx c, const ShiftSpec& shift, const float* vel_dev, i
       if (rc != SFM_OK) return rc;
       // A~ = V^T A_+ V, one block row at a time (symmetric: rows jj*p.. of the column-major kp x kp)
       for (int jj = 0; jj < k; ++jj) {
-        B_LAUNCH(stencil_kernel, (int64_t)nb * N * p, g, Sd, N, nb, Z + (int64_t)jj * p, kp, sZ, Wl, p, N * p, 0.0);
+        B_LAUNCH(stencil_kernel, (int64_t)nb * (N / g.n[2]) * p, g, Sd, N, nb, Z + (int64_t)jj * p, kp, sZ, Wl, p, N * p, 0.0);
         B_TRY_HIP(dgemm_batched(NN, TT, p, kp, (int)N, one, Wl, p, N * p, Z, kp, sZ, zero, At + (int64_t)jj * p, kp, kpkp, nb, st, gw, kGemmWorkBytes));
       }
       B_LAUNCH(symmetrize_kernel, (int64_t)nb * kpkp, At, kp, kpkp, nb);
