@@ -126,16 +126,18 @@ def cpu_baseline(cfg: W.Workload, c_full: np.ndarray, dt_ratio: float, nsub=(1, 
     }
 
 
-def finite_shift_probe(torch, sfm, dev, stream, n: int = 4, steps: int = 200, sigma_factor: float = 16.0):
+def finite_shift_probe(torch, sfm, dev, stream, n: int = 4, steps: int = 200, sigma_factors=(16.0, 32.0, 64.0)):
     """Finite-shift ROMs on an n^3-subdomain sample with the large workload's subdomain and ROM
     shape (33^3 nodes, m = 16, k = 16): device build rate (Jacobi-PCG shifted solves), the CFL
-    step against sigma = infinity ROMs of the same sample, and the FP64-coefficient step rate."""
+    step against sigma = infinity ROMs of the same sample, and the FP64-coefficient step rate.
+    The shift is the first of sigma_factors * (2 pi f_peak)^2 whose S-fraction is positive definite
+    at the FP64 level in every subdomain (the build reports a breakdown otherwise: the deepest
+    level of a small shift can sit at rounding level, e.g. a Gamma-hat_16 pivot at 1.6e-14 of its
+    diagonal at factor 16); the refused factors are listed."""
     cfg = W.scaled_large((n, n, n), nsteps=steps)
     c = cfg.velocity_model()
     vel = torch.from_numpy(c.astype(np.float32)).to(dev)
-    sigma = sigma_factor * (2.0 * math.pi * cfg.f_peak) ** 2
-    out = {"workload": cfg.name, "subdomains": n ** 3, "sigma": sigma,
-           "sigma_over_peak_omega_sq": sigma_factor, "coefficients": "f64"}
+    out = {"workload": cfg.name, "subdomains": n ** 3, "coefficients": "f64", "refused_sigma_factors": []}
     h_inf = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -145,11 +147,27 @@ def finite_shift_probe(torch, sfm, dev, stream, n: int = 4, steps: int = 200, si
     dt_inf = sfm.sfm_cfl_dt(h_inf.ctx, 200, stream=stream)
     h_inf.close()
     h = sfm.Sfm(cfg.ncell, cfg.sub_cells, cfg.h, cfg.m, cfg.k, precision=sfm.SFM_PREC_FP64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = sfm.sfm_build_roms_shifted(h.ctx, sigma, vel, stream=stream)
-    torch.cuda.synchronize()
-    t_b = time.perf_counter() - t0
+    iters = None
+    for factor in sigma_factors:
+        sigma = factor * (2.0 * math.pi * cfg.f_peak) ** 2
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            iters = sfm.sfm_build_roms_shifted(h.ctx, sigma, vel, stream=stream)
+        except sfm.SfmError as e:
+            if e.status != sfm.SFM_EBREAKDOWN:
+                raise
+            log(f"[bench] finite shift {factor} (2 pi f_peak)^2: {e.message}")
+            out["refused_sigma_factors"].append(factor)
+            continue
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        out.update(sigma=sigma, sigma_over_peak_omega_sq=factor)
+        break
+    if iters is None:
+        h.close()
+        out["error"] = "every shift factor broke down"
+        return out
     out.update(build_seconds=t_b, builds_per_s=n ** 3 / t_b, cg_iters_max=iters)
     dt_sh = sfm.sfm_cfl_dt(h.ctx, 200, stream=stream)
     out["dt_ratio_vs_sigma_inf"] = dt_sh / dt_inf
@@ -729,7 +747,7 @@ def main():
         out["learned_roms"] = surrogate_probe(torch, sfm, dev, stream, args.surrogate_samples, args.surrogate_epochs)
     if not args.no_finite_shift:
         out["finite_shift"] = finite_shift_probe(torch, sfm, dev, stream)
-        if prec == sfm.SFM_PREC_FP32:
+        if prec == sfm.SFM_PREC_FP32 and "dt_ratio_vs_sigma_inf" in out["finite_shift"]:
             out["finite_shift"]["fp64_stream_at_scale"] = fp64_stream_probe(
                 torch, sfm, h, cfg, dt, ratio, out["finite_shift"]["dt_ratio_vs_sigma_inf"])
     if args.adjoint_steps:
