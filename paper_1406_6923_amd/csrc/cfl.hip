@@ -86,33 +86,34 @@ __global__ void fill_kernel(int32_t* __restrict__ v, int n, int32_t value) {
 }
 
 // Lower Cholesky in place of the p x p column-major matrix a (leading dimension p) held by the
-// work-group; the strict upper triangle is zeroed.  Returns, uniformly over the work-group, whether
-// every pivot exceeded thr; a pivot that does not is replaced by 1 so the factorisation still ends.
+// work-group (a multiple of 16 threads); the strict upper triangle is zeroed.  Returns, uniformly
+// over the work-group, whether every pivot exceeded thr; a pivot that does not is replaced by 1 so
+// the factorisation still ends.  Every thread forms the pivot itself; the trailing update runs
+// over 16-lane groups, one column per group and consecutive rows across its lanes.
 __device__ bool chol_body(double* a, int p, double thr) {
-  __shared__ double piv;
   __shared__ int bad;
   const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4, nty = blockDim.x >> 4;
   if (tid == 0) bad = 0;
   for (int c = 0; c < p; ++c) {
-    __syncthreads();
-    if (tid == 0) {
-      double d = a[c + (int64_t)c * p];
-      if (!(d > thr)) {
-        bad = 1;
-        d = 1.0;
-      }
-      piv = sqrt(d);
-      a[c + (int64_t)c * p] = piv;
-    }
-    __syncthreads();
+    __syncthreads();                     // column c is final
+    double d = a[c + (int64_t)c * p];
+    const bool ok = d > thr;
+    if (!ok) d = 1.0;
+    const double piv = sqrt(d);
     const double inv = 1.0 / piv;
     for (int i = c + 1 + tid; i < p; i += blockDim.x) a[i + (int64_t)c * p] *= inv;
-    __syncthreads();
+    __syncthreads();                     // the scaled column is visible, every thread has read a_cc
+    if (tid == 0) {
+      a[c + (int64_t)c * p] = piv;
+      if (!ok) bad = 1;
+    }
     const int nr = p - c - 1;
     const double* col = a + (int64_t)c * p + c + 1;
-    for (int e = tid; e < nr * nr; e += blockDim.x) {
-      const int ii = e % nr, jj = e / nr;
-      if (ii >= jj) a[(c + 1 + ii) + (int64_t)(c + 1 + jj) * p] -= col[ii] * col[jj];
+    for (int jj = ty; jj < nr; jj += nty) {
+      const double lj = col[jj];
+      double* dst = a + (c + 1) + (int64_t)(c + 1 + jj) * p;
+      for (int ii = jj + tx; ii < nr; ii += 16) dst[ii] -= col[ii] * lj;
     }
   }
   __syncthreads();
@@ -123,14 +124,22 @@ __device__ bool chol_body(double* a, int p, double thr) {
 }
 
 // w <- r^{-1} w for the lower triangular r (p x p, leading dimension p) and p columns of w
-// (leading dimension ldw), one column per thread, plain forward substitution.
+// (leading dimension ldw), one column per thread, forward substitution.  Each row's dot product
+// runs in eight interleaved partial sums (added in a fixed order), so the loads of the next terms
+// are in flight while the current ones accumulate.
 __device__ void solve_body(const double* r, double* w, int p, int ldw) {
   for (int c = threadIdx.x; c < p; c += blockDim.x) {
     double* x = w + (int64_t)c * ldw;
     for (int row = 0; row < p; ++row) {
-      double v = x[row];
-      for (int i = 0; i < row; ++i) v = fma(-r[row + (int64_t)i * p], x[i], v);
-      x[row] = v / r[row + (int64_t)row * p];
+      double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int i = 0;
+      for (; i + 8 <= row; i += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = fma(r[row + (int64_t)(i + u) * p], x[i + u], acc[u]);
+      }
+      for (int u = 0; i < row; ++i, ++u) acc[u] = fma(r[row + (int64_t)i * p], x[i], acc[u]);
+      const double dot = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+      x[row] = (x[row] - dot) / r[row + (int64_t)row * p];
     }
   }
   __syncthreads();
