@@ -431,35 +431,32 @@ __global__ __launch_bounds__(256) void cholesky_kernel(double* __restrict__ A, i
                                                        const double* __restrict__ thr, double rel,
                                                        int* __restrict__ flag) {
   double* a = A + (int64_t)blockIdx.x * stride;
-  __shared__ double piv;
   __shared__ int bad;
   __shared__ double diag0[kTile * kMaxNt];
   const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4, nty = blockDim.x >> 4;   // 16-lane column groups
+  const double tb = thr ? thr[blockIdx.x] : 0.0;
   if (tid == 0) bad = 0;
   for (int c = tid; c < p; c += blockDim.x) diag0[c] = a[c + (int64_t)c * p];
   for (int c = 0; c < p; ++c) {
-    __syncthreads();
-    if (tid == 0) {
-      double d = a[c + (int64_t)c * p];
-      const double t = fmax(thr ? thr[blockIdx.x] : 0.0, rel * diag0[c]);
-      if (!(d > t)) {
-        bad = 1;
-        d = 1.0;
-      }
-      piv = sqrt(d);
-      a[c + (int64_t)c * p] = piv;
-    }
-    __syncthreads();
+    __syncthreads();                     // column c is final
+    double d = a[c + (int64_t)c * p];    // every thread forms the pivot
+    const bool ok = d > fmax(tb, rel * diag0[c]);
+    if (!ok) d = 1.0;
+    const double piv = sqrt(d);
     const double inv = 1.0 / piv;
     for (int i = c + 1 + tid; i < p; i += blockDim.x) a[i + (int64_t)c * p] *= inv;
-    __syncthreads();
+    __syncthreads();                     // the scaled column is visible, every thread has read a_cc
+    if (tid == 0) {
+      a[c + (int64_t)c * p] = piv;
+      if (!ok) bad = 1;
+    }
     const int nr = p - c - 1;
-    for (int e = tid; e < nr * nr; e += blockDim.x) {
-      const int ii = e % nr, jj = e / nr;
-      if (ii >= jj) {
-        const int i = c + 1 + ii, j = c + 1 + jj;
-        a[i + (int64_t)j * p] -= a[i + (int64_t)c * p] * a[j + (int64_t)c * p];
-      }
+    const double* col = a + (int64_t)c * p + c + 1;
+    for (int jj = ty; jj < nr; jj += nty) {
+      const double lj = col[jj];
+      double* dst = a + (c + 1) + (int64_t)(c + 1 + jj) * p;
+      for (int ii = jj + tx; ii < nr; ii += 16) dst[ii] -= col[ii] * lj;
     }
   }
   __syncthreads();
