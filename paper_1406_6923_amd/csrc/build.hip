@@ -17,8 +17,10 @@
 //      (the last identity keeps every inverse triangular or SPD: no pivoting).
 //  a4  projections (eq. "Uj"): s = G Z^T M^{-1/2} e_s, r = e_r^T M^{-1/2} Z G^{-1}, and
 //      U(0) = G Z^T M^{1/2} u0.
-// The reductions run in FP64 on the device; the large dense products (Z^T W, Z C, W^T W and the
-// products with the inverse Cholesky factors) are plain rocBLAS strided-batched DGEMM calls.
+// The reductions run in FP64 on the device; the dense products (Z^T W, Z C, W^T W, the products
+// with the inverse Cholesky factors and the p x p products of the S-fraction) run on the batched
+// FP64 matrix-core kernel of dgemm.hip, the triangular inverses and solves on its compensated
+// substitution kernels.
 
 #include <algorithm>
 #include <chrono>
