@@ -409,6 +409,13 @@ sfm_status sfm_shots_set_state(sfm_ctx ctx, const float* u_host, const float* d_
  * shots per subdomain.  Errors: SFM_ESTATE. */
 sfm_status sfm_shots_tuning(sfm_ctx ctx, int32_t* chosen_waves, double* ms, int32_t cap, int32_t* count);
 
+/* Use shot-kernel variant `variant` (the order of sfm_shots_tuning; every variant computes the
+ * same step) instead of the autotuner's choice, or go back to that choice with variant = -1; for
+ * checking each variant against the others and for timing.  Lasts until the next sfm_shots_init.
+ * Errors: SFM_ESTATE (no sfm_shots_init), SFM_EINVAL (out of range, or the variant's work-group
+ * limit or prefetch capacity is below this 6m). */
+sfm_status sfm_shots_select(sfm_ctx ctx, int32_t variant);
+
 /* Device times of the shot kernels summed over the steps run while sfm_set_timing was on:
  * *timed_steps, ms3 = {main, face, record}; then resets the counters.  Never fails for a valid ctx. */
 sfm_status sfm_shots_timing(sfm_ctx ctx, int64_t* timed_steps, double* ms3);

@@ -280,7 +280,8 @@ struct sfm_ctx_s {
   int64_t shots_n = 0;
   int64_t shots_timed = 0;
   double shots_ms[3] = {0, 0, 0};   // main, face, record
-  int shots_variant = 0;            // main-kernel variant chosen by the autotuner
+  int shots_variant = 0;            // main-kernel variant in use
+  int shots_tuned = 0;              // the variant the autotuner chose
   double shots_tune_ms[4] = {0, 0, 0, 0};
   // hipGraph of one receiver window of shot steps (replayed by sfm_shots_step)
   bool shots_graph = true;

@@ -673,6 +673,7 @@ sfm_status autotune_shots(sfm_ctx c, hipStream_t st) {
   SH_TRY_HIP(hipEventDestroy(a));
   SH_TRY_HIP(hipEventDestroy(b));
   c->shots_variant = best;
+  c->shots_tuned = best;
   return SFM_OK;
 }
 
@@ -907,12 +908,28 @@ sfm_status sfm_shots_tuning(sfm_ctx c, int32_t* chosen_waves, double* ms, int32_
   if (!c) return SFM_EINVAL;
   c->err.clear();
   if (c->nshot == 0) return c->fail(SFM_ESTATE, "call sfm_shots_init first");
-  if (chosen_waves) *chosen_waves = kShotVariantWaves[shot_kind(c)][c->shots_variant];
+  if (chosen_waves) *chosen_waves = kShotVariantWaves[shot_kind(c)][c->shots_tuned];
   if (count) *count = kNumShotVariants;
   for (int v = 0; v < std::min<int>(cap, kNumShotVariants); ++v) {
     if (ms) ms[2 * v] = kShotVariantWaves[shot_kind(c)][v];
     if (ms) ms[2 * v + 1] = c->shots_tune_ms[v];
   }
+  return SFM_OK;
+}
+
+sfm_status sfm_shots_select(sfm_ctx c, int32_t variant) {
+  if (!c) return SFM_EINVAL;
+  c->err.clear();
+  if (c->nshot == 0) return c->fail(SFM_ESTATE, "call sfm_shots_init first");
+  if (variant == -1) {
+    c->shots_variant = c->shots_tuned;
+    return SFM_OK;
+  }
+  if (variant < 0 || variant >= kNumShotVariants)
+    return c->fail(SFM_EINVAL, "variant must be -1 or in [0, " + std::to_string(kNumShotVariants) + ")");
+  if (!shot_variant_fits(c, variant))
+    return c->fail(SFM_EINVAL, "variant " + std::to_string(variant) + " does not fit 6m = " + std::to_string(c->topo.p));
+  c->shots_variant = variant;
   return SFM_OK;
 }
 

@@ -96,6 +96,7 @@ SIGNATURES = {
     "sfm_shots_set_state": (_I32, [_VP, _VP, _VP]),
     "sfm_shots_timing": (_I32, [_VP, ctypes.POINTER(_I64), _VP]),
     "sfm_shots_tuning": (_I32, [_VP, ctypes.POINTER(_I32), _VP, _I32, ctypes.POINTER(_I32)]),
+    "sfm_shots_select": (_I32, [_VP, _I32]),
     "sfm_load_roms": (_I32, [_VP, _VP, _VP, _I32, _VP, _VP, _I32, _VP, _VP]),
     "sfm_export_roms": (_I32, [_VP, _VP, _VP]),
     "sfm_export_projections": (_I32, [_VP, _VP, _VP]),
@@ -354,14 +355,20 @@ def sfm_shots_set_state(ctx: int, u, d) -> None:
     _check(ctx, load_library().sfm_shots_set_state(ctx, _ptr(u), _ptr(d)))
 
 
-def sfm_shots_tuning(ctx: int):
-    """(chosen waves per SIMD, [(waves, ms per step) of each variant]) from the last sfm_shots_init."""
+def sfm_shots_select(ctx: int, variant: int) -> None:
+    """Force shot-kernel variant `variant` (order of sfm_shots_tuning), or -1 for the autotuner's."""
+    _check(ctx, load_library().sfm_shots_select(ctx, int(variant)))
+
+
+def sfm_shots_tuning(ctx: int, every_variant: bool = False):
+    """(chosen waves per SIMD, [(waves, ms per step) of each variant]) from the last sfm_shots_init.
+    Variants whose work-group limit is below this 6m were not run (time < 0): they are left out,
+    unless every_variant, which lists all of them in variant order (the sfm_shots_select index)."""
     chosen, count = _I32(0), _I32(0)
     ms = np.zeros(16, np.float64)
     _check(ctx, load_library().sfm_shots_tuning(ctx, ctypes.byref(chosen), _ptr(ms), 8, ctypes.byref(count)))
-    # variants whose work-group limit is below this 6m were not run (time < 0)
     return int(chosen.value), [(int(ms[2 * v]), float(ms[2 * v + 1])) for v in range(count.value)
-                               if ms[2 * v + 1] >= 0]
+                               if every_variant or ms[2 * v + 1] >= 0]
 
 
 def sfm_shots_timing(ctx: int):

@@ -63,6 +63,48 @@ def test_shots_operator_matches_oracle(name, tol, precision):
     h.close()
 
 
+@pytest.mark.parametrize("name, tol, precision", [("ragged", 1e-5, 0), ("mid", 5e-5, 0), ("ragged", 1e-6, 2),
+                                                  ("mid", 1e-6, 2)])
+def test_every_shot_variant_matches_oracle(name, tol, precision):
+    """Every compiled variant of the shot kernel that fits this 6m (forced with sfm_shots_select),
+    not only the autotuner's choice: the operator of 64 shots against the oracle, and bit-equal
+    across the variants (each output element takes the same products in the same order)."""
+    from paper_1406_6923_amd import sfm
+    cfg, c, subs, roms, cs = oracle_case(name)
+    print(f"[case] every shot variant {name}, precision {precision}", flush=True)
+    h = _load(cfg, cs, precision=precision)
+    sfm.sfm_shots_init(h.ctx, NSHOT, np.full(NSHOT, -1))
+    chosen, variants = sfm.sfm_shots_tuning(h.ctx, every_variant=True)
+    U = np.stack([random_consistent_state(cs, seed=300 + n) for n in range(NSHOT)], axis=-1).astype(np.float32)
+    refs = [np.stack(cs.accel(list(U[..., n].astype(np.float64)))) for n in range(NSHOT)]
+    wav = torch.zeros((1, NSHOT), dtype=torch.float32, device="cuda")
+    first = None
+    ran = 0
+    for v, (waves, ms) in enumerate(variants):
+        if ms < 0:                       # work-group limit or prefetch capacity below this 6m
+            with pytest.raises(sfm.SfmError) as ei:
+                sfm.sfm_shots_select(h.ctx, v)
+            assert ei.value.status == sfm.SFM_EINVAL
+            continue
+        sfm.sfm_shots_select(h.ctx, v)
+        sfm.sfm_shots_set_state(h.ctx, U, np.zeros_like(U))
+        sfm.sfm_shots_step(h.ctx, 1, 1.0, wav, None)
+        _, a = sfm.sfm_shots_get_state(h.ctx, NSHOT)
+        worst = max(rel_l2(a[..., n], refs[n]) for n in range(NSHOT))
+        print(f"{name} precision {precision}: variant {v} ({waves} waves per SIMD, {ms:.3f} ms) worst {worst:.2e}")
+        assert worst < tol, v
+        if first is None:
+            first = a
+        else:
+            assert np.array_equal(a, first), v
+        ran += 1
+    assert ran >= 1
+    sfm.sfm_shots_select(h.ctx, -1)
+    with pytest.raises(sfm.SfmError):
+        sfm.sfm_shots_select(h.ctx, len(variants))
+    h.close()
+
+
 def _shot_sources(cfg, n):
     """n surface-near source nodes strictly inside subdomains (off every interface plane)."""
     rng = np.random.default_rng(7)
