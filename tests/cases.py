@@ -36,6 +36,15 @@ def case_config(name: str) -> W.Workload:
         cfg = W.Workload(name=f"layered_64c_2x2x2_m{m}_k16", ncell=(64, 64, 64), sub_cells=(32, 32, 32),
                          h=10.0, m=m, k=16, f_peak=12.0, nsteps=500, src=((31, 31, 2),), rec_grid=(32, 32),
                          velocity="layered_inclusions", seed=1406 + m)
+    elif name in ("m18", "m24"):
+        # Wide blocks with few levels: 16^3-cell boxes on a 2 x 2 x 2 split, k = 3; m = 18 gives
+        # 6m = 108 (seven 16-row tiles), m = 24 gives 6m = 144 (nine).  Past 6m = 100 the stability
+        # certificate's factor-and-solve no longer fits LDS, past 6m = 143 neither does its
+        # Cholesky: both run on global memory there.
+        m = 18 if name == "m18" else 24
+        cfg = W.Workload(name=f"layered_32c_2x2x2_m{m}_k3", ncell=(32, 32, 32), sub_cells=(16, 16, 16),
+                         h=10.0, m=m, k=3, f_peak=15.0, nsteps=200, src=((15, 15, 2),), rec_grid=(16, 16),
+                         velocity="layered_inclusions", seed=1406 + m)
     else:
         raise KeyError(name)
     return cfg

@@ -6,7 +6,8 @@ split of 32^3-cell boxes.  An odd tile count gives every block a job that holds 
 strip (the middle one), and 6m = 72 adds four padded rows per block; the even shapes of the other
 tests (6m = 18, 24, 96) never reach either in the step, adjoint or operator kernels.  The ROMs come
 from the oracle (sfm_load_roms), so the kernels are isolated from the device build, except in
-test_device_build_traces, which runs the whole path.
+test_device_build_traces, which runs the whole path.  test_wide_blocks adds 6m = 108 and 144
+(seven and nine tiles) with k = 3, where the stability certificate leaves LDS for global memory.
 
 Bars.  One application of the step operator is held elementwise to the first-order forward error
 bound of FP32 storage and FP32 dot products (tests.cases.operator_error_bound); its rel-L2 is
@@ -159,5 +160,40 @@ def test_device_build_traces(name):
     torch.cuda.synchronize()
     err = rel_l2(tr.cpu().numpy(), ref)
     print(f"{name}: device build + device step, {nsteps}-step traces rel-L2 {err:.2e}")
+    assert err < 1e-5
+    h.close()
+
+
+@pytest.mark.parametrize("name", ["m18", "m24"])
+def test_wide_blocks(name):
+    """6m = 108 and 144 (seven and nine tiles, k = 3): the step operator within its forward-error
+    bound, 200-step traces at 1e-5, and the stability limit, whose certificate runs its
+    factor-and-solve (6m > 100) and, at 6m = 144, its Cholesky (6m > 143) on global memory instead of
+    LDS; the no-allocation variant returns the same limit."""
+    from paper_1406_6923_amd import sfm
+    h, cfg, cs = _loaded(name)
+    U = random_consistent_state(cs, seed=21).astype(np.float32).astype(np.float64)
+    ref = np.stack(cs.accel(list(U)))
+    got = _apply(h, U)
+    ratio = (np.abs(got - ref) / operator_error_bound(cs, U)).max()
+    print(f"{name}: operator rel-L2 {rel_l2(got, ref):.2e}, max error / bound {ratio:.3f}")
+    assert ratio < 1.0
+    dt_ref = cs.cfl_dt()
+    dt_gpu = sfm.sfm_cfl_dt(h.ctx)
+    dt_na = sfm.sfm_cfl_dt_noalloc(h.ctx)
+    print(f"{name}: dt_max device {dt_gpu:.6e} (no-alloc {dt_na:.6e}), oracle {dt_ref:.6e} "
+          f"(ratio {dt_gpu / dt_ref:.5f})")
+    assert dt_gpu <= dt_ref * (1 + 1e-6) and dt_gpu >= 0.95 * dt_ref
+    assert dt_na == dt_gpu
+    dt = 0.9 * dt_ref
+    nsteps = 200
+    wav = W.ricker(cfg.f_peak, dt, nsteps)[:, None]
+    tref = cs.run(dt, wav)
+    tr = torch.zeros((len(cs.receivers), nsteps), dtype=torch.float32, device="cuda")
+    sfm.sfm_set_state(h.ctx, None, None, 0)
+    sfm.sfm_step(h.ctx, nsteps, dt, torch.tensor(wav, dtype=torch.float32, device="cuda"), tr)
+    torch.cuda.synchronize()
+    err = rel_l2(tr.cpu().numpy(), tref)
+    print(f"{name}: {nsteps}-step traces rel-L2 {err:.2e}")
     assert err < 1e-5
     h.close()
