@@ -403,10 +403,11 @@ sfm_status sfm_shots_set_state(sfm_ctx ctx, const float* u_host, const float* d_
 
 /* Autotuner result of the last sfm_shots_init: *chosen_waves = the register budget (minimum
  * waves per SIMD) of the chosen variant; ms (host, double [2 cap]) = {waves, ms per step} of
- * each variant (up to cap; ms < 0 for a variant whose work-group limit or prefetch capacity is
- * below this 6m, which is not run); *count = number of variants.  The variants, in this order:
- * one work-group of 64 shots per subdomain at two register budgets, then two work-groups of 32
- * shots per subdomain.  Errors: SFM_ESTATE. */
+ * each variant (up to cap; ms < 0 for a variant whose work-group limit, prefetch capacity or LDS
+ * is below this 6m, which is not run); *count = number of variants.  The variants, in this
+ * order: one work-group of 64 shots per subdomain at two register budgets, two work-groups of 32
+ * shots per subdomain, and the first with two block buffers in LDS (the next block expanded while
+ * the current one multiplies).  Errors: SFM_ESTATE. */
 sfm_status sfm_shots_tuning(sfm_ctx ctx, int32_t* chosen_waves, double* ms, int32_t cap, int32_t* count);
 
 /* Use shot-kernel variant `variant` (the order of sfm_shots_tuning; every variant computes the

@@ -179,14 +179,18 @@ __device__ __forceinline__ void block_product(const T* __restrict__ G, const T* 
 // Xt lets two work-groups share a CU where the 64-shot one needs most of its LDS (FP64 blocks).
 // Work-groups g and g + 8 of every 16 take the two halves of one subdomain: the same XCD (and L2)
 // reads the subdomain's blocks for both.  kPF: 16-byte prefetch loads per thread.
+// kDB: two dense block buffers in LDS; each block product runs while the next block of the stream
+// (Gamma_1, Gamma_2, Gamma-hat_2, Gamma_3, Gamma-hat_3, ...) is expanded into the other buffer, so the
+// expansion leaves the products' critical path (the same arithmetic, in the same order).
 template <typename T, int kMinWaves, int kMaxNtWG = kMaxShotP16 / kTile, int kCols = 64,
-          int kPF = ShotMath<T>::kPrefetch>
+          int kPF = ShotMath<T>::kPrefetch, bool kDB = false>
 __global__ __launch_bounds__((kCols == 64 ? 128 : 64) * kMaxNtWG, kMinWaves) void shots_main_kernel(ShotParams prm) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   typedef typename ShotMath<T>::Acc A4;
   const int P = prm.P, PP = prm.PP, k = prm.k;
   T* G = reinterpret_cast<T*>(lds_raw);  // [P][PP]      dense block
-  T* Xt = G + P * PP;                    // [kCols][PP]  block input, then a_j, transposed
+  T* G2 = kDB ? G + P * PP : G;          // [P][PP]      second block buffer (kDB)
+  T* Xt = G2 + P * PP;                   // [kCols][PP]  block input, then a_j, transposed
   const T* tiles = static_cast<const T*>(prm.tiles);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index: uniform
@@ -229,75 +233,163 @@ __global__ __launch_bounds__((kCols == 64 ? 128 : 64) * kMaxNtWG, kMinWaves) voi
     Ub[i] = Uw[xrow(1, i)];
   }
   const int rb = 16 * I;                 // first row of the wave's row tile
-  for (int j = 0; j < ks; ++j) {
-    __syncthreads();                                       // G, Xt free
-    expand_block<T, kPF>(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma_j
+  if constexpr (!kDB) {
+    for (int j = 0; j < ks; ++j) {
+      __syncthreads();                                       // G, Xt free
+      expand_block<T, kPF>(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma_j
 #pragma unroll
-    for (int i = 0; i < R; ++i) Xt[xl * PP + trow(i)] = (T)Ub[i] - (T)Ua[i];   // U_{j+1} - U_j
-    __syncthreads();
-    if (j >= 1) {
-      prefetch_block<T, kPF>(tiles + block_word(prm, s, k + j - 1), nq, tid, nthr, buf);   // Gamma-hat_j
-#pragma unroll
-      for (int i = 0; i < R; ++i) Dr[i] = Dw[xrow(j, i)];
-    } else {
-      prefetch_block<T, kPF>(tiles + block_word(prm, s, 1), nq, tid, nthr, buf);           // Gamma_2
-    }
-#pragma unroll
-    for (int i = 0; i < R; ++i) Un[i] = (j + 2 < ks) ? Uw[xrow(j + 2, i)] : 0.f;
-    block_product<T>(G, Xt, PP, P, I, sh, g, li, acc);     // phi_j
-    __syncthreads();                                       // every wave done with G, Xt
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int n = 16 * (sh + h) + li;   // local column
-      if (j == 0) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          prm.exch[((size_t)s * P + rb + ShotMath<T>::out_row(g, v)) * kShotCols + c0 + n] = (float)acc[h][v];  // 2.1
-      } else {
-        store_rows<T>(Xt + n * PP + rb, g, acc[h] - phip[h]);   // phi_j - phi_{j-1}
-      }
-      phip[h] = acc[h];
-    }
-    if (j >= 1) {
-      expand_block<T, kPF>(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma-hat_j
+      for (int i = 0; i < R; ++i) Xt[xl * PP + trow(i)] = (T)Ub[i] - (T)Ua[i];   // U_{j+1} - U_j
       __syncthreads();
-      if (j + 1 < ks) prefetch_block<T, kPF>(tiles + block_word(prm, s, j + 1), nq, tid, nthr, buf);  // Gamma_{j+1}
-      block_product<T>(G, Xt, PP, P, I, sh, g, li, acc);     // a_j
-      // sources of this subdomain: a_j += f_n(t) s_j for the shot n each source drives
-      for (int q = ns0; q < ns1; ++q) {
-        const int src = prm.src_ids[q];
-        const int n = prm.src_shot[src];
-        const int nl = n - c0;               // local column of the shot (outside: another half)
-        if (n < 0 || nl < 0 || nl >= kCols || (nl & 15) != li || (nl >> 4) < sh || (nl >> 4) > sh + 1) continue;
-        const int64_t stp = prm.step + (prm.step_base ? *prm.step_base : 0);
-        const float wv = prm.wavelet[stp * prm.nshot + n];
-        const float* sv = prm.src_vec + ((size_t)src * k + j) * P + rb;
-        const int h = (nl >> 4) - sh;
+      if (j >= 1) {
+        prefetch_block<T, kPF>(tiles + block_word(prm, s, k + j - 1), nq, tid, nthr, buf);   // Gamma-hat_j
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const T x = (T)sv[ShotMath<T>::out_row(g, v)];
-          if constexpr (std::is_same<T, float>::value) acc[h][v] = fmaf(wv, x, acc[h][v]);
-          else acc[h][v] = fma((double)wv, x, acc[h][v]);
+        for (int i = 0; i < R; ++i) Dr[i] = Dw[xrow(j, i)];
+      } else {
+        prefetch_block<T, kPF>(tiles + block_word(prm, s, 1), nq, tid, nthr, buf);           // Gamma_2
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) Un[i] = (j + 2 < ks) ? Uw[xrow(j + 2, i)] : 0.f;
+      block_product<T>(G, Xt, PP, P, I, sh, g, li, acc);     // phi_j
+      __syncthreads();                                       // every wave done with G, Xt
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int n = 16 * (sh + h) + li;   // local column
+        if (j == 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            prm.exch[((size_t)s * P + rb + ShotMath<T>::out_row(g, v)) * kShotCols + c0 + n] = (float)acc[h][v];  // 2.1
+        } else {
+          store_rows<T>(Xt + n * PP + rb, g, acc[h] - phip[h]);   // phi_j - phi_{j-1}
+        }
+        phip[h] = acc[h];
+      }
+      if (j >= 1) {
+        expand_block<T, kPF>(G, PP, P, prm.wmap, nq, tid, nthr, buf);  // G <- Gamma-hat_j
+        __syncthreads();
+        if (j + 1 < ks) prefetch_block<T, kPF>(tiles + block_word(prm, s, j + 1), nq, tid, nthr, buf);  // Gamma_{j+1}
+        block_product<T>(G, Xt, PP, P, I, sh, g, li, acc);     // a_j
+        // sources of this subdomain: a_j += f_n(t) s_j for the shot n each source drives
+        for (int q = ns0; q < ns1; ++q) {
+          const int src = prm.src_ids[q];
+          const int n = prm.src_shot[src];
+          const int nl = n - c0;               // local column of the shot (outside: another half)
+          if (n < 0 || nl < 0 || nl >= kCols || (nl & 15) != li || (nl >> 4) < sh || (nl >> 4) > sh + 1) continue;
+          const int64_t stp = prm.step + (prm.step_base ? *prm.step_base : 0);
+          const float wv = prm.wavelet[stp * prm.nshot + n];
+          const float* sv = prm.src_vec + ((size_t)src * k + j) * P + rb;
+          const int h = (nl >> 4) - sh;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T x = (T)sv[ShotMath<T>::out_row(g, v)];
+            if constexpr (std::is_same<T, float>::value) acc[h][v] = fmaf(wv, x, acc[h][v]);
+            else acc[h][v] = fma((double)wv, x, acc[h][v]);
+          }
+        }
+        __syncthreads();                                     // every wave done reading Xt
+#pragma unroll
+        for (int h = 0; h < 2; ++h) store_rows<T>(Xt + (16 * (sh + h) + li) * PP + rb, g, acc[h]);
+        __syncthreads();
+        // leapfrog in increment form: D_j += dt^2 a_j, U_j += D_j
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const float d = std::is_same<T, float>::value
+                              ? fmaf(prm.dt2, (float)Xt[xl * PP + trow(i)], Dr[i])
+                              : (float)fma((double)prm.dt2, (double)Xt[xl * PP + trow(i)], (double)Dr[i]);
+          Dw[xrow(j, i)] = d;
+          Uw[xrow(j, i)] = Ua[i] + d;
         }
       }
-      __syncthreads();                                     // every wave done reading Xt
-#pragma unroll
-      for (int h = 0; h < 2; ++h) store_rows<T>(Xt + (16 * (sh + h) + li) * PP + rb, g, acc[h]);
-      __syncthreads();
-      // leapfrog in increment form: D_j += dt^2 a_j, U_j += D_j
 #pragma unroll
       for (int i = 0; i < R; ++i) {
-        const float d = std::is_same<T, float>::value
-                            ? fmaf(prm.dt2, (float)Xt[xl * PP + trow(i)], Dr[i])
-                            : (float)fma((double)prm.dt2, (double)Xt[xl * PP + trow(i)], (double)Dr[i]);
-        Dw[xrow(j, i)] = d;
-        Uw[xrow(j, i)] = Ua[i] + d;
+        Ua[i] = Ub[i];
+        Ub[i] = Un[i];
       }
     }
+
+  } else {
+    // the blocks in order of use: t = 0 the Gamma block of level 0 (block 0); for a level j >= 1,
+    // t = 2j - 1 its Gamma block (block j) and t = 2j its Gamma-hat block (block k + j - 1)
+    const int nt_s = 2 * ks - 1;
+    auto block_of = [&](int t) { return t == 0 ? 0 : ((t & 1) ? (t + 1) / 2 : k + t / 2 - 1); };
+    expand_block<T, kPF>(G, PP, P, prm.wmap, nq, tid, nthr, buf);               // stream block 0
+    prefetch_block<T, kPF>(tiles + block_word(prm, s, block_of(1)), nq, tid, nthr, buf);
+    int t = 0;
+    for (int j = 0; j < ks; ++j) {
+      T* Gc = (t & 1) ? G2 : G;
+      T* Gn = (t & 1) ? G : G2;
+      __syncthreads();                                     // Xt and Gn free, Gc expanded
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      Ua[i] = Ub[i];
-      Ub[i] = Un[i];
+      for (int i = 0; i < R; ++i) Xt[xl * PP + trow(i)] = (T)Ub[i] - (T)Ua[i];   // U_{j+1} - U_j
+      __syncthreads();
+      if (j >= 1) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) Dr[i] = Dw[xrow(j, i)];
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) Un[i] = (j + 2 < ks) ? Uw[xrow(j + 2, i)] : 0.f;
+      if (t + 1 < nt_s) {
+        expand_block<T, kPF>(Gn, PP, P, prm.wmap, nq, tid, nthr, buf);          // next block, other buffer
+        if (t + 2 < nt_s) prefetch_block<T, kPF>(tiles + block_word(prm, s, block_of(t + 2)), nq, tid, nthr, buf);
+      }
+      block_product<T>(Gc, Xt, PP, P, I, sh, g, li, acc);  // phi_j
+      ++t;
+      __syncthreads();                                     // every wave done with Xt; Gn expanded
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int n = 16 * (sh + h) + li;   // local column
+        if (j == 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            prm.exch[((size_t)s * P + rb + ShotMath<T>::out_row(g, v)) * kShotCols + c0 + n] = (float)acc[h][v];  // 2.1
+        } else {
+          store_rows<T>(Xt + n * PP + rb, g, acc[h] - phip[h]);   // phi_j - phi_{j-1}
+        }
+        phip[h] = acc[h];
+      }
+      if (j >= 1) {
+        Gc = (t & 1) ? G2 : G;
+        Gn = (t & 1) ? G : G2;
+        __syncthreads();                                   // phi_j - phi_{j-1} in Xt
+        if (t + 1 < nt_s) {
+          expand_block<T, kPF>(Gn, PP, P, prm.wmap, nq, tid, nthr, buf);
+          if (t + 2 < nt_s) prefetch_block<T, kPF>(tiles + block_word(prm, s, block_of(t + 2)), nq, tid, nthr, buf);
+        }
+        block_product<T>(Gc, Xt, PP, P, I, sh, g, li, acc);   // a_j
+        ++t;
+        for (int q = ns0; q < ns1; ++q) {
+          const int src = prm.src_ids[q];
+          const int n = prm.src_shot[src];
+          const int nl = n - c0;
+          if (n < 0 || nl < 0 || nl >= kCols || (nl & 15) != li || (nl >> 4) < sh || (nl >> 4) > sh + 1) continue;
+          const int64_t stp = prm.step + (prm.step_base ? *prm.step_base : 0);
+          const float wv = prm.wavelet[stp * prm.nshot + n];
+          const float* sv = prm.src_vec + ((size_t)src * k + j) * P + rb;
+          const int h = (nl >> 4) - sh;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T x = (T)sv[ShotMath<T>::out_row(g, v)];
+            if constexpr (std::is_same<T, float>::value) acc[h][v] = fmaf(wv, x, acc[h][v]);
+            else acc[h][v] = fma((double)wv, x, acc[h][v]);
+          }
+        }
+        __syncthreads();                                   // every wave done reading Xt
+#pragma unroll
+        for (int h = 0; h < 2; ++h) store_rows<T>(Xt + (16 * (sh + h) + li) * PP + rb, g, acc[h]);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const float d = std::is_same<T, float>::value
+                              ? fmaf(prm.dt2, (float)Xt[xl * PP + trow(i)], Dr[i])
+                              : (float)fma((double)prm.dt2, (double)Xt[xl * PP + trow(i)], (double)Dr[i]);
+          Dw[xrow(j, i)] = d;
+          Uw[xrow(j, i)] = Ua[i] + d;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        Ua[i] = Ub[i];
+        Ub[i] = Un[i];
+      }
     }
   }
 }
@@ -483,18 +575,22 @@ typedef void (*ShotKernel)(ShotParams);
 // registers, no spills); the 4-wave variant serves every 6m <= 112.
 // Third variant of each: 32 shots per work-group (two per subdomain), with twice the prefetch
 // loads per thread since the work-group is half the size.
-constexpr int kNumShotVariants = 3;
+// Fourth variant of each: the first with two block buffers (kDB), where its LDS fits.
+constexpr int kNumShotVariants = 4;
 constexpr ShotKernel kShotVariants[2][kNumShotVariants] = {
-    {shots_main_kernel<float, 4>, shots_main_kernel<float, 6>, shots_main_kernel<float, 3, 7, 32, 4>},
-    {shots_main_kernel<double, 3, 5>, shots_main_kernel<double, 4>, shots_main_kernel<double, 3, 5, 32, 6>}};
-constexpr int kShotVariantWaves[2][kNumShotVariants] = {{4, 6, 3}, {3, 4, 3}};
-constexpr int kShotVariantMaxNt[2][kNumShotVariants] = {{7, 7, 7}, {5, 7, 5}};   // largest P16 / 16
-constexpr int kShotVariantCols[kNumShotVariants] = {64, 64, 32};
-constexpr int kShotVariantPrefetch[2][kNumShotVariants] = {{2, 2, 4}, {4, 4, 6}};
+    {shots_main_kernel<float, 4>, shots_main_kernel<float, 6>, shots_main_kernel<float, 3, 7, 32, 4>,
+     shots_main_kernel<float, 4, 7, 64, 2, true>},
+    {shots_main_kernel<double, 3, 5>, shots_main_kernel<double, 4>, shots_main_kernel<double, 3, 5, 32, 6>,
+     shots_main_kernel<double, 3, 5, 64, 4, true>}};
+constexpr int kShotVariantWaves[2][kNumShotVariants] = {{4, 6, 3, 4}, {3, 4, 3, 3}};
+constexpr int kShotVariantMaxNt[2][kNumShotVariants] = {{7, 7, 7, 7}, {5, 7, 5, 5}};   // largest P16 / 16
+constexpr int kShotVariantCols[kNumShotVariants] = {64, 64, 32, 64};
+constexpr int kShotVariantPrefetch[2][kNumShotVariants] = {{2, 2, 4, 2}, {4, 4, 6, 4}};
+constexpr bool kShotVariantDB[kNumShotVariants] = {false, false, false, true};
 
-size_t shots_lds_bytes(int P, size_t elem, int cols = kShotCols) {
+size_t shots_lds_bytes(int P, size_t elem, int cols = kShotCols, bool db = false) {
   const int PP = P + 4;
-  return elem * ((size_t)P * PP + (size_t)cols * PP);
+  return elem * ((size_t)(db ? 2 : 1) * P * PP + (size_t)cols * PP);
 }
 
 int shot_kind(sfm_ctx c) { return c->cfg.precision == SFM_PREC_FP64 ? 1 : 0; }
@@ -626,7 +722,7 @@ ShotParams main_params(sfm_ctx c, const float* wavelet_dev, double dt) {
 hipError_t launch_shots_main(int kind, int variant, const ShotParams& prm, int nt, hipStream_t st,
                              bool set_attr = true) {
   const int cols = kShotVariantCols[variant];
-  const size_t lds = shots_lds_bytes(prm.P, kind ? sizeof(double) : sizeof(float), cols);
+  const size_t lds = shots_lds_bytes(prm.P, kind ? sizeof(double) : sizeof(float), cols, kShotVariantDB[variant]);
   const ShotKernel kern = kShotVariants[kind][variant];
   if (lds > kDefaultLdsBytes && set_attr) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -644,7 +740,9 @@ bool shot_variant_fits(sfm_ctx c, int v) {
   const int64_t words = kind ? ShotMath<double>::kWords : ShotMath<float>::kWords;
   const int64_t threads = (kShotVariantCols[v] == 64 ? 128 : 64) * (int64_t)c->geo.nt;
   return c->geo.nt <= kShotVariantMaxNt[kind][v] &&
-         c->geo.words_per_block <= (int64_t)kShotVariantPrefetch[kind][v] * words * threads;
+         c->geo.words_per_block <= (int64_t)kShotVariantPrefetch[kind][v] * words * threads &&
+         shots_lds_bytes(c->geo.P16, kind ? sizeof(double) : sizeof(float), kShotVariantCols[v],
+                         kShotVariantDB[v]) <= (size_t)kMaxLdsBytes;
 }
 
 // Times every kernel variant on the (zero) shot state with no sources and dt = 0, which leaves
