@@ -175,30 +175,57 @@ __device__ __forceinline__ void acc2(double& s, double& e, double a, double b) {
   s = t;
 }
 
-// X_b = L_b^{-1} (lower triangular, non-unit), p x p column-major (lda p), in place over X;
-// one thread per column of X (X has the identity's column), forward substitution.
+// X_b = L_b^{-1} (lower triangular, non-unit), p x p column-major (lda p), written to X; one thread
+// per column of X (X has the identity's column), forward substitution.  With kLds, L and X are
+// staged in LDS (X's columns padded to p + 1); the arithmetic and its order are the same.
+template <bool kLds>
 __global__ void trtri_lower_kernel(const double* __restrict__ L, int64_t sL, double* __restrict__ X, int64_t sX,
                                    int p) {
-  const double* Lb = L + (int64_t)blockIdx.x * sL;
-  double* Xb = X + (int64_t)blockIdx.x * sX;
+  extern __shared__ __align__(16) double tri_lds[];
+  const double* Lg = L + (int64_t)blockIdx.x * sL;
+  double* Xg = X + (int64_t)blockIdx.x * sX;
+  const int ldx = kLds ? p + 1 : p;
+  if (kLds) {
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) tri_lds[e] = Lg[e];
+    __syncthreads();
+  }
+  const double* Lb = kLds ? tri_lds : Lg;
+  double* Xb = kLds ? tri_lds + p * p : Xg;
   for (int c = threadIdx.x; c < p; c += blockDim.x) {
-    for (int r = 0; r < c; ++r) Xb[r + (int64_t)c * p] = 0.0;
+    for (int r = 0; r < c; ++r) Xb[r + (int64_t)c * ldx] = 0.0;
     for (int r = c; r < p; ++r) {
       double s = r == c ? 1.0 : 0.0, e = 0.0;
-      for (int i = c; i < r; ++i) acc2(s, e, -Lb[r + (int64_t)i * p], Xb[i + (int64_t)c * p]);
-      Xb[r + (int64_t)c * p] = (s + e) / Lb[r + (int64_t)r * p];
+      for (int i = c; i < r; ++i) acc2(s, e, -Lb[r + (int64_t)i * p], Xb[i + (int64_t)c * ldx]);
+      Xb[r + (int64_t)c * ldx] = (s + e) / Lb[r + (int64_t)r * p];
     }
+  }
+  if (kLds) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) Xg[e] = Xb[e % p + (int64_t)(e / p) * ldx];
   }
 }
 
 // B_b <- alpha op(L_b)^{-1} B_b, L lower triangular non-unit (p x p, ld p), B p x p (ld p); one
-// thread per column of B: forward substitution for op = N, backward for op = T.
+// thread per column of B: forward substitution for op = N, backward for op = T.  With kLds, L and B
+// are staged in LDS (B's columns padded to p + 1); the arithmetic and its order are the same.
+template <bool kLds>
 __global__ void trsm_lower_kernel(const double* __restrict__ L, int64_t sL, double* __restrict__ Bm, int64_t sB,
                                   int p, int trans, double alpha) {
-  const double* Lb = L + (int64_t)blockIdx.x * sL;
-  double* Bb = Bm + (int64_t)blockIdx.x * sB;
+  extern __shared__ __align__(16) double tri_lds[];
+  const double* Lg = L + (int64_t)blockIdx.x * sL;
+  double* Bg = Bm + (int64_t)blockIdx.x * sB;
+  const int ldb = kLds ? p + 1 : p;
+  if (kLds) {
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+      tri_lds[e] = Lg[e];
+      tri_lds[p * p + e % p + (e / p) * ldb] = Bg[e];
+    }
+    __syncthreads();
+  }
+  const double* Lb = kLds ? tri_lds : Lg;
+  double* Bb = kLds ? tri_lds + p * p : Bg;
   for (int c = threadIdx.x; c < p; c += blockDim.x) {
-    double* x = Bb + (int64_t)c * p;
+    double* x = Bb + (int64_t)c * ldb;
     if (!trans) {
       for (int r = 0; r < p; ++r) {
         double s = alpha * x[r], e = fma(alpha, x[r], -s);
@@ -213,7 +240,18 @@ __global__ void trsm_lower_kernel(const double* __restrict__ L, int64_t sL, doub
       }
     }
   }
+  if (kLds) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) Bg[e] = Bb[e % p + (int64_t)(e / p) * ldb];
+  }
 }
+
+// LDS of the staged triangular kernels: L and a padded p x p right-hand side.  Staging pays while
+// several matrices still share a CU's LDS in flight with the global version's occupancy: measured
+// faster at 6m = 72 (the many-shot build: 14.6 -> 13.7 s), slower at 6m = 96 (one work-group of
+// 96 busy threads per CU; the 512^3 build 23.0 -> 24.6 s), so it is used up to 6m = 80.
+size_t tri_lds_bytes(int p) { return ((size_t)p * p + (size_t)p * (p + 1)) * sizeof(double); }
+constexpr int kTriLdsMaxP = 80;
 
 template <bool TA, bool TB, int TM, int TN>
 hipError_t launch_tile(GemmArgs& g, hipStream_t st) {
@@ -293,15 +331,36 @@ hipError_t dgemm_batched(bool tA, bool tB, int M, int N, int K, double alpha, co
 
 hipError_t trtri_lower_batched(const double* L, int64_t sL, double* X, int64_t sX, int p, int batch, hipStream_t st) {
   if (batch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(trtri_lower_kernel, dim3(batch), dim3(std::min(256, (p + 63) / 64 * 64)), 0, st, L, sL, X, sX, p);
+  const dim3 threads(std::min(256, (p + 63) / 64 * 64));
+  const size_t lds = tri_lds_bytes(p);
+  if (p <= kTriLdsMaxP && lds <= kMaxLdsBytes) {
+    if (lds > kDefaultLdsBytes) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&trtri_lower_kernel<true>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(trtri_lower_kernel<true>, dim3(batch), threads, lds, st, L, sL, X, sX, p);
+  } else {
+    hipLaunchKernelGGL(trtri_lower_kernel<false>, dim3(batch), threads, 0, st, L, sL, X, sX, p);
+  }
   return hipGetLastError();
 }
 
 hipError_t trsm_lower_batched(bool trans, double alpha, const double* L, int64_t sL, double* B, int64_t sB, int p,
                               int batch, hipStream_t st) {
   if (batch <= 0) return hipSuccess;
-  hipLaunchKernelGGL(trsm_lower_kernel, dim3(batch), dim3(std::min(256, (p + 63) / 64 * 64)), 0, st, L, sL, B, sB, p,
-                     trans ? 1 : 0, alpha);
+  const dim3 threads(std::min(256, (p + 63) / 64 * 64));
+  const size_t lds = tri_lds_bytes(p);
+  if (p <= kTriLdsMaxP && lds <= kMaxLdsBytes) {
+    if (lds > kDefaultLdsBytes) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&trsm_lower_kernel<true>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(trsm_lower_kernel<true>, dim3(batch), threads, lds, st, L, sL, B, sB, p, trans ? 1 : 0, alpha);
+  } else {
+    hipLaunchKernelGGL(trsm_lower_kernel<false>, dim3(batch), threads, 0, st, L, sL, B, sB, p, trans ? 1 : 0, alpha);
+  }
   return hipGetLastError();
 }
 
