@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "sfm_internal.h"
+#include "xcd.h"
 
 namespace sfm {
 namespace {
@@ -158,30 +159,19 @@ __global__ void init_q1_kernel(BoxGeo g, const double* __restrict__ S, const int
   }
 }
 
-// Work-groups are dispatched to the 8 XCDs in turn (work-group b to XCD b mod 8), and each XCD has
-// its own L2.  This renumbers them so that every XCD takes one contiguous range of the grid
-// (a bijection of [0, gridDim.x)): neighbouring work-groups, which read each other's rows, then
-// share an L2.
-__device__ __forceinline__ int64_t xcd_local_block() {
-  constexpr int kXcds = 8;
-  const int64_t G = gridDim.x, b = blockIdx.x;
-  const int64_t q = G / kXcds, r = G % kXcds, x = b % kXcds;
-  return x * q + (x < r ? x : r) + b / kXcds;
-}
-
 // W = (A_+ + shift I) X = S K S X + shift X for the p columns of X (ld ldx) into W (ld ldw).
 // K is the geometric stiffness: coefficient h per edge, halved for every box plane holding the edge.
 // One thread per (subdomain, node column (i, j), column of X) marches along z with the scale and
 // value of the planes l - 1, l, l + 1 in registers, so a z-neighbour (a whole plane of rows away)
 // is loaded once; the x- and y-neighbours lie in the plane the neighbouring threads load (on the
-// same XCD, through xcd_local_block).  Every term is formed as y_n - S_nb X_nb with
+// same XCD, through xcd_contiguous_id).  Every term is formed as y_n - S_nb X_nb with
 // y_n = S_n X_n, in the order x-, x+, y-, y+, z-, z+.
 __global__ void stencil_kernel(BoxGeo g, const double* __restrict__ S, int64_t N, int nb, const double* __restrict__ X,
                                int ldx, int64_t sx, double* __restrict__ W, int ldw, int64_t sw, double shift) {
   const int nx = g.n[0], nz = g.n[2];
   const int64_t plane = (int64_t)nx * g.n[1];
   const int64_t total = (int64_t)nb * plane * g.p;
-  const int64_t lb = xcd_local_block();
+  const int64_t lb = xcd_contiguous_id(blockIdx.x, gridDim.x);
   for (int64_t idx = lb * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
     const int col = (int)(idx % g.p);
     const int64_t bq = idx / g.p;

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "sfm_internal.h"
+#include "xcd.h"
 
 namespace sfm {
 namespace {
@@ -61,15 +62,12 @@ __global__ __launch_bounds__(kFdtdTx * kFdtdTy) void fdtd_march_kernel(const flo
                                                                     int nz) {
   __shared__ float pl[2][kFdtdTy + 2][kFdtdTx + 2];
   const int tx = threadIdx.x % kFdtdTx, ty = threadIdx.x / kFdtdTx;
-  // XCD-aware numbering: work-group b (linear, x fastest) runs on XCD b mod 8, each XCD with its own
-  // L2; renumber so that each XCD takes one contiguous range of tiles and the ring nodes a tile
-  // reads from its neighbours come through the same L2
+  // tiles in XCD-contiguous order, so the ring nodes a tile reads from its neighbours come
+  // through the same L2
   int bx, by, bz;
   {
-    const int64_t X = gridDim.x, Y = gridDim.y, G = X * Y * gridDim.z;
-    const int64_t L = blockIdx.x + X * (blockIdx.y + Y * (int64_t)blockIdx.z);
-    const int64_t q = G / 8, r = G % 8, xcd = L % 8;
-    const int64_t lb = xcd * q + (xcd < r ? xcd : r) + L / 8;
+    const int64_t X = gridDim.x, Y = gridDim.y;
+    const int64_t lb = xcd_contiguous_id(blockIdx.x + X * (blockIdx.y + Y * (int64_t)blockIdx.z), X * Y * gridDim.z);
     bx = (int)(lb % X);
     by = (int)((lb / X) % Y);
     bz = (int)(lb / (X * Y));
