@@ -271,10 +271,14 @@ sfm_status sfm_record_receivers(sfm_ctx ctx, float* out_dev, void* stream);
  * Errors: SFM_ESTATE. */
 sfm_status sfm_apply_operator(sfm_ctx ctx, const float* u_dev, float* a_dev, void* stream);
 
-/* Enable (1) or disable (0) per-kernel device timing inside sfm_step: hipEvents are recorded
- * around every kernel of every step on the caller's stream and summed into the timed_* fields
- * of sfm_info (sfm_query synchronizes the stream work and reads them).  Enabling resets the
- * sums.  Adds two event records per kernel launch. */
+/* Per-kernel device timing inside sfm_step and sfm_shots_step.  enable = 0 turns it off;
+ * enable = n >= 1 times one step in n (the 1st, (n+1)th, ... step run after this call, counted
+ * over both calls): four hipEvents are recorded on the caller's stream around that step's main,
+ * face and receiver kernels, and the elapsed times are summed into the timed_* fields of
+ * sfm_info (sfm_query synchronizes on the events and reads them; sfm_shots_timing does so for
+ * the shot steps).  Every event record between two kernels costs device time of its own, so
+ * n > 1 keeps the step rate of the untimed steps.  Enabling resets the sums; the events come
+ * from a pool the context keeps until sfm_destroy.  Errors: SFM_EINVAL (enable < 0). */
 sfm_status sfm_set_timing(sfm_ctx ctx, int32_t enable);
 
 /* Checkpoint: copy U^n and the increment U^n - U^{n-1} (host, float [S][k][p] each; either
@@ -417,8 +421,9 @@ sfm_status sfm_shots_tuning(sfm_ctx ctx, int32_t* chosen_waves, double* ms, int3
  * limit or prefetch capacity is below this 6m). */
 sfm_status sfm_shots_select(sfm_ctx ctx, int32_t variant);
 
-/* Device times of the shot kernels summed over the steps run while sfm_set_timing was on:
- * *timed_steps, ms3 = {main, face, record}; then resets the counters.  Never fails for a valid ctx. */
+/* Device times of the shot kernels summed over the shot steps timed while sfm_set_timing was
+ * on (one in n, as set there): *timed_steps, ms3 = {main, face, record}; then resets the
+ * counters.  Synchronizes on the last recorded event.  Errors: SFM_EHIP. */
 sfm_status sfm_shots_timing(sfm_ctx ctx, int64_t* timed_steps, double* ms3);
 
 /* ------------------------------------------------------------------------------------------

@@ -296,6 +296,26 @@ sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vec
 
 using namespace sfm;
 
+namespace sfm {
+sfm_status drain_events(sfm_ctx c, std::vector<hipEvent_t>& ev, double* ms3, int64_t* steps) {
+  if (ev.empty()) return SFM_OK;
+  SFM_TRY_HIP(c, hipEventSynchronize(ev.back()));
+  for (size_t s = 0; s + 4 <= ev.size(); s += 4) {
+    float ms = 0.f;
+    for (int q = 0; q < 3; ++q) {
+      SFM_TRY_HIP(c, hipEventElapsedTime(&ms, ev[s + q], ev[s + q + 1]));
+      ms3[q] += ms;
+    }
+    ++*steps;
+  }
+  c->ev_pool.insert(c->ev_pool.end(), ev.begin(), ev.end());
+  ev.clear();
+  return SFM_OK;
+}
+
+static sfm_status drain_timing(sfm_ctx c) { return drain_events(c, c->ev, c->timed_ms, &c->timed_steps); }
+}  // namespace sfm
+
 // ----------------------------------------------------------------------------- ABI
 extern "C" {
 
@@ -377,6 +397,8 @@ void sfm_destroy(sfm_ctx c) {
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->shot_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   sfm::drop_shot_graph(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   c->dfree_all();
@@ -386,35 +408,17 @@ void sfm_destroy(sfm_ctx c) {
 
 const char* sfm_last_error(sfm_ctx c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
-namespace sfm {
-// Fold recorded step events into the timing sums (synchronizes on the last event).
-static sfm_status drain_timing(sfm_ctx c) {
-  if (c->ev.empty()) return SFM_OK;
-  SFM_TRY_HIP(c, hipEventSynchronize(c->ev.back()));
-  for (size_t s = 0; s < c->ev_rec.size(); ++s) {
-    hipEvent_t* e = &c->ev[4 * s];
-    float ms = 0.f;
-    for (int q = 0; q < 3; ++q) {
-      SFM_TRY_HIP(c, hipEventElapsedTime(&ms, e[q], e[q + 1]));
-      c->timed_ms[q] += ms;
-    }
-    c->timed_steps++;
-  }
-  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-  c->ev.clear();
-  c->ev_rec.clear();
-  return SFM_OK;
-}
-}  // namespace sfm
-
 extern "C" sfm_status sfm_set_timing(sfm_ctx c, int32_t enable) {
   if (!c) return SFM_EINVAL;
   c->err.clear();
   SFM_TRY_HIP(c, hipSetDevice(c->device));
   sfm_status rc = drain_timing(c);
   if (rc != SFM_OK) return rc;
+  if (enable < 0) return c->fail(SFM_EINVAL, "sfm_set_timing: enable must be >= 0");
   c->timing = enable != 0;
   if (c->timing) {
+    c->timing_every = enable;
+    c->timing_seen = 0;
     c->timed_steps = 0;
     c->timed_ms[0] = c->timed_ms[1] = c->timed_ms[2] = 0.0;
   }
@@ -678,12 +682,9 @@ sfm_status sfm_step(sfm_ctx c, int32_t nsteps, double dt, const float* wavelet_d
     prm.hist_off = f.hist_off = t * slot_stride;
     const bool rec = recording && (t == kHistWindow - 1 || i + 1 == nsteps);
     hipEvent_t* e = nullptr;
-    if (c->timing) {
-      const size_t base = c->ev.size();
-      c->ev.resize(base + 4);
-      for (int q = 0; q < 4; ++q) SFM_TRY_HIP(c, hipEventCreate(&c->ev[base + q]));
-      c->ev_rec.push_back(rec ? 1 : 0);
-      e = &c->ev[base];
+    if (c->time_this_step()) {
+      SFM_TRY_HIP(c, c->take_events(c->ev));
+      e = &c->ev[c->ev.size() - 4];
       SFM_TRY_HIP(c, hipEventRecord(e[0], st));
     }
     SFM_TRY_HIP(c, launch_step_main(prm, c->cfg.precision, st));

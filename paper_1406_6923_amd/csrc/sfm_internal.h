@@ -202,6 +202,9 @@ sfm_status finalize_roms(sfm_ctx c, const std::vector<double>& H, const std::vec
 void release_roms(sfm_ctx c);
 void release_shots(sfm_ctx c);
 void drop_shot_graph(sfm_ctx c);   // destroys the cached shot-window graph (synchronizes)
+// Fold the recorded step events `ev` (4 per timed step) into ms3 = {main, face, record} and
+// *steps, then return the events to the context's pool.  Synchronizes on the last event.
+sfm_status drain_events(sfm_ctx c, std::vector<hipEvent_t>& ev, double* ms3, int64_t* steps);
 // Zero the levels j >= k_of[s] of a [S][k][P16][cols] state (no-op without a level table).
 hipError_t clear_extra_levels(sfm_ctx c, float* X, int cols, hipStream_t st);
 sfm_status forward_step(sfm_ctx c, double dt, const float* wavelet_row, float* kx_out, float* u_out,
@@ -309,12 +312,36 @@ struct sfm_ctx_s {
   double wd_max_norm = 0.0;
   int64_t wd_checks = 0;
   double build_seconds = 0.0;
-  // per-kernel timing of sfm_step (events recorded on the caller's stream)
+  // per-kernel timing of sfm_step and sfm_shots_step (events recorded on the caller's stream)
   bool timing = false;
+  int32_t timing_every = 1;         // time one step in timing_every (counted from the enable call)
+  int64_t timing_seen = 0;          // steps run since timing was enabled
   std::vector<hipEvent_t> ev;       // 4 events per timed step: main start, face start, record start, end
-  std::vector<uint8_t> ev_rec;      // whether the record kernel ran in that step
+  std::vector<hipEvent_t> shot_ev;  // the same for the shot steps
+  std::vector<hipEvent_t> ev_pool;  // created once, reused after every drain
   int64_t timed_steps = 0;
   double timed_ms[3] = {0, 0, 0};
+
+  // Should the step about to run be timed?  Advances the step count.
+  bool time_this_step() {
+    if (!timing) return false;
+    return timing_seen++ % timing_every == 0;
+  }
+  // Four events for one timed step, appended to `to` (from the pool when it has them).
+  hipError_t take_events(std::vector<hipEvent_t>& to) {
+    for (int q = 0; q < 4; ++q) {
+      hipEvent_t e = nullptr;
+      if (!ev_pool.empty()) {
+        e = ev_pool.back();
+        ev_pool.pop_back();
+      } else {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+      }
+      to.push_back(e);
+    }
+    return hipSuccess;
+  }
 
   sfm_status fail(sfm_status code, const std::string& msg) {
     err = msg;

@@ -902,21 +902,22 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
       SH_TRY_HIP(launch_step(n, 0, n + 1 == nsteps - nwin * kShotWindow, c->shot_base_d, st, true));
     n_done = nsteps;
   }
-  hipEvent_t ev[4] = {};
   for (int n = n_done; n < nsteps; ++n) {
-    if (timing) {
-      for (auto& x : ev) SH_TRY_HIP(hipEventCreate(&x));
+    hipEvent_t* ev = nullptr;
+    if (c->time_this_step()) {
+      SH_TRY_HIP(c->take_events(c->shot_ev));
+      ev = &c->shot_ev[c->shot_ev.size() - 4];
       SH_TRY_HIP(hipEventRecord(ev[0], st));
     }
     prm.step = n;
     prm.step_base = nullptr;
     SH_TRY_HIP(launch_shots_main(shot_kind(c), c->shots_variant, prm, g.nt, st));
-    if (timing) SH_TRY_HIP(hipEventRecord(ev[1], st));
+    if (ev) SH_TRY_HIP(hipEventRecord(ev[1], st));
     fp.step = n;
     fp.step_base = nullptr;
     hipLaunchKernelGGL(shots_face_kernel, dim3((unsigned)((nface + 255) / 256)), dim3(256), 0, st, fp);
     SH_TRY_HIP(hipGetLastError());
-    if (timing) SH_TRY_HIP(hipEventRecord(ev[2], st));
+    if (ev) SH_TRY_HIP(hipEventRecord(ev[2], st));
     if (record) {
       rp.slot = n % kShotWindow;
       hipLaunchKernelGGL(shots_record_kernel, rgrid, dim3(256), 0, st, rp);
@@ -929,15 +930,7 @@ sfm_status sfm_shots_step(sfm_ctx c, int32_t nsteps, double dt, const float* wav
         SH_TRY_HIP(hipGetLastError());
       }
     }
-    if (timing) {
-      SH_TRY_HIP(hipEventRecord(ev[3], st));
-      SH_TRY_HIP(hipEventSynchronize(ev[3]));
-      float ms[3];
-      for (int q = 0; q < 3; ++q) SH_TRY_HIP(hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]));
-      for (int q = 0; q < 3; ++q) c->shots_ms[q] += ms[q];
-      c->shots_timed++;
-      for (auto& x : ev) SH_TRY_HIP(hipEventDestroy(x));
-    }
+    if (ev) SH_TRY_HIP(hipEventRecord(ev[3], st));
   }
   c->shots_n += nsteps;
   return SFM_OK;
@@ -1034,6 +1027,9 @@ sfm_status sfm_shots_select(sfm_ctx c, int32_t variant) {
 sfm_status sfm_shots_timing(sfm_ctx c, int64_t* timed_steps, double* ms3) {
   if (!c) return SFM_EINVAL;
   c->err.clear();
+  SH_TRY_HIP(hipSetDevice(c->device));
+  const sfm_status rc = drain_events(c, c->shot_ev, c->shots_ms, &c->shots_timed);
+  if (rc != SFM_OK) return rc;
   if (timed_steps) *timed_steps = c->shots_timed;
   if (ms3)
     for (int q = 0; q < 3; ++q) ms3[q] = c->shots_ms[q];

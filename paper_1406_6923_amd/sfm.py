@@ -387,8 +387,9 @@ def sfm_apply_operator(ctx: int, u, a, stream=None) -> None:
     _check(ctx, load_library().sfm_apply_operator(ctx, _dev(u), _dev(a), _stream(stream)))
 
 
-def sfm_set_timing(ctx: int, enable: bool) -> None:
-    _check(ctx, load_library().sfm_set_timing(ctx, 1 if enable else 0))
+def sfm_set_timing(ctx: int, enable, every: int = 1) -> None:
+    """Time one step in `every` while enabled (False / 0 turns the timing off)."""
+    _check(ctx, load_library().sfm_set_timing(ctx, int(every) if enable else 0))
 
 
 def sfm_get_state(ctx: int):

@@ -152,6 +152,40 @@ def test_shots_traces_match_oracle(name, nsteps, precision):
     h.close()
 
 
+def test_sampled_shot_timing_leaves_traces_alone():
+    """Shot steps timed one in three (events pooled, read back once by sfm_shots_timing): the
+    count matches and the traces equal those of an untimed run bit for bit."""
+    from paper_1406_6923_amd import sfm
+    cfg, c, subs, roms, cs = oracle_case("small")
+    h = _load(cfg, cs)
+    shot_src = np.full(NSHOT, -1)
+    shot_src[0] = 0
+    sfm.sfm_shots_init(h.ctx, NSHOT, shot_src)
+    u0, d0 = sfm.sfm_shots_get_state(h.ctx, NSHOT)
+    dt = 0.9 * cs.cfl_dt()
+    nsteps = 40
+    wav = torch.tensor(np.repeat(W.ricker(cfg.f_peak, dt, nsteps)[:, None], NSHOT, axis=1),
+                       dtype=torch.float32, device="cuda")
+    nrec = len(cfg.receivers())
+    out = []
+    for every in (0, 3):
+        sfm.sfm_shots_set_state(h.ctx, u0, d0)
+        sfm.sfm_shots_timing(h.ctx)
+        sfm.sfm_set_timing(h.ctx, every > 0, every=max(every, 1))
+        tr = torch.zeros((NSHOT, nrec, nsteps), dtype=torch.float32, device="cuda")
+        sfm.sfm_shots_step(h.ctx, nsteps, dt, wav, tr)
+        torch.cuda.synchronize()
+        sfm.sfm_set_timing(h.ctx, False)
+        nt, ms = sfm.sfm_shots_timing(h.ctx)
+        assert nt == (0 if every == 0 else (nsteps + every - 1) // every), (every, nt)
+        if every:
+            assert ms[0] > 0 and ms[1] > 0
+        out.append(tr.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+    assert np.abs(out[0]).max() > 0
+    h.close()
+
+
 def test_shots_errors():
     from paper_1406_6923_amd import sfm
     cfg, c, subs, roms, cs = oracle_case("small")

@@ -239,6 +239,41 @@ def test_checkpoint_resume_and_determinism():
     h.close()
 
 
+def test_sampled_timing_counts_and_leaves_results_alone():
+    """sfm_set_timing(n) times steps 1, n+1, 2n+1, ... counted across calls; the event records
+    change no result (traces and state bit-identical to an untimed run)."""
+    from paper_1406_6923_amd import sfm
+    h, cfg, cs = _loaded("small")
+    dt = 0.9 * cs.cfl_dt()
+    nsteps = 50
+    wav = torch.tensor(W.ricker(cfg.f_peak, dt, nsteps)[:, None], dtype=torch.float32, device="cuda")
+    nrec = len(cs.receivers)
+    runs = []
+    for every in (0, 4, 1):
+        sfm.sfm_set_state(h.ctx, None, None, 0)
+        sfm.sfm_set_timing(h.ctx, every > 0, every=max(every, 1))
+        tr = [torch.zeros((nrec, n), dtype=torch.float32, device="cuda") for n in (30, 20)]
+        sfm.sfm_step(h.ctx, 30, dt, wav[:30].contiguous(), tr[0])
+        sfm.sfm_step(h.ctx, 20, dt, wav[30:].contiguous(), tr[1])
+        torch.cuda.synchronize()
+        tr = torch.cat(tr, dim=1)
+        info = h.info()
+        expect = 0 if every == 0 else (nsteps + every - 1) // every
+        assert info["timed_steps"] == expect, (every, info["timed_steps"])
+        if every:
+            assert info["timed_main_ms"] > 0 and info["timed_face_ms"] > 0
+        sfm.sfm_set_timing(h.ctx, False)
+        runs.append((tr.cpu().numpy(), sfm.sfm_get_state(h.ctx)[:2]))
+    for tr, (u, d) in runs[1:]:
+        assert np.array_equal(tr, runs[0][0])
+        assert np.array_equal(u, runs[0][1][0]) and np.array_equal(d, runs[0][1][1])
+    assert np.abs(runs[0][0]).max() > 0
+    with pytest.raises(sfm.SfmError) as ei:
+        sfm.sfm_set_timing(h.ctx, True, every=-2)
+    assert ei.value.status == sfm.SFM_EINVAL
+    h.close()
+
+
 def test_bf16_traces_report():
     """BF16 coefficient storage (FP32 accumulation): measured trace error, held below 1e-1.
 
