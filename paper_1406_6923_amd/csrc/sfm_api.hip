@@ -299,17 +299,23 @@ using namespace sfm;
 namespace sfm {
 sfm_status drain_events(sfm_ctx c, std::vector<hipEvent_t>& ev, double* ms3, int64_t* steps) {
   if (ev.empty()) return SFM_OK;
-  SFM_TRY_HIP(c, hipEventSynchronize(ev.back()));
-  for (size_t s = 0; s + 4 <= ev.size(); s += 4) {
-    float ms = 0.f;
-    for (int q = 0; q < 3; ++q) {
-      SFM_TRY_HIP(c, hipEventElapsedTime(&ms, ev[s + q], ev[s + q + 1]));
-      ms3[q] += ms;
+  const hipError_t sync = hipEventSynchronize(ev.back());
+  for (size_t s = 0; sync == hipSuccess && s + 4 <= ev.size(); s += 4) {
+    // A step that failed part-way left some of its events unrecorded: it is not counted, and
+    // the error the query leaves behind is cleared so that no later launch check reports it.
+    float ms[3];
+    bool ok = true;
+    for (int q = 0; q < 3 && ok; ++q) ok = hipEventElapsedTime(&ms[q], ev[s + q], ev[s + q + 1]) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      continue;
     }
+    for (int q = 0; q < 3; ++q) ms3[q] += ms[q];
     ++*steps;
   }
   c->ev_pool.insert(c->ev_pool.end(), ev.begin(), ev.end());
   ev.clear();
+  if (sync != hipSuccess) return c->fail(SFM_EHIP, std::string("hipEventSynchronize failed: ") + hipGetErrorString(sync));
   return SFM_OK;
 }
 
