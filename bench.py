@@ -30,7 +30,9 @@ import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 # The library records hipEvents around the kernels of one step in TIMING_EVERY; an event record
 # between two kernels costs device time of its own, so the other steps run as they would untimed.
-TIMING_EVERY = 16
+# Odd, so that the timed steps fall on every position of the 64-step (32 for shots) receiver
+# windows and the window flushes are sampled in proportion.
+TIMING_EVERY = 17
 COUNTERS = os.path.join(ROOT, "profiles", "step_main_counters.json")
 STEP_SRC = os.path.join(ROOT, "paper_1406_6923_amd", "csrc", "step_kernels.hip")
 
