@@ -32,7 +32,8 @@ constexpr int kTT = 64;   // time samples per tile (= kHistWindow)
 constexpr int kTK = 32;   // reduction chunk
 
 // C[r][t] = sum_e R[r][e] H[t][e] for one receiver subdomain: blockIdx.y = subdomain slot,
-// blockIdx.x = tile of 64 receivers; 256 threads, 4 x 4 outputs each.
+// blockIdx.x = tile of 64 receivers; 256 threads, 4 x 4 outputs each.  The next 64 x 32 chunks of
+// R and H are loaded into registers while the products of the current ones run from LDS.
 __global__ __launch_bounds__(256) void record_window_kernel(RecWindowParams prm) {
   __shared__ float Rs[kTK][kTR + 4];
   __shared__ float Hs[kTK][kTT + 4];
@@ -45,17 +46,32 @@ __global__ __launch_bounds__(256) void record_window_kernel(RecWindowParams prm)
   const int tx = tid & 15, ty = tid >> 4;
   const float* H = prm.hist + (size_t)slot * K;
   const size_t hstride = (size_t)prm.n_rs * K;
-  float acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += kTK) {
-    // 64 x 32 tiles of R and H, 8 words per thread, coalesced along e
-    for (int q = tid; q < kTR * kTK; q += 256) {
+  constexpr int kPer = kTR * kTK / 256;   // words of each tile per thread
+  static_assert(kTR == kTT && kTR * kTK % 256 == 0, "tile shape");
+  float rv[kPer], hv[kPer];
+  // 64 x 32 tiles of R and H, coalesced along e
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int v = 0; v < kPer; ++v) {
+      const int q = tid + 256 * v;
       const int rr = q / kTK, kk = q % kTK;
       const int r = r0 + rr, e = k0 + kk;
-      Rs[kk][rr] = (r < r1 && e < K) ? prm.rows[(size_t)r * K + e] : 0.f;
-      const int t = rr;
-      Hs[kk][t] = (t < prm.w && e < K) ? H[(size_t)t * hstride + e] : 0.f;
+      rv[v] = (r < r1 && e < K) ? prm.rows[(size_t)r * K + e] : 0.f;
+      hv[v] = (rr < prm.w && e < K) ? H[(size_t)rr * hstride + e] : 0.f;
+    }
+  };
+  float acc[4][4] = {};
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += kTK) {
+#pragma unroll
+    for (int v = 0; v < kPer; ++v) {
+      const int q = tid + 256 * v;
+      const int rr = q / kTK, kk = q % kTK;
+      Rs[kk][rr] = rv[v];
+      Hs[kk][rr] = hv[v];
     }
     __syncthreads();
+    if (k0 + kTK < K) load(k0 + kTK);
 #pragma unroll 8
     for (int kk = 0; kk < kTK; ++kk) {
       float a[4], b[4];
