@@ -389,10 +389,14 @@ struct sfm_cnn_s {
     err = m;
     return s;
   }
+  // *e is written only on failure: the first failure of a run of allocations is kept
   void* alloc(size_t bytes, hipError_t* e) {
     void* p = nullptr;
-    *e = hipMalloc(&p, std::max<size_t>(bytes, 16));
-    if (*e != hipSuccess) return nullptr;
+    const hipError_t r = hipMalloc(&p, std::max<size_t>(bytes, 16));
+    if (r != hipSuccess) {
+      *e = r;
+      return nullptr;
+    }
     owned.push_back(p);
     return p;
   }

@@ -52,10 +52,15 @@ hipError_t sfm::clear_extra_levels(sfm_ctx c, float* X, int cols, hipStream_t st
 }
 
 // ----------------------------------------------------------------------------- context helpers
+// *e is written only on failure, so a run of allocations sharing one status reports the first
+// failure even when later ones succeed (callers initialise it to hipSuccess).
 void* sfm_ctx_s::dalloc(size_t bytes, hipError_t* e) {
   void* p = nullptr;
-  *e = hipMalloc(&p, std::max<size_t>(bytes, 16));
-  if (*e != hipSuccess) return nullptr;
+  const hipError_t r = hipMalloc(&p, std::max<size_t>(bytes, 16));
+  if (r != hipSuccess) {
+    *e = r;
+    return nullptr;
+  }
   owned.push_back(p);
   return p;
 }
@@ -108,7 +113,10 @@ template <typename T>
 static T* alloc_copy(sfm_ctx c, const std::vector<T>& v, hipError_t* e) {
   T* d = static_cast<T*>(c->dalloc(v.size() * sizeof(T), e));
   if (!d) return nullptr;
-  if (!v.empty()) *e = hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (!v.empty()) {
+    const hipError_t r = hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (r != hipSuccess) *e = r;
+  }
   return d;
 }
 

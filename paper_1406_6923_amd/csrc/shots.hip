@@ -672,7 +672,9 @@ sfm_status sfm_shots_init(sfm_ctx c, int32_t nshot, const int32_t* shot_src, voi
   if (c->nrec > 0)
     c->rec_stage_d =
         static_cast<float*>(c->dalloc((size_t)kShotWindow * kRecSplit * c->nrec * kShotCols * sizeof(float), &e));
-  if (e != hipSuccess) {
+  // every pointer is checked: a later allocation that succeeds overwrites the status of a failed one
+  if (!c->Us_d || !c->Ds_d || !c->exch_s_d || !c->src_shot_d || !c->shot_base_d ||
+      (c->nrec > 0 && !c->rec_stage_d)) {
     release_shots(c);
     return c->fail(SFM_ENOMEM, "shot state: out of device memory");
   }
