@@ -3,6 +3,8 @@
 * tests/host/geometry_check.cpp with topology.cpp: the decomposition and tile-layout invariants
   (every upper-triangle entry of a block stored once, lines aligned, symmetric neighbour tables,
   owners), built with -fsanitize=address,undefined and no recovery, so any report fails the run.
+* tests/host/xcd_check.cpp: the XCD-contiguous work-group numbering (xcd.h) is a bijection whose
+  per-XCD shares are contiguous ranges, for every grid size up to 20,000 work-groups.
 * the debug build of libsfm.so (SFM_DEBUG launch checks, host code sanitized, build_lib
   debug=True) loads and runs the configuration checks of sfm_create with the sanitizer runtime
   preloaded.
@@ -36,6 +38,19 @@ def test_geometry_under_sanitizers(tmp_path):
     res = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert res.returncode == 0, res.stderr[-4000:]
     assert "geometry checks passed" in res.stdout
+
+
+def test_xcd_numbering_under_sanitizers(tmp_path):
+    """The work-group renumbering of the build stencil and the FDTD comparator: a bijection for
+    every grid size, each XCD's round-robin share mapped to one contiguous range."""
+    exe = tmp_path / "xcd_check"
+    cmd = [_compiler(), "-std=c++17", "-O1", "-g", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", os.path.join(ROOT, "tests", "host", "xcd_check.cpp"), "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    res = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert res.returncode == 0, res.stdout[-2000:] + res.stderr[-2000:]
+    assert "xcd numbering checks passed" in res.stdout
 
 
 def _asan_runtime():
